@@ -1,0 +1,175 @@
+/*
+ * ndft.h -- C ABI of libndft.so: the multiplication-free nonlinear DFT (NDFT) and the
+ * NDFT cross-ambiguity surface on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bozkurt, Arslan, Sevimli, Akbas, Cetin, "Approximate Computation of DFT
+ * without Performing Any Multiplications: Applications to Radar Signal Processing"
+ * (arXiv 1402.0532).
+ *
+ *   a (x) b = sign(a*b)(|a| + |b|), 0 when either operand is 0        -- Eq. (1)-(2)
+ *   complex:  a (x) b = a_r(x)b_r - a_i(x)b_i + j(a_i(x)b_r + b_i(x)a_r) -- Eq. (6)
+ *   NDFT:     X[k] = sum_n W^{kn mod N} (x) x[n],  W = e^{-j 2 pi / N}  -- Eq. (7)
+ *   surface:  A[l][p] = sum_i (s[i] (x) conj(r[i-d])) (x) W^{ip}        -- Eq. (12a)
+ *
+ * Conventions shared by every entry point:
+ *   - Complex data is complex64: interleaved {re, im} float pairs (ndft_c64), the
+ *     layout of torch.complex64 and std::complex<float>.
+ *   - All data pointers are DEVICE pointers owned by the caller. The library allocates
+ *     no device memory: scratch space comes from the caller as `ws` (size from the
+ *     matching *_workspace query; a NULL ws is allowed when the query returns 0).
+ *     Pointers must be 8-byte aligned; `ws` must be 256-byte aligned.
+ *   - Outputs must not alias inputs or the workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls
+ *     only enqueue work on it and never synchronize; results are visible after the
+ *     stream is synchronized. All calls are asynchronous and thread-safe.
+ *   - Arguments are validated on the host before anything is enqueued; a rejected
+ *     call returns NDFT_E_INVAL (or NDFT_E_WORKSPACE) and touches no memory.
+ *   - Inputs must be finite, with magnitudes below 1e30.
+ *   - Doppler / frequency bins are taken mod N, so negative starts are allowed.
+ *   - Results are deterministic for a fixed plan: no floating-point atomics.
+ *   - No exception crosses this boundary.
+ */
+#ifndef NDFT_H
+#define NDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float re, im;
+} ndft_c64;
+
+typedef enum {
+    NDFT_OK = 0,
+    NDFT_E_INVAL = 1,       /* invalid argument (checked before any launch)        */
+    NDFT_E_UNSUPPORTED = 2, /* precision or shape not available                   */
+    NDFT_E_WORKSPACE = 3,   /* ws NULL, misaligned or smaller than the query      */
+    NDFT_E_HIP = 4          /* a HIP runtime call or kernel launch failed         */
+} ndft_status;
+
+/* Arithmetic of the dense contraction (sign operands are exact in every form):
+ *   NDFT_FP32   FP32 operands on FP32 matrix cores, FP32 accumulation.
+ *   NDFT_BF16X2 data split into BF16 hi + lo (|v - hi - lo| <= 2^-18 |v|), exact BF16
+ *               signs, FP32 accumulation.
+ *   NDFT_FP8    reserved (returns NDFT_E_UNSUPPORTED).                               */
+typedef enum { NDFT_FP32 = 0, NDFT_BF16X2 = 1, NDFT_FP8 = 2 } ndft_prec;
+
+/* Maximum transform length. */
+#define NDFT_MAX_N (1 << 24)
+
+/* ---------------------------------------------------------------------------------
+ * NDFT, Eq. (7) (no 1/N normalisation):
+ *   X[b][q] = sum_{n=0}^{N-1} W^{(k0+q) n mod N} (x) x[b][n],  q in [0, k_count).
+ * x: [batch][n] complex64 (row-major), X: [batch][k_count] complex64.
+ * Limits: 1 <= n <= NDFT_MAX_N, batch >= 0, 1 <= k_count <= n, k0 any integer.
+ * ------------------------------------------------------------------------------- */
+size_t ndft_forward_workspace(int64_t batch, int64_t n, int64_t k0, int64_t k_count,
+                              ndft_prec prec);
+ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int64_t k0,
+                         int64_t k_count, ndft_prec prec, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Cross-ambiguity surface, Eq. (12a) of Section 4, read as
+ *   A[l][q] = sum_{i=0}^{N-1} ( s[i] (x) conj(r[i - d]) ) (x) W^{i p mod N},
+ *   d = tau0 + l (l in [0, n_tau)),  p = p0 + q mod N (q in [0, n_dop)),
+ *   r[m] = 0 for m < 0 (the record is not circular).
+ * The conjugate on the reference is the one of Eq. (11); the two operators associate
+ * left to right, i.e. each range row is the NDFT of its lag-product sequence.
+ * surv, ref: [n] complex64. A: [n_tau][n_dop] complex64, row-major (delay-major).
+ * Limits: 1 <= n <= NDFT_MAX_N, 0 <= tau0, n_tau >= 1, tau0 + n_tau <= n,
+ *         1 <= n_dop <= n, p0 any integer.
+ * ------------------------------------------------------------------------------- */
+size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
+                          ndft_prec prec);
+ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                     int64_t n_tau, int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batched surfaces (many CPIs of uneven length) in one persistent launch.
+ * A CPI c computes the ndft_caf surface of
+ *   surv_pool[surv_off .. surv_off+n), ref_pool[ref_off .. ref_off+n)
+ * into out_pool[out_off .. out_off + n_tau*n_dop) with its own (n, tau0, n_tau, p0,
+ * n_dop); offsets are in complex elements. Each CPI obeys the ndft_caf limits.
+ *
+ * ndft_caf_batched_prepare() writes the CPI table and the tile schedule into `ws`
+ * (a blocking host-to-device copy; call it once per batch layout, outside stream
+ * capture). ndft_caf_batched() then only launches kernels on `stream` (no copies,
+ * allocations or memsets), so it may be captured into a hipGraph and replayed; each
+ * replay recomputes every surface from the current pool contents. The `cpis` array is
+ * HOST memory and may be freed after prepare returns.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n, surv_off, ref_off, out_off, tau0, n_tau, p0, n_dop;
+} ndft_cpi;
+
+size_t ndft_caf_batched_workspace(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec);
+ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec,
+                                     void *ws, size_t ws_bytes);
+ndft_status ndft_caf_batched(const ndft_c64 *surv_pool, const ndft_c64 *ref_pool,
+                             ndft_c64 *out_pool, ndft_prec prec, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Adjoint of the surface with respect to the reference (and optionally the
+ * surveillance) input, for a real loss L. grad_A[l][q] = dL/dRe A + j dL/dIm A; the
+ * outputs use the same convention (grad_ref[m] = dL/dRe r[m] + j dL/dIm r[m]).
+ * Derivative rule at every operator node: d(x (x) y)/dx = sign(y) (almost everywhere;
+ * the jump of the sign is ignored), so no lag-product value enters the adjoint:
+ *   gz[l][i]     = sum_q conj(grad_A[l][q]) csgn(W^{i p_q})
+ *   grad_ref[m]  = sum_l csgn(s[m + d_l]) gz[l][m + d_l]
+ *   grad_surv[i] = sum_l csgn(r[i - d_l]) conj(gz[l][i])
+ * grad_ref, grad_surv: [n] complex64, fully overwritten; grad_surv may be NULL.
+ * Same limits as ndft_caf. prec selects the contraction arithmetic of gz.
+ * ------------------------------------------------------------------------------- */
+size_t ndft_caf_backward_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0,
+                                   int64_t n_dop, ndft_prec prec);
+ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                              int64_t n_tau, int64_t p0, int64_t n_dop, const ndft_c64 *grad_A,
+                              ndft_c64 *grad_ref, ndft_c64 *grad_surv, ndft_prec prec, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Test hook: the exact ternary sign operands the kernels use, as int8 in {-1, 0, 1}.
+ *   tw_sign[q][i][2]  = (sign Re, sign Im) of W^{i (p0+q) mod N}   (Eq. (7) twiddles)
+ *   lag_sign[l][i][2] = (sign Re, sign Im) of s[i] (x) conj(r[i - tau0 - l])
+ * Either output may be NULL. Same limits as ndft_caf. Device pointers.
+ * ------------------------------------------------------------------------------- */
+ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                           int64_t n_tau, int64_t p0, int64_t n_dop, int8_t *tw_sign,
+                           int8_t *lag_sign, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Tile plans (used by the autotuner). A plan is a tile shape of the contraction
+ * kernel; ksplit is the number of sample chunks reduced in a fixed order (0 = pick
+ * from the shape). Setting plan -1 restores the built-in choice. The setting is
+ * process-wide per precision (mutex-guarded); calls already enqueued are unaffected.
+ * ------------------------------------------------------------------------------- */
+int32_t ndft_plan_count(ndft_prec prec);
+const char *ndft_plan_name(ndft_prec prec, int32_t plan);
+ndft_status ndft_set_plan(ndft_prec prec, int32_t plan, int32_t ksplit);
+ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t n_bins,
+                          int32_t *plan, int32_t *ksplit);
+
+/* ---------------------------------------------------------------------------------
+ * Timing of the contraction kernel: when enabled, every call records a pair of
+ * hipEvents around its contraction launch on the call's stream. ndft_prof_read()
+ * waits for the recorded events, returns the summed milliseconds and the number of
+ * launches since the last read, and resets both. Process-wide, mutex-guarded.
+ * ------------------------------------------------------------------------------- */
+ndft_status ndft_prof_enable(int32_t on);
+ndft_status ndft_prof_read(double *contract_ms, int64_t *launches);
+
+const char *ndft_status_string(ndft_status st);
+const char *ndft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDFT_H */

@@ -1,0 +1,223 @@
+"""Python binding of libndft.so: the multiplication-free NDFT (Eq. (7)) and the NDFT
+cross-ambiguity surface (Eq. (12a)) of Bozkurt et al. (arXiv 1402.0532) on MI355X.
+
+This module only marshals arguments: torch tensors provide device memory and the
+current stream; every step of the computation runs in the HIP kernels of libndft.so.
+There is no CPU or PyTorch fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+FP32 = 0
+BF16X2 = 1
+FP8 = 2
+PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
+
+__all__ = [
+    "FP32", "BF16X2", "FP8", "forward", "caf", "caf_backward", "caf_batched", "BatchPlan",
+    "NDFTCaf", "dbg_signs", "plan_count", "plan_name", "set_plan", "get_plan",
+    "prof_enable", "prof_read", "version",
+]
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p.lower()]
+    return int(p)
+
+
+def _stream_handle() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _check_c64(t: torch.Tensor, name: str, ndim: int) -> None:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex64:
+        raise TypeError("%s must be a complex64 tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on a GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.dim() != ndim:
+        raise ValueError("%s must have %d dimension(s)" % (name, ndim))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def version() -> str:
+    return _lib.load().ndft_version().decode()
+
+
+def forward(x: torch.Tensor, k0: int = 0, k_count: int | None = None, prec=FP32) -> torch.Tensor:
+    """NDFT (Eq. (7)) of each row of x [batch, n] at bins k0 .. k0+k_count-1 (mod n)."""
+    lib = _lib.load()
+    if x.dim() == 1:
+        return forward(x[None], k0, k_count, prec)[0]
+    _check_c64(x, "x", 2)
+    batch, n = x.shape
+    k_count = n if k_count is None else int(k_count)
+    p = _prec(prec)
+    out = torch.empty((batch, k_count), dtype=torch.complex64, device=x.device)
+    nbytes = lib.ndft_forward_workspace(batch, n, k0, k_count, p)
+    ws = _workspace(nbytes, x.device)
+    st = lib.ndft_forward(_ptr(x), _ptr(out), batch, n, int(k0), k_count, p, _ptr(ws),
+                          nbytes, _stream_handle())
+    _lib.check(st, "ndft_forward")
+    return out
+
+
+def caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
+        prec=FP32, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. (12a) surface A[n_tau, n_dop]: delays tau0 + l, Doppler bins p0 + q (mod n)."""
+    lib = _lib.load()
+    _check_c64(s, "surv", 1)
+    _check_c64(r, "ref", 1)
+    n = s.shape[0]
+    if r.shape[0] != n:
+        raise ValueError("surv and ref must have the same length")
+    p = _prec(prec)
+    if out is None:
+        out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device)
+    nbytes = lib.ndft_caf_workspace(n, tau0, n_tau, p0, n_dop, p)
+    if ws is None or ws.numel() < nbytes:
+        ws = _workspace(nbytes, s.device)
+    st = lib.ndft_caf(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
+                      p, _ptr(ws), nbytes, _stream_handle())
+    _lib.check(st, "ndft_caf")
+    return out
+
+
+def caf_workspace_bytes(n: int, tau0: int, n_tau: int, p0: int, n_dop: int, prec=FP32) -> int:
+    return int(_lib.load().ndft_caf_workspace(n, tau0, n_tau, p0, n_dop, _prec(prec)))
+
+
+def caf_backward(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
+                 grad_A: torch.Tensor, prec=FP32, need_grad_s: bool = True):
+    """Adjoint of caf: (grad_ref, grad_surv or None) for upstream grad_A [n_tau, n_dop]."""
+    lib = _lib.load()
+    _check_c64(s, "surv", 1)
+    _check_c64(r, "ref", 1)
+    _check_c64(grad_A, "grad_A", 2)
+    n = s.shape[0]
+    if tuple(grad_A.shape) != (n_tau, n_dop):
+        raise ValueError("grad_A must be [n_tau, n_dop]")
+    p = _prec(prec)
+    gr = torch.empty(n, dtype=torch.complex64, device=s.device)
+    gs = torch.empty(n, dtype=torch.complex64, device=s.device) if need_grad_s else None
+    nbytes = lib.ndft_caf_backward_workspace(n, tau0, n_tau, p0, n_dop, p)
+    ws = _workspace(nbytes, s.device)
+    st = lib.ndft_caf_backward(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop),
+                               _ptr(grad_A), _ptr(gr), _ptr(gs), p, _ptr(ws), nbytes,
+                               _stream_handle())
+    _lib.check(st, "ndft_caf_backward")
+    return gr, gs
+
+
+class NDFTCaf(torch.autograd.Function):
+    """Differentiable Eq. (12a) surface; gradients through libndft's hand adjoint."""
+
+    @staticmethod
+    def forward(ctx, s, r, tau0, n_tau, p0, n_dop, prec=FP32):
+        ctx.save_for_backward(s, r)
+        ctx.args = (int(tau0), int(n_tau), int(p0), int(n_dop), _prec(prec))
+        return caf(s.detach(), r.detach(), tau0, n_tau, p0, n_dop, prec)
+
+    @staticmethod
+    def backward(ctx, grad_A):
+        s, r = ctx.saved_tensors
+        tau0, n_tau, p0, n_dop, prec = ctx.args
+        gr, gs = caf_backward(s.detach(), r.detach(), tau0, n_tau, p0, n_dop,
+                              grad_A.contiguous(), prec, need_grad_s=ctx.needs_input_grad[0])
+        return (gs if ctx.needs_input_grad[0] else None,
+                gr if ctx.needs_input_grad[1] else None, None, None, None, None, None)
+
+
+class BatchPlan:
+    """Prepared batch of CPIs for caf_batched (tile schedule resident in the workspace)."""
+
+    def __init__(self, cpis, prec=FP32, device="cuda"):
+        lib = _lib.load()
+        self.prec = _prec(prec)
+        self.n_cpi = len(cpis)
+        arr = (_lib.NdftCpi * self.n_cpi)()
+        for k, c in enumerate(cpis):
+            for f in ("n", "surv_off", "ref_off", "out_off", "tau0", "n_tau", "p0", "n_dop"):
+                setattr(arr[k], f, int(c[f]))
+        self._arr = arr
+        self.ws_bytes = int(lib.ndft_caf_batched_workspace(arr, self.n_cpi, self.prec))
+        self.ws = _workspace(self.ws_bytes, device)
+        st = lib.ndft_caf_batched_prepare(arr, self.n_cpi, self.prec, _ptr(self.ws), self.ws_bytes)
+        _lib.check(st, "ndft_caf_batched_prepare")
+
+    def run(self, surv_pool, ref_pool, out_pool) -> torch.Tensor:
+        lib = _lib.load()
+        _check_c64(surv_pool, "surv_pool", 1)
+        _check_c64(ref_pool, "ref_pool", 1)
+        _check_c64(out_pool, "out_pool", 1)
+        st = lib.ndft_caf_batched(_ptr(surv_pool), _ptr(ref_pool), _ptr(out_pool), self.prec,
+                                  _ptr(self.ws), self.ws_bytes, _stream_handle())
+        _lib.check(st, "ndft_caf_batched")
+        return out_pool
+
+
+def caf_batched(plan: BatchPlan, surv_pool, ref_pool, out_pool):
+    return plan.run(surv_pool, ref_pool, out_pool)
+
+
+def dbg_signs(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, twiddle: bool = True,
+              lag: bool = True):
+    """Exact sign operands used by the kernels: (tw [n_dop, n, 2], lag [n_tau, n, 2]) int8."""
+    lib = _lib.load()
+    _check_c64(s, "surv", 1)
+    _check_c64(r, "ref", 1)
+    n = s.shape[0]
+    tw = torch.empty((n_dop, n, 2), dtype=torch.int8, device=s.device) if twiddle else None
+    lg = torch.empty((n_tau, n, 2), dtype=torch.int8, device=s.device) if lag else None
+    st = lib.ndft_dbg_signs(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop),
+                            _ptr(tw), _ptr(lg), _stream_handle())
+    _lib.check(st, "ndft_dbg_signs")
+    return tw, lg
+
+
+def plan_count(prec=FP32) -> int:
+    return int(_lib.load().ndft_plan_count(_prec(prec)))
+
+
+def plan_name(prec, plan: int) -> str:
+    v = _lib.load().ndft_plan_name(_prec(prec), int(plan))
+    return None if v is None else v.decode()
+
+
+def set_plan(prec, plan: int = -1, ksplit: int = 0) -> None:
+    _lib.check(_lib.load().ndft_set_plan(_prec(prec), int(plan), int(ksplit)), "ndft_set_plan")
+
+
+def get_plan(prec, n: int, n_cols: int, n_bins: int):
+    a = ctypes.c_int32()
+    b = ctypes.c_int32()
+    _lib.check(_lib.load().ndft_get_plan(_prec(prec), n, n_cols, n_bins, ctypes.byref(a),
+                                         ctypes.byref(b)), "ndft_get_plan")
+    return a.value, b.value
+
+
+def prof_enable(on: bool = True) -> None:
+    _lib.check(_lib.load().ndft_prof_enable(1 if on else 0), "ndft_prof_enable")
+
+
+def prof_read():
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _lib.check(_lib.load().ndft_prof_read(ctypes.byref(ms), ctypes.byref(cnt)), "ndft_prof_read")
+    return ms.value, cnt.value

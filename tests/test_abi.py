@@ -1,0 +1,117 @@
+"""The C ABI library: loads without a GPU, exports every declared symbol, and rejects
+invalid arguments on the host before anything is enqueued (no device memory touched:
+the pointers passed here are NULL or host addresses)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1402_0532_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ndft.h")
+
+INVAL, UNSUPPORTED, WORKSPACE = 1, 2, 3
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ndft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared_symbols()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, name
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_status_strings_and_version():
+    lib = _lib.load()
+    for st in range(5):
+        assert lib.ndft_status_string(st).startswith(b"NDFT_")
+    assert b"gfx950" in lib.ndft_version()
+
+
+def _host_buf(nbytes=4096):
+    buf = ctypes.create_string_buffer(nbytes + 256)
+    addr = (ctypes.addressof(buf) + 255) // 256 * 256
+    return buf, ctypes.c_void_p(addr)
+
+
+@pytest.mark.parametrize(
+    "n,tau0,n_tau,p0,n_dop",
+    [(0, 0, 1, 0, 1), (8, -1, 1, 0, 1), (8, 0, 0, 0, 1), (8, 4, 5, 0, 1), (8, 0, 1, 0, 0),
+     (8, 0, 1, 0, 9), ((1 << 24) + 1, 0, 1, 0, 1)],
+)
+def test_caf_rejects_bad_shapes(n, tau0, n_tau, p0, n_dop):
+    lib = _lib.load()
+    keep, p = _host_buf()
+    st = lib.ndft_caf(p, p, n, tau0, n_tau, p0, n_dop, p, 0, p, 4096, None)
+    assert st == INVAL
+    assert lib.ndft_caf_workspace(n, tau0, n_tau, p0, n_dop, 0) == 0
+    st = lib.ndft_dbg_signs(p, p, n, tau0, n_tau, p0, n_dop, p, p, None)
+    assert st == INVAL
+
+
+def test_caf_rejects_null_misaligned_and_precision():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    odd = ctypes.c_void_p(p.value + 4)
+    assert lib.ndft_caf(None, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == INVAL
+    assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, None, 0, p, 4096, None) == INVAL
+    assert lib.ndft_caf(odd, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == INVAL
+    assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, p, 7, p, 4096, None) == INVAL
+    assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, p, 2, p, 4096, None) == UNSUPPORTED
+
+
+def test_caf_rejects_small_or_misaligned_workspace():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    need = lib.ndft_caf_workspace(4096, 0, 256, 0, 4096, 0)
+    assert need > 0
+    assert lib.ndft_caf(p, p, 4096, 0, 256, 0, 4096, p, 0, None, 0, None) == WORKSPACE
+    assert lib.ndft_caf(p, p, 4096, 0, 256, 0, 4096, p, 0, p, need - 1, None) == WORKSPACE
+    odd = ctypes.c_void_p(p.value + 8)
+    assert lib.ndft_caf(p, p, 4096, 0, 256, 0, 4096, p, 0, odd, need, None) == WORKSPACE
+
+
+def test_forward_rejects_bad_args():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    assert lib.ndft_forward(p, p, 1, 0, 0, 1, 0, p, 4096, None) == INVAL
+    assert lib.ndft_forward(p, p, 1, 8, 0, 9, 0, p, 4096, None) == INVAL
+    assert lib.ndft_forward(p, p, -1, 8, 0, 8, 0, p, 4096, None) == INVAL
+    assert lib.ndft_forward(None, p, 2, 8, 0, 8, 0, p, 4096, None) == INVAL
+    assert lib.ndft_forward(p, p, 0, 8, 0, 8, 0, None, 0, None) == 0  # empty batch: no-op
+    assert lib.ndft_forward(p, p, 2, 8, 0, 8, 2, p, 4096, None) == UNSUPPORTED
+
+
+def test_workspace_query_is_consistent():
+    lib = _lib.load()
+    # symmetric Doppler window: 257 base bins (0..256) serve bins -256..255
+    a = lib.ndft_caf_workspace(65536, 0, 1024, -256, 512, 0)
+    b = lib.ndft_caf_workspace(65536, 0, 1024, -256, 512, 0)
+    assert a == b and a % 256 == 0 and a > 0
+    plan = ctypes.c_int32()
+    ks = ctypes.c_int32()
+    assert lib.ndft_get_plan(0, 65536, 1024, 512, ctypes.byref(plan), ctypes.byref(ks)) == 0
+    assert 0 <= plan.value < lib.ndft_plan_count(0) and ks.value >= 1
+
+
+def test_plan_table():
+    lib = _lib.load()
+    for prec in (0, 1):
+        cnt = lib.ndft_plan_count(prec)
+        assert cnt >= 1
+        names = [lib.ndft_plan_name(prec, k) for k in range(cnt)]
+        assert all(names) and len(set(names)) == cnt
+        assert lib.ndft_plan_name(prec, cnt) is None
+        assert lib.ndft_set_plan(prec, cnt, 0) == INVAL
+        assert lib.ndft_set_plan(prec, 0, 3) == 0
+        assert lib.ndft_set_plan(prec, -1, 0) == 0
+    assert lib.ndft_plan_count(5) == 0

@@ -28,7 +28,8 @@ def test_reference_statistics():
     r = cfg["r"].astype(np.complex128)
     n = cfg["n"]
     assert r.dtype == np.complex128 and cfg["r"].dtype == np.complex64
-    assert abs(np.mean(r.real ** 2) - 1.0) < 1e-5 and abs(np.mean(r.imag ** 2) - 1.0) < 0.2
+    assert abs(np.mean(r.real ** 2 + r.imag ** 2) / 2.0 - 1.0) < 1e-5
+    assert abs(np.mean(r.real ** 2) - 1.0) < 0.1 and abs(np.mean(r.imag ** 2) - 1.0) < 0.1
     spec = np.abs(np.fft.fft(r)) ** 2
     k = np.abs(np.fft.fftfreq(n, 1.0 / n))
     assert spec[k > 0.1 * n + 1].sum() < 1e-6 * spec.sum()

@@ -1,0 +1,206 @@
+"""Benchmark: NDFT cross-ambiguity surface cells/s on one MI355X.
+
+Workload (the N = 65536 radar CPI): surveillance/reference of 65536 complex64 samples
+(low-pass Gaussian reference, one target at delay 37 / Doppler 12 bins at -10 dB, clutter
+at delays 0/5/11, -20 dB noise), delays 0..1023, Doppler bins -256..255:
+1024 x 512 = 524288 surface cells per step. A step is one ndft_caf call (contraction +
+ordered split-K reduction) with inputs already resident in HBM.
+
+Prints ONE JSON line. `value` is cells/s of the reported form (default: split-BF16);
+`forms` gives every form with its speed-up over the plain FP32 path; `roofline` is for
+the contraction kernel (algorithmic flops 16 N per cell over its event-timed duration);
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same surface's rows.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0}  # dense MFMA peaks, MI355X spec sheet
+KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_contract.hpp",
+                  "paper_1402_0532_amd/csrc/ndft_device.hpp"]
+TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(form: str):
+    """HBM bytes per contraction launch measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, calibrated on a copy kernel), if recorded for the current kernel source."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = "traffic_bytes_per_launch_" + form
+    return float(rec[key]) if key in rec else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2"])
+    ap.add_argument("--forms", default="fp32,bf16x2", help="forms to time (comma list)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(the surface would shard by delay rows, see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1402_0532_amd as nd
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = synth.config3()
+    n, tau0, n_tau, p0, n_dop = c["n"], c["tau0"], c["n_tau"], c["p0"], c["n_dop"]
+    cells = n_tau * n_dop
+    flops_per_call = 16.0 * n * cells
+    s = torch.from_numpy(c["s"]).to(dev)
+    r = torch.from_numpy(c["r"]).to(dev)
+
+    forms = [f for f in args.forms.split(",") if f]
+    if args.form not in forms:
+        forms.append(args.form)
+    results = {}
+    outs = {}
+    for form in forms:
+        prec = nd.PRECISIONS[form]
+        ws = torch.empty(nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, prec),
+                         dtype=torch.uint8, device=dev)
+        out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=dev)
+        for _ in range(args.warmup):
+            nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        nd.prof_read()  # drop anything recorded before
+        nd.prof_enable(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(args.steps):
+            nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nd.prof_enable(False)
+        k_ms, k_cnt = nd.prof_read()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        kern_ms = k_ms / max(k_cnt, 1)
+        plan, ks = nd.get_plan(prec, n, n_tau, 257)
+        achieved = flops_per_call / (kern_ms * 1e-3) / 1e12
+        results[form] = {
+            "cells_per_s": cells / (ms * 1e-3),
+            "ms_per_step": ms,
+            "wall_ms_per_step": wall * 1e3 / args.steps,
+            "contract_kernel_ms": kern_ms,
+            "contract_tflops_algorithmic": achieved,
+            "mfma_peak_tflops": PEAK_TFLOPS[form],
+            "frac_of_peak": achieved / PEAK_TFLOPS[form],
+            "plan": nd.plan_name(prec, plan),
+            "ksplit": ks,
+        }
+        if form == "bf16x2":
+            # the split form issues two MFMA passes per algorithmic product
+            results[form]["contract_tflops_issued"] = 2 * achieved
+        outs[form] = out.cpu().numpy()
+        del ws
+
+    base = results.get("fp32")
+    for form, rres in results.items():
+        rres["speedup_vs_fp32"] = (base["ms_per_step"] / rres["ms_per_step"]) if base else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        rows = [0]
+        t0 = time.perf_counter()
+        Ao, sc = oracle.caf(c["s"], c["r"], tau0, n_tau, p0, n_dop, rows=np.array(rows))
+        t1 = time.perf_counter() - t0
+        more = max(1, min(n_tau - 1, int(args.cpu_seconds / max(t1, 1e-3)) - 1))
+        rows2 = list(range(1, 1 + more))
+        t0 = time.perf_counter()
+        Ao2, sc2 = oracle.caf(c["s"], c["r"], tau0, n_tau, p0, n_dop, rows=np.array(rows2))
+        t2 = time.perf_counter() - t0
+        cpu = {
+            "value": len(rows2) * n_dop / t2,
+            "unit": "cells/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 literal oracle, delay rows 1..%d x all %d Doppler bins of the same "
+                      "N=65536 surface (%.1f s)" % (len(rows2), n_dop, t2),
+        }
+        # max l1-relative error of each form on the sampled rows
+        allrows = np.array(rows + rows2)
+        Aor = np.concatenate([Ao, Ao2])
+        scr = np.concatenate([sc, sc2])
+        for form, o in outs.items():
+            g = o[allrows].astype(np.complex128)
+            err = (np.abs(g.real - Aor.real) + np.abs(g.imag - Aor.imag)) / np.where(scr > 0, scr, 1)
+            results[form]["max_l1_rel_err_vs_oracle"] = float(err.max())
+            results[form]["err_rows_checked"] = int(len(allrows))
+
+    main_res = results[args.form]
+    line = {
+        "metric": "ambiguity cells/s (tau x Doppler) at N=65536",
+        "value": main_res["cells_per_s"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.form,
+        "data": "synthetic",
+        "config": {"workload": "caf_n65536_tau1024_dop512", "n": n, "tau0": tau0,
+                   "n_tau": n_tau, "p0": p0, "n_dop": n_dop, "form": args.form},
+        "roofline": {
+            "bound": "mfma",
+            "achieved": main_res["contract_tflops_algorithmic"],
+            "peak": PEAK_TFLOPS[args.form],
+            "unit": "TFLOP/s",
+            "frac": main_res["frac_of_peak"],
+            "traffic": load_traffic(args.form),
+        },
+        "cpu_baseline": cpu,
+        "forms": results,
+        "kernel_source_sha256_16": kernel_source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

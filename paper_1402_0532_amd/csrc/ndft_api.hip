@@ -115,15 +115,18 @@ Plan make_plan(const char *name)
 
 const std::vector<Plan> &plans(int prec)
 {
+    // name: bases x delays per work-group, waves, samples per stage
     static const std::vector<Plan> f32 = {
-        make_plan<PREC_FP32, 2, 2, 2, 2, 4>("fp32_b128_l128_ks4"),
-        make_plan<PREC_FP32, 1, 4, 2, 2, 4>("fp32_b64_l256_ks4"),
-        make_plan<PREC_FP32, 4, 1, 2, 2, 4>("fp32_b256_l64_ks4"),
+        make_plan<PREC_FP32, 2, 4, 2, 1, 8>("fp32_b128_l128_w8_ks8"),
+        make_plan<PREC_FP32, 1, 8, 2, 1, 8>("fp32_b64_l256_w8_ks8"),
+        make_plan<PREC_FP32, 4, 2, 2, 1, 8>("fp32_b256_l64_w8_ks8"),
+        make_plan<PREC_FP32, 3, 4, 1, 1, 8>("fp32_b96_l128_w12_ks8"),
     };
     static const std::vector<Plan> bf16 = {
-        make_plan<PREC_BF16X2, 2, 2, 2, 2, 8>("bf16x2_b128_l128_ks8"),
-        make_plan<PREC_BF16X2, 1, 4, 2, 2, 8>("bf16x2_b64_l256_ks8"),
-        make_plan<PREC_BF16X2, 4, 1, 2, 2, 8>("bf16x2_b256_l64_ks8"),
+        make_plan<PREC_BF16X2, 2, 4, 2, 1, 8>("bf16x2_b128_l128_w8_ks8"),
+        make_plan<PREC_BF16X2, 1, 8, 2, 1, 8>("bf16x2_b64_l256_w8_ks8"),
+        make_plan<PREC_BF16X2, 4, 2, 2, 1, 8>("bf16x2_b256_l64_w8_ks8"),
+        make_plan<PREC_BF16X2, 3, 4, 1, 1, 8>("bf16x2_b96_l128_w12_ks8"),
     };
     return prec == NDFT_BF16X2 ? bf16 : f32;
 }
@@ -157,8 +160,11 @@ struct Launch {
     int n_bases, n_bases_pad, n_cols_pad;
     int tb, n_coarse;
     BaseMap bm;
-    size_t ws_bytes;
+    size_t part_bytes; // split-K partials
+    size_t ws_bytes;   // partials + signed copies of the inputs
 };
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 int pick_ksplit(int tiles, int64_t n, int ks, int cus)
 {
@@ -178,7 +184,7 @@ int pick_ksplit(int tiles, int64_t n, int ks, int cus)
     return best;
 }
 
-Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins)
+Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins, int64_t signed_elems)
 {
     Launch L;
     std::memset(&L, 0, sizeof(L));
@@ -192,13 +198,17 @@ Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bi
     }
     const std::vector<Plan> &ps = plans(prec);
     if (pi < 0 || pi >= (int)ps.size()) {
-        // built-in choice: least padded work, then the earlier plan
-        int64_t best = -1;
+        // built-in choice: padded matrix-core work plus operand generation (a tile
+        // generates one twiddle row per base and one lag column per delay, shared by
+        // the other dimension), then the earlier plan
+        double best = -1.0;
         pi = 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
-            int64_t work = cdiv(L.n_bases, ps[k].bt) * ps[k].bt * cdiv(n_cols, ps[k].lt) * ps[k].lt;
-            if (best < 0 || work < best) {
-                best = work;
+            double rows = (double)(cdiv(L.n_bases, ps[k].bt) * ps[k].bt);
+            double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
+            double cost = rows * cols * (1.0 + 64.0 / ps[k].bt + 64.0 / ps[k].lt);
+            if (best < 0 || cost < best * 0.999) {
+                best = cost;
                 pi = k;
             }
         }
@@ -216,7 +226,8 @@ Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bi
     while ((1LL << (2 * tb)) < n) ++tb; // 2^tb >= sqrt(n)
     L.tb = tb;
     L.n_coarse = (int)cdiv(n, 1LL << tb);
-    L.ws_bytes = (size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad * sizeof(float4);
+    L.part_bytes = align256((size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad * sizeof(float4));
+    L.ws_bytes = L.part_bytes + align256((size_t)signed_elems * sizeof(float4));
     return L;
 }
 
@@ -266,15 +277,25 @@ ndft_status check_launch()
     return hipGetLastError() == hipSuccess ? NDFT_OK : NDFT_E_HIP;
 }
 
-ndft_status launch_contract(const Launch &L, int prod, const float2 *s, const float2 *r, long long col_stride,
+ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, int64_t ostride, int64_t lead,
+                        hipStream_t stream)
+{
+    int64_t count = rows * ostride;
+    if (count == 0) return NDFT_OK;
+    hipLaunchKernelGGL(sign_prep_kernel, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, stream, x, out, (int)n,
+                       (long long)rows, (long long)ostride, (int)lead);
+    return check_launch();
+}
+
+ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const float4 *r4, long long col_stride,
                             int64_t n, int64_t n_cols, int64_t tau0, float4 *partial, hipStream_t stream)
 {
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
     ContractParams P;
     std::memset(&P, 0, sizeof(P));
-    P.s = s;
-    P.r = r;
+    P.s4 = s4;
+    P.r4 = r4;
     P.col_stride = col_stride;
     P.n = (int)n;
     P.n_cols = (int)n_cols;
@@ -362,7 +383,7 @@ const char *ndft_version(void) { return "ndft-mi355x 0.1 (gfx950)"; }
 size_t ndft_forward_workspace(int64_t batch, int64_t n, int64_t k0, int64_t k_count, ndft_prec prec)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || batch < 1 || k_count < 1 || k_count > n) return 0;
-    return plan_launch((int)prec, n, batch, k0, k_count).ws_bytes;
+    return plan_launch((int)prec, n, batch, k0, k_count, batch * (n + kTailPad)).ws_bytes;
 }
 
 ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int64_t k0, int64_t k_count,
@@ -375,12 +396,15 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     if (batch == 0) return NDFT_OK;
     if (batch > INT32_MAX / 2) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, batch, k0, k_count);
+    Launch L = plan_launch((int)prec, n, batch, k0, k_count, batch * (n + kTailPad));
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float4 *part = reinterpret_cast<float4 *>(ws);
-    st = launch_contract(L, PROD_IDENTITY, reinterpret_cast<const float2 *>(x), nullptr, n, n, batch, 0, part, s);
+    float4 *x4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
+    st = launch_prep(reinterpret_cast<const float2 *>(x), x4, n, batch, n + kTailPad, 0, s);
+    if (st != NDFT_OK) return st;
+    st = launch_contract(L, PROD_IDENTITY, x4, nullptr, n + kTailPad, n, batch, 0, part, s);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, batch, k0, k_count, reinterpret_cast<float2 *>(X), s);
 }
@@ -388,7 +412,7 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
 size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
 {
     if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
-    return plan_launch((int)prec, n, n_tau, p0, n_dop).ws_bytes;
+    return plan_launch((int)prec, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad).ws_bytes;
 }
 
 ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
@@ -399,13 +423,17 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
     if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, n_tau, p0, n_dop);
+    Launch L = plan_launch((int)prec, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float4 *part = reinterpret_cast<float4 *>(ws);
-    st = launch_contract(L, PROD_LAG, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref),
-                         0, n, n_tau, tau0, part, s);
+    float4 *s4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
+    float4 *r4 = s4 + n + kTailPad; // n zeros, then the reference, then a zero tail
+    st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, s);
+    if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, s);
+    if (st != NDFT_OK) return st;
+    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }
@@ -471,7 +499,7 @@ ndft_status ndft_set_plan(ndft_prec prec, int32_t plan, int32_t ksplit)
 ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t n_bins, int32_t *plan, int32_t *ksplit)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || n_cols < 1 || n_bins < 1 || n_bins > n) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, n_cols, 0, n_bins);
+    Launch L = plan_launch((int)prec, n, n_cols, 0, n_bins, 0);
     if (plan) *plan = (int32_t)(L.plan - plans((int)prec).data());
     if (ksplit) *ksplit = L.ksplit;
     return NDFT_OK;

@@ -50,10 +50,16 @@ __device__ __forceinline__ int base_of(const BaseMap &bm, int idx)
     return b;
 }
 
+// Zero samples after the end of every signed row (covers the last stage's tail).
+constexpr int kTailPad = 16;
+
 struct ContractParams {
-    const float2 *s;      // lag producer: surveillance [n]; identity producer: x [cols][n]
-    const float2 *r;      // lag producer: reference [n]
-    long long col_stride; // identity producer: elements between rows of x
+    const float4 *s4;     // signed samples (re, im, sign re, sign im), each row followed
+                          // by kTailPad zeros: lag producer: surveillance [n + pad];
+                          // identity producer: x [cols][col_stride]
+    const float4 *r4;     // lag producer: signed reference with n zeros in front:
+                          // r4[n + m] = r[m], r4[j < n] = 0 (so r[m < 0] reads 0)
+    long long col_stride; // identity producer: elements between rows of x (>= n + pad)
     int n;
     int n_cols;           // delays (lag) or rows (identity)
     int tau0;             // first delay (lag)
@@ -66,19 +72,32 @@ struct ContractParams {
     float4 *partial;      // [ksplit][n_cols_pad][n_bases_pad] of (U, V, X, Y)
 };
 
+// Pack each complex sample with its exact component signs (read by the producers):
+// rows of n samples from x (row stride n) go to out with row stride `ostride`, starting
+// `lead` elements into each output row; every other output element is zero.
+__global__ __launch_bounds__(256) void sign_prep_kernel(const float2 *__restrict__ x, float4 *__restrict__ out,
+                                                        int n, long long rows, long long ostride, int lead)
+{
+    long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= rows * ostride) return;
+    long long row = k / ostride;
+    long long j = k - row * ostride - lead;
+    out[k] = (j >= 0 && j < n) ? with_signs(x[row * n + j]) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
 {
     bf16x2v v = {(__bf16)lo, (__bf16)hi};
     return __builtin_bit_cast(uint32_t, v);
 }
 
-// bf16 of a value and of its remainder: v = hi + lo + O(2^-18 |v|).
-__device__ __forceinline__ uint32_t split_bf16(float v)
+// bf16 pairs of (a, b) and of their remainders: a = hi.x + lo.x + O(2^-18 |a|).
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t &hi, uint32_t &lo)
 {
-    __bf16 h = (__bf16)v;
-    __bf16 l = (__bf16)(v - (float)h);
-    bf16x2v p = {h, l};
-    return __builtin_bit_cast(uint32_t, p);
+    bf16x2v h = {(__bf16)a, (__bf16)b};
+    bf16x2v l = {(__bf16)(a - (float)h[0]), (__bf16)(b - (float)h[1])};
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -90,19 +109,38 @@ struct ContractCfg {
     // KS/4 groups x 2 x 2 x rows x 16 bytes (BF16): the same byte count.
     static constexpr int STAGE_A_F4 = KS * BT; // float4 units
     static constexpr int STAGE_B_F4 = KS * LT;
-    static constexpr int TW_UNITS = BT * KS / 2; // (row, sample pair) units per stage
+    // producer work per stage: twiddle units (base row, sample pair) and lag-product
+    // units (column, sample pair); thread t takes units t, t + NT, ... of each kind
+    static constexpr int TW_UNITS = BT * KS / 2;
     static constexpr int LG_UNITS = LT * KS / 2;
     static constexpr int TW_ITERS = (TW_UNITS + NT - 1) / NT;
     static constexpr int LG_ITERS = (LG_UNITS + NT - 1) / NT;
     static_assert(PREC != PREC_BF16X2 || KS % 4 == 0, "BF16 stage is whole 4-sample groups");
     static_assert(KS % 2 == 0, "pairs of samples");
+    static_assert(KS <= kTailPad, "the last stage reads at most KS - 1 samples past the record");
 };
 
+struct LagIn {
+    float4 s1, s2, r1, r2;
+};
+
+// Empty instruction that reads the four registers (no code is emitted).
+__device__ __forceinline__ void mark_read(const float4 &v)
+{
+    asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+// BF16 K order inside one lane's 8 elements (a pair of samples i, i+1):
+//   A1 = [Sc_i, Sc_i+1, Sc_i, Sc_i+1, C_hi_i, C_hi_i+1, C_lo_i, C_lo_i+1]
+//   B1 = [zr_hi_i, zr_hi_i+1, zr_lo_i, zr_lo_i+1, sr_i, sr_i+1, sr_i, sr_i+1]
+// so A1.B1 = sum over the pair of Sc z_r + C sigma_r (U); A2 = (St, T) and B2 = (z_i,
+// sigma_i) give X, Y, V the same way.
 template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
 __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(ContractParams P)
 {
     using Cfg = ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>;
     constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT;
+    constexpr int TWI = Cfg::TW_ITERS, LGI = Cfg::LG_ITERS;
 
     __shared__ float4 bufA[2][Cfg::STAGE_A_F4];
     __shared__ float4 bufB[2][Cfg::STAGE_B_F4];
@@ -132,17 +170,32 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
 
     build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, NT);
 
-    // ---- producer state: twiddle units (row, pair) and lag units (col, pair) ----
-    int tw_m[Cfg::TW_ITERS], tw_b[Cfg::TW_ITERS], tw_dm[Cfg::TW_ITERS];
+    // ---- twiddle slots: base row, sample pair, base b, m = b i mod n, step ----
+    int tw_row[TWI], tw_pair[TWI], tw_b[TWI], tw_m[TWI], tw_dm[TWI];
 #pragma unroll
-    for (int it = 0; it < Cfg::TW_ITERS; ++it) {
-        int u = tid + it * NT;
+    for (int it = 0; it < TWI; ++it) {
+        int u = min(tid + it * NT, Cfg::TW_UNITS - 1);
         int row = u % BT, pair = u / BT;
         int b = base_of(P.bm, b0 + row);
         long long i0 = (long long)k_begin + 2 * pair;
+        tw_row[it] = row;
+        tw_pair[it] = pair;
         tw_b[it] = b;
         tw_m[it] = (int)(((long long)b * i0) % n);
         tw_dm[it] = (int)(((long long)b * KS) % n);
+    }
+    // ---- lag slots: column, sample pair, delay d, row pointer (identity) ----
+    int lg_col[LGI], lg_pair[LGI], lg_d[LGI];
+    const float4 *lg_x[LGI];
+#pragma unroll
+    for (int it = 0; it < LGI; ++it) {
+        int u = min(tid + it * NT, Cfg::LG_UNITS - 1);
+        int col = u % LT;
+        int c = min(c0 + col, P.n_cols - 1); // padding columns repeat a valid one
+        lg_col[it] = col;
+        lg_pair[it] = u / LT;
+        lg_d[it] = P.tau0 + c;
+        lg_x[it] = PROD == PROD_LAG ? P.s4 : P.s4 + (long long)c * P.col_stride;
     }
 
     f32x16 acc[WB][WL][4];
@@ -155,16 +208,29 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[i][j][t][e] = 0.0f;
 
-    __syncthreads(); // tables ready
-
-    auto produce = [&](int st, int buf) {
+    // Lag slots load without a branch: padded rows make every address valid and
+    // samples outside the record read as zero.
+    auto load_lag = [&](int st, LagIn *in) {
         const int ibase = k_begin + st * KS;
-        // twiddle rows
 #pragma unroll
-        for (int it = 0; it < Cfg::TW_ITERS; ++it) {
-            int u = tid + it * NT;
-            if (Cfg::TW_UNITS % NT == 0 || u < Cfg::TW_UNITS) {
-                int row = u % BT, pair = u / BT;
+        for (int it = 0; it < LGI; ++it) {
+            int i1 = ibase + 2 * lg_pair[it];
+            in[it].s1 = lg_x[it][i1];
+            in[it].s2 = lg_x[it][i1 + 1];
+            if (PROD == PROD_LAG) {
+                const float4 *rr = P.r4 + (n + i1 - lg_d[it]);
+                in[it].r1 = rr[0];
+                in[it].r2 = rr[1];
+            }
+        }
+    };
+
+    auto produce = [&](int buf, const LagIn *in) {
+        // ---- twiddle rows: signs from integer m, values from the table ----
+#pragma unroll
+        for (int it = 0; it < TWI; ++it) {
+            if (Cfg::TW_UNITS % NT == 0 || tid + it * NT < Cfg::TW_UNITS) {
+                const int row = tw_row[it], pair = tw_pair[it];
                 int m1 = tw_m[it];
                 int m2 = m1 + tw_b[it];
                 m2 = m2 >= n ? m2 - n : m2;
@@ -185,16 +251,13 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
                 } else {
                     uint4 *A = reinterpret_cast<uint4 *>(bufA[buf]);
                     int g = pair >> 1, hh = pair & 1;
-                    float c1 = (float)g1.c, t1 = (float)g1.t, c2 = (float)g2.c, t2 = (float)g2.t;
                     uint4 a1, a2;
-                    a1.x = pack_bf16x2(c1, c1);
-                    a1.y = split_bf16(w1.x);
-                    a1.z = pack_bf16x2(c2, c2);
-                    a1.w = split_bf16(w2.x);
-                    a2.x = pack_bf16x2(t1, t1);
-                    a2.y = split_bf16(w1.y);
-                    a2.z = pack_bf16x2(t2, t2);
-                    a2.w = split_bf16(w2.y);
+                    a1.x = pack_bf16x2((float)g1.c, (float)g2.c);
+                    a1.y = a1.x;
+                    split_pair(w1.x, w2.x, a1.z, a1.w);
+                    a2.x = pack_bf16x2((float)g1.t, (float)g2.t);
+                    a2.y = a2.x;
+                    split_pair(w1.y, w2.y, a2.z, a2.w);
                     A[((g * 2 + 0) * 2 + hh) * BT + row] = a1;
                     A[((g * 2 + 1) * 2 + hh) * BT + row] = a2;
                 }
@@ -202,28 +265,26 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
                 tw_m[it] = mn >= n ? mn - n : mn;
             }
         }
-        // lag-product (or identity) columns
+        // ---- lag-product (or identity) columns ----
 #pragma unroll
-        for (int it = 0; it < Cfg::LG_ITERS; ++it) {
-            int u = tid + it * NT;
-            if (Cfg::LG_UNITS % NT == 0 || u < Cfg::LG_UNITS) {
-                int col = u % LT, pair = u / LT;
-                int c = c0 + col;
-                int i1 = ibase + 2 * pair, i2 = i1 + 1;
+        for (int it = 0; it < LGI; ++it) {
+            // the prefetched registers count as read here on every path, so the next
+            // prefetch into them never waits on newer loads
+            mark_read(in[it].s1);
+            mark_read(in[it].s2);
+            if (PROD == PROD_LAG) {
+                mark_read(in[it].r1);
+                mark_read(in[it].r2);
+            }
+            if (Cfg::LG_UNITS % NT == 0 || tid + it * NT < Cfg::LG_UNITS) {
+                const int col = lg_col[it], pair = lg_pair[it];
                 Lag z1, z2;
-                const float2 zero = make_float2(0.0f, 0.0f);
                 if (PROD == PROD_LAG) {
-                    int d = P.tau0 + min(c, P.n_cols - 1);
-                    float2 s1 = i1 < k_end ? P.s[i1] : zero;
-                    float2 s2 = i2 < k_end ? P.s[i2] : zero;
-                    float2 r1 = (i1 < k_end && i1 - d >= 0) ? P.r[i1 - d] : zero;
-                    float2 r2 = (i2 < k_end && i2 - d >= 0) ? P.r[i2 - d] : zero;
-                    z1 = lag_product(s1, r1);
-                    z2 = lag_product(s2, r2);
+                    z1 = lag_product4(in[it].s1, in[it].r1);
+                    z2 = lag_product4(in[it].s2, in[it].r2);
                 } else {
-                    const float2 *x = P.s + (long long)min(c, P.n_cols - 1) * P.col_stride;
-                    z1 = identity_entry(i1 < k_end ? x[i1] : zero);
-                    z2 = identity_entry(i2 < k_end ? x[i2] : zero);
+                    z1 = identity_entry(in[it].s1);
+                    z2 = identity_entry(in[it].s2);
                 }
                 if (PREC == PREC_FP32) {
                     float *B = reinterpret_cast<float *>(bufB[buf]);
@@ -240,14 +301,12 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
                     uint4 *B = reinterpret_cast<uint4 *>(bufB[buf]);
                     int g = pair >> 1, hh = pair & 1;
                     uint4 v1, v2;
-                    v1.x = split_bf16(z1.zr);
-                    v1.y = pack_bf16x2(z1.sr, z1.sr);
-                    v1.z = split_bf16(z2.zr);
-                    v1.w = pack_bf16x2(z2.sr, z2.sr);
-                    v2.x = split_bf16(z1.zi);
-                    v2.y = pack_bf16x2(z1.si, z1.si);
-                    v2.z = split_bf16(z2.zi);
-                    v2.w = pack_bf16x2(z2.si, z2.si);
+                    split_pair(z1.zr, z2.zr, v1.x, v1.y);
+                    v1.z = pack_bf16x2(z1.sr, z2.sr);
+                    v1.w = v1.z;
+                    split_pair(z1.zi, z2.zi, v2.x, v2.y);
+                    v2.z = pack_bf16x2(z1.si, z2.si);
+                    v2.w = v2.z;
                     B[((g * 2 + 0) * 2 + hh) * LT + col] = v1;
                     B[((g * 2 + 1) * 2 + hh) * LT + col] = v2;
                 }
@@ -313,13 +372,44 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
         }
     };
 
+    // One pipeline step with compile-time buffer indices (so the generator's LDS
+    // writes are known not to alias the multiply's LDS reads): inputs of stage st+1
+    // are in `cur`; fetch stage st+2 into `nxt`, generate stage st+1 into buffer PB,
+    // multiply stage st from buffer CB, then one barrier.
+    LagIn inA[LGI], inB[LGI];
+    __syncthreads(); // tables ready
     if (nst > 0) {
-        produce(0, 0);
+        load_lag(0, inB);
+        if (nst > 1) load_lag(1, inA);
+        produce(0, inB);
         __syncthreads();
-        for (int st = 0; st < nst; ++st) {
-            if (st + 1 < nst) produce(st + 1, (st + 1) & 1);
-            consume(st & 1);
+        // Steady state: every step prefetches stage st+2, generates stage st+1 and
+        // multiplies stage st; the scheduling barriers keep each prefetch ahead of the
+        // generator so its registers stay separate from the stage being generated.
+        int st = 0;
+        for (; st + 3 < nst; st += 2) {
+            load_lag(st + 2, inB);
+            __builtin_amdgcn_sched_barrier(0);
+            produce(1, inA);
+            consume(0);
             __syncthreads();
+            load_lag(st + 3, inA);
+            __builtin_amdgcn_sched_barrier(0);
+            produce(0, inB);
+            consume(1);
+            __syncthreads();
+        }
+        // the last one to three stages
+        for (; st < nst; st += 2) {
+            if (st + 2 < nst) load_lag(st + 2, inB);
+            if (st + 1 < nst) produce(1, inA);
+            consume(0);
+            __syncthreads();
+            if (st + 1 < nst) {
+                if (st + 2 < nst) produce(0, inB);
+                consume(1);
+                __syncthreads();
+            }
         }
     }
 

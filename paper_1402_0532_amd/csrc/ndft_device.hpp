@@ -32,7 +32,7 @@ __device__ __forceinline__ int isgn(int v) { return min(max(v, -1), 1); }
 // In FP64 each pair sum is split exactly into value + error (Knuth's TwoSum). Rounding
 // to nearest is monotone, so unequal rounded sums order the exact sums; equal rounded
 // sums leave the difference of the two error terms, which FP64 compares exactly.
-__device__ __noinline__ int cmp_sum_exact(float a, float b, float c, float d)
+__device__ __forceinline__ int cmp_sum_exact(float a, float b, float c, float d)
 {
     double A = a, B = b, C = c, D = d;
     double x = A + B;
@@ -59,14 +59,19 @@ struct Lag {
     float sr, si; // exact sign of each component, in {-1, 0, +1}
 };
 
-__device__ __forceinline__ Lag lag_product(float2 s, float2 r)
+// Sample packed with its exact component signs: (re, im, sign re, sign im).
+__device__ __forceinline__ float4 with_signs(float2 x)
 {
-    float ssr = sgnf(s.x), ssi = sgnf(s.y);
-    float srr = sgnf(r.x), sri = sgnf(r.y);
-    float t1 = fmaf(s.x, srr, r.x * ssr); // s_r (x) r_r
-    float t2 = fmaf(s.y, sri, r.y * ssi); // s_i (x) r_i
-    float t3 = fmaf(s.y, srr, r.x * ssi); // s_i (x) r_r
-    float t4 = fmaf(r.y, ssr, s.x * sri); // r_i (x) s_r
+    return make_float4(x.x, x.y, sgnf(x.x), sgnf(x.y));
+}
+
+// Lag product from signed samples s = (s_r, s_i, sgn s_r, sgn s_i), r likewise.
+__device__ __forceinline__ Lag lag_product4(float4 s, float4 r)
+{
+    float t1 = fmaf(s.x, r.z, r.x * s.z); // s_r (x) r_r
+    float t2 = fmaf(s.y, r.w, r.y * s.w); // s_i (x) r_i
+    float t3 = fmaf(s.y, r.z, r.x * s.w); // s_i (x) r_r
+    float t4 = fmaf(r.y, s.z, s.x * r.w); // r_i (x) s_r
     Lag z;
     z.zr = t1 + t2;
     z.zi = t3 - t4;
@@ -83,14 +88,19 @@ __device__ __forceinline__ Lag lag_product(float2 s, float2 r)
     return z;
 }
 
-// Identity producer (plain NDFT of x): value x, exact signs by bit test.
-__device__ __forceinline__ Lag identity_entry(float2 x)
+__device__ __forceinline__ Lag lag_product(float2 s, float2 r)
+{
+    return lag_product4(with_signs(s), with_signs(r));
+}
+
+// Identity producer (plain NDFT of x): a signed sample as it is.
+__device__ __forceinline__ Lag identity_entry(float4 x)
 {
     Lag z;
     z.zr = x.x;
     z.zi = x.y;
-    z.sr = sgnf(x.x);
-    z.si = sgnf(x.y);
+    z.sr = x.z;
+    z.si = x.w;
     return z;
 }
 

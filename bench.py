@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x2", help="forms to time (comma list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size per step (a known-size "
+                         "kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,13 +113,19 @@ def main():
         for _ in range(args.steps):
             nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
         ev1.record()
+        if args.calib_copy_mib:
+            src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(args.steps):
+                dst.copy_(src)
+            del src, dst
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         nd.prof_enable(False)
         k_ms, k_cnt = nd.prof_read()
         ms = ev0.elapsed_time(ev1) / args.steps
         kern_ms = k_ms / max(k_cnt, 1)
-        plan, ks = nd.get_plan(prec, n, n_tau, 257)
+        plan, ks = nd.get_plan(prec, n, n_tau, p0, n_dop)
         achieved = flops_per_call / (kern_ms * 1e-3) / 1e12
         results[form] = {
             "cells_per_s": cells / (ms * 1e-3),
@@ -144,12 +153,14 @@ def main():
         import oracle
 
         oracle.build()
-        rows = [0]
+        nthr = oracle.num_threads()
+        rows = list(range(nthr))  # one row per thread: the oracle runs rows in parallel
         t0 = time.perf_counter()
         Ao, sc = oracle.caf(c["s"], c["r"], tau0, n_tau, p0, n_dop, rows=np.array(rows))
         t1 = time.perf_counter() - t0
-        more = max(1, min(n_tau - 1, int(args.cpu_seconds / max(t1, 1e-3)) - 1))
-        rows2 = list(range(1, 1 + more))
+        per_batch = max(t1, 1e-3)
+        batches = max(1, int(args.cpu_seconds / per_batch))
+        rows2 = list(range(nthr, min(n_tau, nthr * (1 + batches))))
         t0 = time.perf_counter()
         Ao2, sc2 = oracle.caf(c["s"], c["r"], tau0, n_tau, p0, n_dop, rows=np.array(rows2))
         t2 = time.perf_counter() - t0
@@ -158,8 +169,8 @@ def main():
             "unit": "cells/s",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "FP64 literal oracle, delay rows 1..%d x all %d Doppler bins of the same "
-                      "N=65536 surface (%.1f s)" % (len(rows2), n_dop, t2),
+            "sample": "FP64 literal oracle, delay rows %d..%d x all %d Doppler bins of the same "
+                      "N=65536 surface (%.1f s)" % (rows2[0], rows2[-1], n_dop, t2),
         }
         # max l1-relative error of each form on the sampled rows
         allrows = np.array(rows + rows2)

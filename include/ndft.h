@@ -153,7 +153,9 @@ ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
 int32_t ndft_plan_count(ndft_prec prec);
 const char *ndft_plan_name(ndft_prec prec, int32_t plan);
 ndft_status ndft_set_plan(ndft_prec prec, int32_t plan, int32_t ksplit);
-ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t n_bins,
+/* The plan and ksplit ndft_caf / ndft_forward would use for (n, n_cols = delays or
+ * rows, bins p0 .. p0 + n_bins - 1). */
+ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
                           int32_t *plan, int32_t *ksplit);
 
 /* ---------------------------------------------------------------------------------

@@ -204,10 +204,11 @@ def set_plan(prec, plan: int = -1, ksplit: int = 0) -> None:
     _lib.check(_lib.load().ndft_set_plan(_prec(prec), int(plan), int(ksplit)), "ndft_set_plan")
 
 
-def get_plan(prec, n: int, n_cols: int, n_bins: int):
+def get_plan(prec, n: int, n_cols: int, p0: int, n_bins: int):
+    """(plan index, ksplit) the library would use for this shape."""
     a = ctypes.c_int32()
     b = ctypes.c_int32()
-    _lib.check(_lib.load().ndft_get_plan(_prec(prec), n, n_cols, n_bins, ctypes.byref(a),
+    _lib.check(_lib.load().ndft_get_plan(_prec(prec), n, n_cols, p0, n_bins, ctypes.byref(a),
                                          ctypes.byref(b)), "ndft_get_plan")
     return a.value, b.value
 

@@ -496,10 +496,11 @@ ndft_status ndft_set_plan(ndft_prec prec, int32_t plan, int32_t ksplit)
     return NDFT_OK;
 }
 
-ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t n_bins, int32_t *plan, int32_t *ksplit)
+ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins, int32_t *plan,
+                          int32_t *ksplit)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || n_cols < 1 || n_bins < 1 || n_bins > n) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, n_cols, 0, n_bins, 0);
+    Launch L = plan_launch((int)prec, n, n_cols, p0, n_bins, 0);
     if (plan) *plan = (int32_t)(L.plan - plans((int)prec).data());
     if (ksplit) *ksplit = L.ksplit;
     return NDFT_OK;

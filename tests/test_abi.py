@@ -99,7 +99,7 @@ def test_workspace_query_is_consistent():
     assert a == b and a % 256 == 0 and a > 0
     plan = ctypes.c_int32()
     ks = ctypes.c_int32()
-    assert lib.ndft_get_plan(0, 65536, 1024, 512, ctypes.byref(plan), ctypes.byref(ks)) == 0
+    assert lib.ndft_get_plan(0, 65536, 1024, -256, 512, ctypes.byref(plan), ctypes.byref(ks)) == 0
     assert 0 <= plan.value < lib.ndft_plan_count(0) and ks.value >= 1
 
 

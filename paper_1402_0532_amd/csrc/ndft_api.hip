@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ndft.h"
+#include "ndft_backward.hpp"
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
 
@@ -359,6 +360,24 @@ ndft_status ws_ok(void *ws, size_t ws_bytes, size_t need)
     return NDFT_OK;
 }
 
+struct AdjLaunch {
+    BaseMap bm;
+    int n_bases, n_bases_pad;
+    size_t eo_bytes, dz_bytes, ws_bytes;
+};
+
+AdjLaunch plan_adjoint(int64_t n, int64_t n_tau, int64_t p0, int64_t n_dop)
+{
+    AdjLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.bm = make_base_map(n, p0, n_dop, &L.n_bases);
+    L.n_bases_pad = (int)(cdiv(L.n_bases, 8) * 8);
+    L.eo_bytes = align256((size_t)L.n_bases_pad * n_tau * sizeof(float4));
+    L.dz_bytes = align256((size_t)n_tau * n * sizeof(float2));
+    L.ws_bytes = L.eo_bytes + L.dz_bytes;
+    return L;
+}
+
 } // namespace
 
 // ======================================================================================
@@ -454,12 +473,57 @@ ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
     return check_launch();
 }
 
-size_t ndft_caf_backward_workspace(int64_t, int64_t, int64_t, int64_t, int64_t, ndft_prec) { return 0; }
-
-ndft_status ndft_caf_backward(const ndft_c64 *, const ndft_c64 *, int64_t, int64_t, int64_t, int64_t, int64_t,
-                              const ndft_c64 *, ndft_c64 *, ndft_c64 *, ndft_prec, void *, size_t, void *)
+size_t ndft_caf_backward_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
+                                   ndft_prec prec)
 {
-    return NDFT_E_UNSUPPORTED;
+    if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
+    return plan_adjoint(n, n_tau, p0, n_dop).ws_bytes;
+}
+
+ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
+                              int64_t p0, int64_t n_dop, const ndft_c64 *grad_A, ndft_c64 *grad_ref,
+                              ndft_c64 *grad_surv, ndft_prec prec, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
+    if (!surv || !ref || !grad_A || !grad_ref) return NDFT_E_INVAL;
+    if (!aligned(surv, 8) || !aligned(ref, 8) || !aligned(grad_A, 8) || !aligned(grad_ref, 8)) return NDFT_E_INVAL;
+    if (grad_surv && !aligned(grad_surv, 8)) return NDFT_E_INVAL;
+    if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
+    if (!prec_ok(prec)) return NDFT_E_INVAL;
+    AdjLaunch L = plan_adjoint(n, n_tau, p0, n_dop);
+    ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
+    if (st != NDFT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float4 *eo = reinterpret_cast<float4 *>(ws);
+    float2 *dz = reinterpret_cast<float2 *>(static_cast<char *>(ws) + L.eo_bytes);
+    int64_t neo = (int64_t)L.n_bases_pad * n_tau;
+    hipLaunchKernelGGL(adj_prep_kernel, dim3((unsigned)cdiv(neo, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float2 *>(grad_A), (int)n_tau, (int)n_dop, (int)n, (int)mod_n(p0, n),
+                       L.bm, L.n_bases, L.n_bases_pad, eo);
+    if ((st = check_launch()) != NDFT_OK) return st;
+    AdjParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.eo = eo;
+    P.bm = L.bm;
+    P.n = (int)n;
+    P.n_tau = (int)n_tau;
+    P.n_bases_pad = L.n_bases_pad;
+    P.dz = dz;
+    dim3 grid((unsigned)(cdiv(n_tau, 64) * cdiv(n, 128)));
+    {
+        ProfScope prof(s);
+        if (prec == NDFT_BF16X2)
+            hipLaunchKernelGGL(adj_contract_kernel<PREC_BF16X2>, grid, dim3(256), 0, s, P);
+        else
+            hipLaunchKernelGGL(adj_contract_kernel<PREC_FP32>, grid, dim3(256), 0, s, P);
+        prof.stop();
+    }
+    if ((st = check_launch()) != NDFT_OK) return st;
+    hipLaunchKernelGGL(adj_band_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, dz,
+                       reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), (int)n,
+                       (int)tau0, (int)n_tau, reinterpret_cast<float2 *>(grad_ref),
+                       reinterpret_cast<float2 *>(grad_surv));
+    return check_launch();
 }
 
 size_t ndft_caf_batched_workspace(const ndft_cpi *, int32_t, ndft_prec) { return 0; }

@@ -1,0 +1,195 @@
+// Adjoint of the Eq. (12a) surface with respect to the reference and surveillance
+// inputs, with the almost-everywhere derivative d(x (x) y)/dx = sign(y) at every
+// operator node (the sign functions are held constant).
+//
+// With G[l][q] = dL/dRe A + j dL/dIm A, the outer operator of Eq. (6) gives
+//     dz[l][i] = sum_q conj(S[p_q, i]) G[l][q],        S = csgn(W^{i p}),
+// and the lag product z = s (x) conj(r) gives
+//     grad_r[m] = sum_l conj(dz[l][m + d_l]) csgn(s[m + d_l]),
+//     grad_s[i] = sum_l dz[l][i] csgn(r[i - d_l]).
+// No lag-product value enters. Bins p and -p share S up to conjugation, so per base
+// bin b, with Gp = G[l][bin +b] and Gm = G[l][bin -b] (0 when not requested):
+//     dz[l][i] = sum_b Sc[b,i] E[l][b] + St[b,i] O[l][b],  E = Gp + Gm,  O = j (Gm - Gp),
+// a real matrix product whose second operand (Sc, St) is exactly ternary.
+#pragma once
+
+#include "ndft_contract.hpp"
+
+namespace ndft {
+
+// E/O operand per (base index, delay), zero for padding bases:
+// eo[bi][l] = (E_r, E_i, O_r, O_i).
+__global__ __launch_bounds__(256) void adj_prep_kernel(const float2 *__restrict__ G, int n_tau, int n_dop,
+                                                       int n, int p0n, BaseMap bm, int n_bases, int n_bases_pad,
+                                                       float4 *__restrict__ eo)
+{
+    long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (long long)n_bases_pad * n_tau) return;
+    int bi = (int)(k / n_tau);
+    int l = (int)(k % n_tau);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (bi < n_bases) {
+        int b = base_of(bm, bi);
+        float2 gp = make_float2(0.f, 0.f), gm = make_float2(0.f, 0.f);
+        int q = b - p0n;
+        q = q < 0 ? q + n : q;
+        if (q < n_dop) gp = G[(long long)l * n_dop + q];
+        int bm2 = b == 0 ? 0 : n - b;
+        if (bm2 != b) {
+            int q2 = bm2 - p0n;
+            q2 = q2 < 0 ? q2 + n : q2;
+            if (q2 < n_dop) gm = G[(long long)l * n_dop + q2];
+        }
+        v.x = gp.x + gm.x;
+        v.y = gp.y + gm.y;
+        v.z = -(gm.y - gp.y);
+        v.w = gm.x - gp.x;
+    }
+    eo[k] = v;
+}
+
+struct AdjParams {
+    const float4 *eo; // [n_bases_pad][n_tau]
+    BaseMap bm;
+    int n, n_tau, n_bases_pad;
+    float2 *dz; // [n_tau][n]
+};
+
+// dz tile: 64 delays x 128 samples per work-group (4 waves of 32 x 64), K = bases.
+//   PREC_FP32:   v_mfma_f32_32x32x2_f32, one base per step: k = (E term, O term).
+//   PREC_BF16X2: v_mfma_f32_32x32x16_bf16, lane k order for bases (b, b+1):
+//                [E_hi_b, E_hi_b+1, E_lo_b, E_lo_b+1, O_hi_b, O_hi_b+1, O_lo_b, O_lo_b+1]
+//                against [Sc_b, Sc_b+1, Sc_b, Sc_b+1, St_b, St_b+1, St_b, St_b+1].
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
+{
+    constexpr int LT = 64, IT = 128, KB = 8; // delays, samples, bases per stage
+    __shared__ float4 sA[KB][LT];            // E/O of the stage's bases
+    __shared__ float2 sB[KB][IT];            // (Sc, St) of the stage's bases
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int wl = wave & 1, wi = wave >> 1; // wave tile: 32 delays x 64 samples
+    const int tiles_l = (P.n_tau + LT - 1) / LT;
+    const int l0 = (blockIdx.x % tiles_l) * LT;
+    const int i0 = (blockIdx.x / tiles_l) * IT;
+    const int n = P.n;
+
+    f32x16 acc[2][2]; // [sample block][re, im]
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[j][c][e] = 0.0f;
+
+    for (int kb0 = 0; kb0 < P.n_bases_pad; kb0 += KB) {
+        // stage: E/O rows (64 delays x 8 bases) and sign columns (8 bases x 128 samples)
+        for (int u = tid; u < KB * LT; u += 256) {
+            int k = u / LT, l = u % LT;
+            int lc = min(l0 + l, P.n_tau - 1);
+            float4 v = P.eo[(long long)(kb0 + k) * P.n_tau + lc];
+            sA[k][l] = l0 + l < P.n_tau ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        for (int u = tid; u < KB * IT; u += 256) {
+            int k = u / IT, c = u % IT;
+            int i = min(i0 + c, n - 1);
+            int b = base_of(P.bm, kb0 + k);
+            int m = (int)(((unsigned long long)b * (unsigned long long)i) % (unsigned long long)n);
+            TwSign g = twiddle_sign(m, n);
+            sB[k][c] = make_float2((float)g.c, (float)g.t);
+        }
+        __syncthreads();
+        if (PREC == PREC_FP32) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                float4 e = sA[k][wl * 32 + l32];
+                float ar = h ? e.z : e.x; // E_r or O_r
+                float ai = h ? e.w : e.y; // E_i or O_i
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    float2 sg = sB[k][wi * 64 + 32 * j + l32];
+                    float bv = h ? sg.y : sg.x; // Sc or St
+                    acc[j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bv, acc[j][0], 0, 0, 0);
+                    acc[j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bv, acc[j][1], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KB; k += 4) {
+                // lane half h takes bases k + 2h, k + 2h + 1
+                float4 e1 = sA[k + 2 * h][wl * 32 + l32];
+                float4 e2 = sA[k + 2 * h + 1][wl * 32 + l32];
+                uint4 ar, ai;
+                split_pair(e1.x, e2.x, ar.x, ar.y);
+                split_pair(e1.z, e2.z, ar.z, ar.w);
+                split_pair(e1.y, e2.y, ai.x, ai.y);
+                split_pair(e1.w, e2.w, ai.z, ai.w);
+                bf16x8 va = __builtin_bit_cast(bf16x8, ar), vi = __builtin_bit_cast(bf16x8, ai);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    float2 s1 = sB[k + 2 * h][wi * 64 + 32 * j + l32];
+                    float2 s2 = sB[k + 2 * h + 1][wi * 64 + 32 * j + l32];
+                    uint4 bv;
+                    bv.x = pack_bf16x2(s1.x, s2.x);
+                    bv.y = bv.x;
+                    bv.z = pack_bf16x2(s1.y, s2.y);
+                    bv.w = bv.z;
+                    bf16x8 vb = __builtin_bit_cast(bf16x8, bv);
+                    acc[j][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, acc[j][0], 0, 0, 0);
+                    acc[j][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vi, vb, acc[j][1], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // rows = delays 8*(e/4) + 4*h + e%4, column = sample l32
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        int i = i0 + wi * 64 + 32 * j + l32;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int l = l0 + wl * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+            if (l < P.n_tau && i < n) P.dz[(long long)l * n + i] = make_float2(acc[j][0][e], acc[j][1][e]);
+        }
+    }
+}
+
+// grad_r[m] = sum_l conj(dz[l][m + d_l]) csgn(s[m + d_l]); grad_s[i] = sum_l dz[l][i] csgn(r[i - d_l]).
+// One thread per output element, delays summed in ascending order.
+__global__ __launch_bounds__(256) void adj_band_kernel(const float2 *__restrict__ dz, const float2 *__restrict__ s,
+                                                       const float2 *__restrict__ r, int n, int tau0, int n_tau,
+                                                       float2 *__restrict__ grad_r, float2 *__restrict__ grad_s)
+{
+    int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    {
+        const int m = k;
+        float ar = 0.f, ai = 0.f;
+        for (int l = 0; l < n_tau; ++l) {
+            int i = m + tau0 + l;
+            if (i >= n) break;
+            float2 z = dz[(long long)l * n + i];
+            float2 sv = s[i];
+            float sr = sgnf(sv.x), si = sgnf(sv.y);
+            ar += z.x * sr + z.y * si;
+            ai += z.x * si - z.y * sr;
+        }
+        grad_r[m] = make_float2(ar, ai);
+    }
+    if (grad_s) {
+        const int i = k;
+        float ar = 0.f, ai = 0.f;
+        for (int l = 0; l < n_tau; ++l) {
+            int m = i - tau0 - l;
+            if (m < 0) break;
+            float2 z = dz[(long long)l * n + i];
+            float2 rv = r[m];
+            float rr = sgnf(rv.x), ri = sgnf(rv.y);
+            ar += z.x * rr - z.y * ri;
+            ai += z.x * ri + z.y * rr;
+        }
+        grad_s[i] = make_float2(ar, ai);
+    }
+}
+
+} // namespace ndft

@@ -91,29 +91,40 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
- * Batched surfaces (many CPIs of uneven length) in one persistent launch.
- * A CPI c computes the ndft_caf surface of
- *   surv_pool[surv_off .. surv_off+n), ref_pool[ref_off .. ref_off+n)
- * into out_pool[out_off .. out_off + n_tau*n_dop) with its own (n, tau0, n_tau, p0,
+ * Batched surfaces: many CPIs of uneven length in one persistent launch.
+ * CPI c computes the ndft_caf surface of
+ *   surv_pool[surv_off .. surv_off + n), ref_pool[ref_off .. ref_off + n)
+ * into out_pool[out_off .. out_off + n_tau * n_dop) with its own (n, tau0, n_tau, p0,
  * n_dop); offsets are in complex elements. Each CPI obeys the ndft_caf limits.
  *
- * ndft_caf_batched_prepare() writes the CPI table and the tile schedule into `ws`
- * (a blocking host-to-device copy; call it once per batch layout, outside stream
- * capture). ndft_caf_batched() then only launches kernels on `stream` (no copies,
- * allocations or memsets), so it may be captured into a hipGraph and replayed; each
- * replay recomputes every surface from the current pool contents. The `cpis` array is
- * HOST memory and may be freed after prepare returns.
+ * ndft_caf_batched_prepare() validates the CPIs, picks one tile plan for the batch,
+ * splits every surface into (tile, sample chunk) work items of about `chunk` samples
+ * (0 = 4096; rounded to the plan's stage size), writes the CPI tables and the item list
+ * (longest chunks first) into `ws` with a blocking host-to-device copy, and fills the
+ * host struct `batch`. Call it outside stream capture. The `cpis` array is host memory
+ * and may be freed afterwards.
+ *
+ * ndft_caf_batched() then only launches kernels on `stream` (no copies, allocations or
+ * memsets), so it may be captured into a hipGraph and replayed; each run recomputes
+ * every surface from the current pool contents. `batch` and `ws` must come from the
+ * same prepare call (the kernels check a tag stored in `ws` and do nothing otherwise).
+ * Calls that share a workspace must not overlap in time.
  * ------------------------------------------------------------------------------- */
 typedef struct {
     int64_t n, surv_off, ref_off, out_off, tau0, n_tau, p0, n_dop;
 } ndft_cpi;
 
-size_t ndft_caf_batched_workspace(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec);
-ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec,
-                                     void *ws, size_t ws_bytes);
-ndft_status ndft_caf_batched(const ndft_c64 *surv_pool, const ndft_c64 *ref_pool,
-                             ndft_c64 *out_pool, ndft_prec prec, void *ws, size_t ws_bytes,
-                             void *stream);
+typedef struct {
+    int32_t prec, plan, n_cpi, n_items, grid, table_bytes, max_red_blocks, max_prep_blocks;
+    uint64_t tag;
+    uint64_t ws_bytes;
+} ndft_batch;
+
+size_t ndft_caf_batched_workspace(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec, int32_t chunk);
+ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec, int32_t chunk,
+                                     void *ws, size_t ws_bytes, ndft_batch *batch);
+ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool, const ndft_c64 *ref_pool,
+                             ndft_c64 *out_pool, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * Adjoint of the surface with respect to the reference (and optionally the

@@ -20,6 +20,7 @@ PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
 
 __all__ = [
     "FP32", "BF16X2", "FP8", "forward", "caf", "caf_backward", "caf_batched", "BatchPlan",
+    "pack_batch",
     "NDFTCaf", "dbg_signs", "plan_count", "plan_name", "set_plan", "get_plan",
     "prof_enable", "prof_read", "version",
 ]
@@ -145,9 +146,14 @@ class NDFTCaf(torch.autograd.Function):
 
 
 class BatchPlan:
-    """Prepared batch of CPIs for caf_batched (tile schedule resident in the workspace)."""
+    """A prepared batch of CPIs for the persistent batched surface kernel.
 
-    def __init__(self, cpis, prec=FP32, device="cuda"):
+    cpis: list of dicts with n, surv_off, ref_off, out_off, tau0, n_tau, p0, n_dop
+    (offsets in complex elements into the pools). chunk: samples per work item (0 =
+    library default). The workspace holds the tables and stays owned by this object.
+    """
+
+    def __init__(self, cpis, prec=FP32, device="cuda", chunk: int = 0):
         lib = _lib.load()
         self.prec = _prec(prec)
         self.n_cpi = len(cpis)
@@ -156,24 +162,51 @@ class BatchPlan:
             for f in ("n", "surv_off", "ref_off", "out_off", "tau0", "n_tau", "p0", "n_dop"):
                 setattr(arr[k], f, int(c[f]))
         self._arr = arr
-        self.ws_bytes = int(lib.ndft_caf_batched_workspace(arr, self.n_cpi, self.prec))
+        self.ws_bytes = int(lib.ndft_caf_batched_workspace(arr, self.n_cpi, self.prec, int(chunk)))
+        if self.ws_bytes == 0:
+            raise RuntimeError("ndft_caf_batched_workspace: invalid batch")
         self.ws = _workspace(self.ws_bytes, device)
-        st = lib.ndft_caf_batched_prepare(arr, self.n_cpi, self.prec, _ptr(self.ws), self.ws_bytes)
+        self.batch = _lib.NdftBatch()
+        st = lib.ndft_caf_batched_prepare(arr, self.n_cpi, self.prec, int(chunk), _ptr(self.ws),
+                                          self.ws_bytes, ctypes.byref(self.batch))
         _lib.check(st, "ndft_caf_batched_prepare")
+
+    @property
+    def plan_name(self) -> str:
+        return plan_name(self.prec, self.batch.plan)
 
     def run(self, surv_pool, ref_pool, out_pool) -> torch.Tensor:
         lib = _lib.load()
         _check_c64(surv_pool, "surv_pool", 1)
         _check_c64(ref_pool, "ref_pool", 1)
         _check_c64(out_pool, "out_pool", 1)
-        st = lib.ndft_caf_batched(_ptr(surv_pool), _ptr(ref_pool), _ptr(out_pool), self.prec,
-                                  _ptr(self.ws), self.ws_bytes, _stream_handle())
+        st = lib.ndft_caf_batched(ctypes.byref(self.batch), _ptr(surv_pool), _ptr(ref_pool),
+                                  _ptr(out_pool), _ptr(self.ws), self.ws_bytes, _stream_handle())
         _lib.check(st, "ndft_caf_batched")
         return out_pool
 
 
 def caf_batched(plan: BatchPlan, surv_pool, ref_pool, out_pool):
     return plan.run(surv_pool, ref_pool, out_pool)
+
+
+def pack_batch(cpis):
+    """Concatenate per-CPI numpy arrays into pools; returns (surv_pool, ref_pool, descs,
+    out_len) with descs ready for BatchPlan."""
+    import numpy as np
+
+    descs = []
+    so = ro = oo = 0
+    for c in cpis:
+        n = int(c["n"])
+        descs.append(dict(n=n, surv_off=so, ref_off=ro, out_off=oo, tau0=int(c["tau0"]),
+                          n_tau=int(c["n_tau"]), p0=int(c["p0"]), n_dop=int(c["n_dop"])))
+        so += n
+        ro += n
+        oo += int(c["n_tau"]) * int(c["n_dop"])
+    surv = np.concatenate([np.asarray(c["s"], np.complex64) for c in cpis])
+    ref = np.concatenate([np.asarray(c["r"], np.complex64) for c in cpis])
+    return surv, ref, descs, oo
 
 
 def dbg_signs(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, twiddle: bool = True,

@@ -22,9 +22,9 @@ SIGNATURES = {
     "ndft_forward": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I32, _P, _SZ, _P]),
     "ndft_caf_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P, _SZ, _P]),
-    "ndft_caf_batched_workspace": (_SZ, [_P, _I32, _I32]),
-    "ndft_caf_batched_prepare": (_ST, [_P, _I32, _I32, _P, _SZ]),
-    "ndft_caf_batched": (_ST, [_P, _P, _P, _I32, _P, _SZ, _P]),
+    "ndft_caf_batched_workspace": (_SZ, [_P, _I32, _I32, _I32]),
+    "ndft_caf_batched_prepare": (_ST, [_P, _I32, _I32, _I32, _P, _SZ, _P]),
+    "ndft_caf_batched": (_ST, [_P, _P, _P, _P, _P, _SZ, _P]),
     "ndft_caf_backward_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf_backward": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P, _SZ, _P]),
     "ndft_dbg_signs": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P]),
@@ -44,6 +44,14 @@ class NdftCpi(ctypes.Structure):
 
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("n", "surv_off", "ref_off", "out_off", "tau0", "n_tau", "p0", "n_dop")]
+
+
+class NdftBatch(ctypes.Structure):
+    """Mirror of ndft_batch (host description of a prepared batch)."""
+
+    _fields_ = [(name, ctypes.c_int32) for name in
+                ("prec", "plan", "n_cpi", "n_items", "grid", "table_bytes", "max_red_blocks",
+                 "max_prep_blocks")] + [("tag", ctypes.c_uint64), ("ws_bytes", ctypes.c_uint64)]
 
 
 _lib = None

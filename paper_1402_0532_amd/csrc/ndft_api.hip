@@ -7,7 +7,9 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <chrono>
 #include <utility>
 #include <vector>
 
@@ -95,7 +97,8 @@ struct Plan {
     const char *name;
     int bt, lt, ks, nt;
     int static_lds;
-    const void *kfn[2]; // [PROD_LAG, PROD_IDENTITY]
+    const void *kfn[2];     // [PROD_LAG, PROD_IDENTITY]
+    const void *kfn_batched; // persistent lag-product kernel
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -111,6 +114,8 @@ Plan make_plan(const char *name)
     p.static_lds = 2 * (Cfg::STAGE_A_F4 + Cfg::STAGE_B_F4) * 16;
     p.kfn[0] = reinterpret_cast<const void *>(&contract_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
     p.kfn[1] = reinterpret_cast<const void *>(&contract_kernel<PREC, PROD_IDENTITY, WAVES_B, WAVES_L, WB, WL, KS>);
+    p.kfn_batched =
+        reinterpret_cast<const void *>(&contract_batched_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
     return p;
 }
 
@@ -146,9 +151,9 @@ void set_kernel_attributes()
 {
     for (int prec = 0; prec < 2; ++prec)
         for (const Plan &p : plans(prec))
-            for (int k = 0; k < 2; ++k) {
-                hipError_t e = hipFuncSetAttribute(p.kfn[k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   kMaxTableBytes);
+            for (int k = 0; k < 3; ++k) {
+                const void *fn = k < 2 ? p.kfn[k] : p.kfn_batched;
+                hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxTableBytes);
                 if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
             }
 }
@@ -378,6 +383,162 @@ AdjLaunch plan_adjoint(int64_t n, int64_t n_tau, int64_t p0, int64_t n_dop)
     return L;
 }
 
+// ------------------------------------------------------------------------------------
+// batched surfaces: geometry, tables and workspace layout
+// ------------------------------------------------------------------------------------
+struct BatchGeom {
+    int plan = 0;
+    int chunk = 0;
+    int table_bytes = 0;
+    int max_red_blocks = 1;
+    int max_prep_blocks = 1;
+    size_t off_params = 0, off_red = 0, off_outoff = 0, off_prep = 0, off_items = 0, total = 0;
+    std::vector<ContractParams> params;
+    std::vector<ReduceParams> red;
+    std::vector<long long> outoff;
+    std::vector<PrepDesc> prep;
+    std::vector<int4> items;
+};
+
+constexpr int kMaxBatch = 16384;
+constexpr int kDefaultChunk = 4096;
+
+bool cpi_ok(const ndft_cpi &c)
+{
+    return caf_args_ok(c.n, c.tau0, c.n_tau, c.n_dop) && c.surv_off >= 0 && c.ref_off >= 0 && c.out_off >= 0;
+}
+
+// Pick the plan (override or least summed cost), lay out the workspace and build the
+// tables; `base` is the workspace address (nullptr when only sizing).
+ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk, char *base, BatchGeom &G)
+{
+    if (!cpis || n_cpi < 1 || n_cpi > kMaxBatch || chunk < 0) return NDFT_E_INVAL;
+    for (int c = 0; c < n_cpi; ++c)
+        if (!cpi_ok(cpis[c])) return NDFT_E_INVAL;
+    const std::vector<Plan> &ps = plans(prec);
+    int pi;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        pi = g_plan_override[prec];
+    }
+    if (pi < 0 || pi >= (int)ps.size()) {
+        double best = -1.0;
+        pi = 0;
+        for (int k = 0; k < (int)ps.size(); ++k) {
+            double cost = 0.0;
+            for (int c = 0; c < n_cpi; ++c) {
+                int nb;
+                make_base_map(cpis[c].n, cpis[c].p0, cpis[c].n_dop, &nb);
+                double rows = (double)(cdiv(nb, ps[k].bt) * ps[k].bt);
+                double cols = (double)(cdiv(cpis[c].n_tau, ps[k].lt) * ps[k].lt);
+                cost += rows * cols * (double)cpis[c].n * (1.0 + 64.0 / ps[k].bt + 64.0 / ps[k].lt);
+            }
+            if (best < 0 || cost < best * 0.999) {
+                best = cost;
+                pi = k;
+            }
+        }
+    }
+    const Plan &P = ps[pi];
+    G.plan = pi;
+    G.chunk = (int)(cdiv(chunk > 0 ? chunk : kDefaultChunk, P.ks) * P.ks);
+    G.params.resize(n_cpi);
+    G.red.resize(n_cpi);
+    G.outoff.resize(n_cpi);
+    G.prep.resize(2 * n_cpi);
+    G.items.clear();
+    std::vector<long long> cost;
+    size_t off = 256; // header
+    G.off_params = off;
+    off = align256(off + sizeof(ContractParams) * n_cpi);
+    G.off_red = off;
+    off = align256(off + sizeof(ReduceParams) * n_cpi);
+    G.off_outoff = off;
+    off = align256(off + sizeof(long long) * n_cpi);
+    G.off_prep = off;
+    off = align256(off + sizeof(PrepDesc) * 2 * n_cpi);
+    int64_t total_items = 0;
+    for (int c = 0; c < n_cpi; ++c) {
+        const ndft_cpi &d = cpis[c];
+        int nb;
+        BaseMap bm = make_base_map(d.n, d.p0, d.n_dop, &nb);
+        int tiles_b = (int)cdiv(nb, P.bt), tiles_l = (int)cdiv(d.n_tau, P.lt);
+        int ks = (int)cdiv(d.n, G.chunk);
+        total_items += (int64_t)tiles_b * tiles_l * ks;
+    }
+    if (total_items > (int64_t)1 << 30) return NDFT_E_INVAL;
+    G.off_items = off;
+    off = align256(off + sizeof(int4) * (size_t)total_items);
+    for (int c = 0; c < n_cpi; ++c) {
+        const ndft_cpi &d = cpis[c];
+        ContractParams &C = G.params[c];
+        std::memset(&C, 0, sizeof(C));
+        int nb;
+        C.bm = make_base_map(d.n, d.p0, d.n_dop, &nb);
+        C.n = (int)d.n;
+        C.n_cols = (int)d.n_tau;
+        C.tau0 = (int)d.tau0;
+        C.n_bases = nb;
+        int tb = 0;
+        while ((1LL << (2 * tb)) < d.n) ++tb;
+        C.tb = tb;
+        C.n_coarse = (int)cdiv(d.n, 1LL << tb);
+        G.table_bytes = std::max(G.table_bytes, (int)((C.n_coarse + (1 << tb)) * sizeof(float2)));
+        C.kchunk = G.chunk;
+        C.ksplit = (int)cdiv(d.n, G.chunk);
+        C.tiles_b = (int)cdiv(nb, P.bt);
+        C.tiles_l = (int)cdiv(d.n_tau, P.lt);
+        C.n_bases_pad = C.tiles_b * P.bt;
+        C.n_cols_pad = C.tiles_l * P.lt;
+        size_t s4_off = off;
+        off = align256(off + sizeof(float4) * (size_t)(d.n + kTailPad));
+        size_t r4_off = off;
+        off = align256(off + sizeof(float4) * (size_t)(2 * d.n + kTailPad));
+        size_t part_off = off;
+        off = align256(off + sizeof(float4) * (size_t)C.ksplit * C.n_cols_pad * C.n_bases_pad);
+        C.s4 = base ? reinterpret_cast<const float4 *>(base + s4_off) : nullptr;
+        C.r4 = base ? reinterpret_cast<const float4 *>(base + r4_off) : nullptr;
+        C.partial = base ? reinterpret_cast<float4 *>(base + part_off) : nullptr;
+        ReduceParams &R = G.red[c];
+        std::memset(&R, 0, sizeof(R));
+        R.partial = C.partial;
+        R.ksplit = C.ksplit;
+        R.n_cols_pad = C.n_cols_pad;
+        R.n_bases_pad = C.n_bases_pad;
+        R.n_cols = C.n_cols;
+        R.n_bases = nb;
+        R.bm = C.bm;
+        R.n = C.n;
+        R.p0n = (int)mod_n(d.p0, d.n);
+        R.n_bins = (int)d.n_dop;
+        G.outoff[c] = (long long)d.out_off;
+        G.prep[2 * c] = PrepDesc{(long long)d.surv_off, base ? reinterpret_cast<float4 *>(base + s4_off) : nullptr,
+                                 (int)d.n, 0, (long long)(d.n + kTailPad)};
+        G.prep[2 * c + 1] = PrepDesc{(long long)d.ref_off, base ? reinterpret_cast<float4 *>(base + r4_off) : nullptr,
+                                     (int)d.n, (int)d.n, (long long)(2 * d.n + kTailPad)};
+        G.max_prep_blocks = std::max(G.max_prep_blocks, (int)std::min<int64_t>(cdiv(2 * d.n + kTailPad, 256), 1024));
+        G.max_red_blocks =
+            std::max(G.max_red_blocks, (int)std::min<int64_t>(cdiv((int64_t)C.n_cols * nb, 256), 4096));
+        for (int tl = 0; tl < C.tiles_l; ++tl)
+            for (int tbi = 0; tbi < C.tiles_b; ++tbi)
+                for (int kc = 0; kc < C.ksplit; ++kc) {
+                    G.items.push_back(make_int4(c, tbi, tl, kc));
+                    cost.push_back(std::min<long long>(G.chunk, d.n - (long long)kc * G.chunk));
+                }
+    }
+    // longest chunks first (stable, so equal items keep their surface order)
+    std::vector<size_t> order(G.items.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<int4> sorted(G.items.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = G.items[order[k]];
+    G.items.swap(sorted);
+    G.total = off;
+    return NDFT_OK;
+}
+
+std::atomic<unsigned long long> g_batch_seq{0};
+
 } // namespace
 
 // ======================================================================================
@@ -526,16 +687,109 @@ ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t
     return check_launch();
 }
 
-size_t ndft_caf_batched_workspace(const ndft_cpi *, int32_t, ndft_prec) { return 0; }
-
-ndft_status ndft_caf_batched_prepare(const ndft_cpi *, int32_t, ndft_prec, void *, size_t)
+size_t ndft_caf_batched_workspace(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec, int32_t chunk)
 {
-    return NDFT_E_UNSUPPORTED;
+    if (!prec_ok(prec)) return 0;
+    BatchGeom G;
+    if (batch_geometry(cpis, n_cpi, (int)prec, chunk, nullptr, G) != NDFT_OK) return 0;
+    return G.total;
 }
 
-ndft_status ndft_caf_batched(const ndft_c64 *, const ndft_c64 *, ndft_c64 *, ndft_prec, void *, size_t, void *)
+ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_prec prec, int32_t chunk, void *ws,
+                                     size_t ws_bytes, ndft_batch *batch)
 {
-    return NDFT_E_UNSUPPORTED;
+    if (!batch) return NDFT_E_INVAL;
+    if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
+    if (!prec_ok(prec)) return NDFT_E_INVAL;
+    BatchGeom G;
+    ndft_status st = batch_geometry(cpis, n_cpi, (int)prec, chunk, static_cast<char *>(ws), G);
+    if (st != NDFT_OK) return st;
+    if ((st = ws_ok(ws, ws_bytes, G.total)) != NDFT_OK) return st;
+    std::call_once(g_attr_once, set_kernel_attributes);
+    if (g_attr_err != hipSuccess) return NDFT_E_HIP;
+    const Plan &P = plans((int)prec)[G.plan];
+    unsigned long long tag = (++g_batch_seq) ^
+        ((unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() << 20);
+    // host image of the tables (header .. items), copied in one blocking transfer
+    std::vector<char> img(G.off_items + sizeof(int4) * G.items.size(), 0);
+    BatchHeader hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.counter = 0;
+    hdr.n_items = (int)G.items.size();
+    hdr.n_cpi = n_cpi;
+    hdr.plan_id = (int)prec * 100 + G.plan;
+    hdr.tag = tag;
+    std::memcpy(img.data(), &hdr, sizeof(hdr));
+    std::memcpy(img.data() + G.off_params, G.params.data(), sizeof(ContractParams) * n_cpi);
+    std::memcpy(img.data() + G.off_red, G.red.data(), sizeof(ReduceParams) * n_cpi);
+    std::memcpy(img.data() + G.off_outoff, G.outoff.data(), sizeof(long long) * n_cpi);
+    std::memcpy(img.data() + G.off_prep, G.prep.data(), sizeof(PrepDesc) * 2 * n_cpi);
+    std::memcpy(img.data() + G.off_items, G.items.data(), sizeof(int4) * G.items.size());
+    if (hipMemcpy(ws, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return NDFT_E_HIP;
+    std::memset(batch, 0, sizeof(*batch));
+    batch->prec = (int32_t)prec;
+    batch->plan = G.plan;
+    batch->n_cpi = n_cpi;
+    batch->n_items = (int32_t)G.items.size();
+    batch->grid = device_cu_count();
+    batch->table_bytes = G.table_bytes;
+    batch->max_red_blocks = G.max_red_blocks;
+    batch->max_prep_blocks = G.max_prep_blocks;
+    batch->tag = tag;
+    batch->ws_bytes = G.total;
+    (void)P;
+    return NDFT_OK;
+}
+
+ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool, const ndft_c64 *ref_pool,
+                             ndft_c64 *out_pool, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!batch || !surv_pool || !ref_pool || !out_pool) return NDFT_E_INVAL;
+    if (!aligned(surv_pool, 8) || !aligned(ref_pool, 8) || !aligned(out_pool, 8)) return NDFT_E_INVAL;
+    if (!prec_ok((ndft_prec)batch->prec)) return NDFT_E_INVAL;
+    if (batch->plan < 0 || batch->plan >= (int)plans(batch->prec).size()) return NDFT_E_INVAL;
+    if (batch->n_cpi < 1 || batch->n_cpi > kMaxBatch || batch->grid < 1 || batch->table_bytes < 0 ||
+        batch->table_bytes > kMaxTableBytes || batch->max_red_blocks < 1 || batch->max_prep_blocks < 1)
+        return NDFT_E_INVAL;
+    ndft_status st = ws_ok(ws, ws_bytes, (size_t)batch->ws_bytes);
+    if (st != NDFT_OK) return st;
+    std::call_once(g_attr_once, set_kernel_attributes);
+    if (g_attr_err != hipSuccess) return NDFT_E_HIP;
+    // offsets of the tables: recomputed from the header layout rules (same order as prepare)
+    char *base = static_cast<char *>(ws);
+    BatchHeader *hdr = reinterpret_cast<BatchHeader *>(base);
+    size_t off = 256;
+    const ContractParams *params = reinterpret_cast<const ContractParams *>(base + off);
+    off = align256(off + sizeof(ContractParams) * batch->n_cpi);
+    const ReduceParams *red = reinterpret_cast<const ReduceParams *>(base + off);
+    off = align256(off + sizeof(ReduceParams) * batch->n_cpi);
+    const long long *outoff = reinterpret_cast<const long long *>(base + off);
+    off = align256(off + sizeof(long long) * batch->n_cpi);
+    const PrepDesc *prep = reinterpret_cast<const PrepDesc *>(base + off);
+    off = align256(off + sizeof(PrepDesc) * 2 * batch->n_cpi);
+    const int4 *items = reinterpret_cast<const int4 *>(base + off);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long tag = batch->tag;
+    int plan_id = batch->prec * 100 + batch->plan;
+    const Plan &P = plans(batch->prec)[batch->plan];
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, hdr);
+    if ((st = check_launch()) != NDFT_OK) return st;
+    hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)batch->max_prep_blocks, (unsigned)(2 * batch->n_cpi)),
+                       dim3(256), 0, s, hdr, prep, reinterpret_cast<const float2 *>(surv_pool),
+                       reinterpret_cast<const float2 *>(ref_pool), tag);
+    if ((st = check_launch()) != NDFT_OK) return st;
+    {
+        void *args[] = {&hdr, &params, &items, &tag, &plan_id};
+        ProfScope prof(s);
+        hipError_t e = hipLaunchKernel(P.kfn_batched, dim3((unsigned)batch->grid), dim3((unsigned)P.nt), args,
+                                       (size_t)batch->table_bytes, s);
+        prof.stop();
+        if (e != hipSuccess) return NDFT_E_HIP;
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
+    hipLaunchKernelGGL(reduce_batched_kernel, dim3((unsigned)batch->max_red_blocks, (unsigned)batch->n_cpi), dim3(256),
+                       0, s, hdr, red, outoff, reinterpret_cast<float2 *>(out_pool), tag);
+    return check_launch();
 }
 
 int32_t ndft_plan_count(ndft_prec prec)

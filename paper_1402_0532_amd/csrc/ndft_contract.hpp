@@ -135,16 +135,19 @@ __device__ __forceinline__ void mark_read(const float4 &v)
 //   B1 = [zr_hi_i, zr_hi_i+1, zr_lo_i, zr_lo_i+1, sr_i, sr_i+1, sr_i, sr_i+1]
 // so A1.B1 = sum over the pair of Sc z_r + C sigma_r (U); A2 = (St, T) and B2 = (z_i,
 // sigma_i) give X, Y, V the same way.
+// One work item: the partial sums of BT bases x LT columns over sample chunk kc.
+// LDS: two stage buffers for each operand and the twiddle table (caller-provided).
 template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
-__global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(ContractParams P)
+__device__ __forceinline__ void contract_tile(const ContractParams &P, const int kc, const int tile_b,
+                                              const int tile_l,
+                                              float4 (*bufA)[ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>::STAGE_A_F4],
+                                              float4 (*bufB)[ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>::STAGE_B_F4],
+                                              float2 *tables)
 {
     using Cfg = ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>;
     constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT;
     constexpr int TWI = Cfg::TW_ITERS, LGI = Cfg::LG_ITERS;
 
-    __shared__ float4 bufA[2][Cfg::STAGE_A_F4];
-    __shared__ float4 bufB[2][Cfg::STAGE_B_F4];
-    extern __shared__ float2 tables[];
     float2 *coarse = tables;
     float2 *fine = tables + P.n_coarse;
 
@@ -156,11 +159,6 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
     const int h = lane >> 5;
     const int l32 = lane & 31;
 
-    int bid = blockIdx.x;
-    const int kc = bid % P.ksplit;
-    bid /= P.ksplit;
-    const int tile_b = bid % P.tiles_b;
-    const int tile_l = bid / P.tiles_b;
     const int b0 = tile_b * BT;
     const int c0 = tile_l * LT;
     const int n = P.n;
@@ -433,6 +431,63 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(Con
         }
 }
 
+// One tile per work-group: blockIdx.x = (tile_l * tiles_b + tile_b) * ksplit + kc.
+template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
+__global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_kernel(ContractParams P)
+{
+    using Cfg = ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>;
+    __shared__ float4 bufA[2][Cfg::STAGE_A_F4];
+    __shared__ float4 bufB[2][Cfg::STAGE_B_F4];
+    extern __shared__ float2 tables[];
+    int bid = blockIdx.x;
+    const int kc = bid % P.ksplit;
+    bid /= P.ksplit;
+    contract_tile<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, bufB,
+                                                            tables);
+}
+
+// Header at the start of a batched workspace (written by the prepare call).
+struct BatchHeader {
+    int counter;      // work-item queue, reset to 0 before each run
+    int n_items;
+    int n_cpi;
+    int plan_id;
+    unsigned long long tag; // identifies the prepare call that wrote the tables
+};
+
+// Persistent form for a batch of surfaces: each work-group takes items (cpi, tile_b,
+// tile_l, kc) from an atomic counter until the list is exhausted. Items are ordered by
+// decreasing sample count so the longest chunks start first. Every work-group leaves
+// the loop once the counter passes n_items; a header written by another prepare call
+// (tag or plan mismatch) makes the kernel do nothing.
+template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
+__global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_batched_kernel(
+    BatchHeader *hdr, const ContractParams *params, const int4 *items, unsigned long long tag, int plan_id)
+{
+    using Cfg = ContractCfg<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>;
+    __shared__ float4 bufA[2][Cfg::STAGE_A_F4];
+    __shared__ float4 bufB[2][Cfg::STAGE_B_F4];
+    __shared__ int s_item;
+    extern __shared__ float2 tables[];
+    if (hdr->tag != tag || hdr->plan_id != plan_id) return;
+    const int n_items = hdr->n_items;
+    for (;;) {
+        __syncthreads(); // every thread has read s_item and finished with the LDS buffers
+        if (threadIdx.x == 0) s_item = atomicAdd(&hdr->counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item); // uniform: scalar loads below
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const ContractParams P = params[__builtin_amdgcn_readfirstlane(w.x)];
+        contract_tile<PREC, PROD, WAVES_B, WAVES_L, WB, WL, KS>(P, w.w, w.y, w.z, bufA, bufB, tables);
+    }
+}
+
+__global__ void batch_reset_kernel(BatchHeader *hdr)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0;
+}
+
 struct ReduceParams {
     const float4 *partial;
     int ksplit, n_cols_pad, n_bases_pad;
@@ -443,9 +498,8 @@ struct ReduceParams {
 };
 
 // Ordered sum of the chunk partials, then the +b / -b assembly into the output rows.
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceParams R)
+__device__ __forceinline__ void reduce_element(const ReduceParams &R, long long idx)
 {
-    long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     long long total = (long long)R.n_cols * R.n_bases;
     if (idx >= total) return;
     int bi = (int)(idx % R.n_bases);
@@ -471,6 +525,46 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceParams R)
         int q2 = pm - R.p0n;
         q2 = q2 < 0 ? q2 + n : q2;
         if (q2 < R.n_bins) row[q2] = make_float2(a.x + a.y, a.z - a.w);
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceParams R)
+{
+    reduce_element(R, (long long)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Batched: blockIdx.y selects the surface; its rows start at out_off[y] in out_pool.
+__global__ __launch_bounds__(256) void reduce_batched_kernel(const BatchHeader *hdr, const ReduceParams *rp,
+                                                             const long long *out_off, float2 *out_pool,
+                                                             unsigned long long tag)
+{
+    if (hdr->tag != tag) return;
+    ReduceParams R = rp[blockIdx.y];
+    R.out = out_pool + out_off[blockIdx.y];
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < (long long)R.n_cols * R.n_bases;
+         idx += (long long)gridDim.x * 256)
+        reduce_element(R, idx);
+}
+
+// Batched sign prep: blockIdx.y selects the surface; x and out rows as sign_prep_kernel.
+struct PrepDesc {
+    long long src_off; // offset of the input row in its pool (complex elements)
+    float4 *out;
+    int n, lead;
+    long long ostride;
+};
+
+__global__ __launch_bounds__(256) void prep_batched_kernel(const BatchHeader *hdr, const PrepDesc *pd,
+                                                           const float2 *pool_s, const float2 *pool_r,
+                                                           unsigned long long tag)
+{
+    if (hdr->tag != tag) return;
+    const PrepDesc D = pd[blockIdx.y];
+    const float2 *x = (blockIdx.y & 1) ? pool_r : pool_s; // even: surveillance, odd: reference
+    x += D.src_off;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < D.ostride; k += (long long)gridDim.x * 256) {
+        long long j = k - D.lead;
+        D.out[k] = (j >= 0 && j < D.n) ? with_signs(x[j]) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 

@@ -130,10 +130,16 @@ def test_caf_zero_surveillance(nd, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_caf_negation_invariant(nd, prec):
+    # A(-s) = -A(s) (every real operator is odd in each argument). The FP32 path is
+    # exactly odd; the BF16 matrix-core dot product rounds asymmetrically in its last
+    # bits, so that form is held to its tolerance.
     s, r = synth.random_pair(600, seed=5)
     A = nd.caf(dev(s), dev(r), 0, 20, -10, 20, prec=prec).cpu().numpy()
     An = nd.caf(dev(-s), dev(r), 0, 20, -10, 20, prec=prec).cpu().numpy()
-    np.testing.assert_array_equal(An, -A)
+    if prec == 0:
+        np.testing.assert_array_equal(An, -A)
+    else:
+        np.testing.assert_allclose(An, -A, rtol=0, atol=1e-6 * np.abs(A).max())
 
 
 @pytest.fixture(scope="module")

@@ -55,7 +55,11 @@ typedef enum {
  *   NDFT_FP32   FP32 operands on FP32 matrix cores, FP32 accumulation.
  *   NDFT_BF16X2 data split into BF16 hi + lo (|v - hi - lo| <= 2^-18 |v|), exact BF16
  *               signs, FP32 accumulation.
- *   NDFT_FP8    reserved (returns NDFT_E_UNSUPPORTED).                               */
+ *   NDFT_FP8    data split into four e4m3 terms (v = t0 + t1/16 + t2/256 + t3/4096 up to
+ *               ~2^-16 |v|), exact e4m3 signs, block-scaled FP8 matrix cores, FP32
+ *               accumulation. Input components must stay below 64 in magnitude; n is
+ *               limited by LDS (NDFT_E_UNSUPPORTED above 2^20 for some plans). The
+ *               adjoint has no FP8 form (NDFT_E_UNSUPPORTED).                         */
 typedef enum { NDFT_FP32 = 0, NDFT_BF16X2 = 1, NDFT_FP8 = 2 } ndft_prec;
 
 /* Maximum transform length. */

@@ -128,32 +128,41 @@ const std::vector<Plan> &plans(int prec)
         make_plan<PREC_FP32, 4, 2, 2, 1, 8>("fp32_b256_l64_w8_ks8"),
         make_plan<PREC_FP32, 3, 4, 1, 1, 8>("fp32_b96_l128_w12_ks8"),
     };
+    static const std::vector<Plan> fp8 = {
+        make_plan<PREC_FP8, 2, 4, 2, 1, 16>("fp8_b128_l128_w8_ks16"),
+        make_plan<PREC_FP8, 3, 4, 1, 1, 16>("fp8_b96_l128_w12_ks16"),
+    };
     static const std::vector<Plan> bf16 = {
         make_plan<PREC_BF16X2, 2, 4, 2, 1, 8>("bf16x2_b128_l128_w8_ks8"),
         make_plan<PREC_BF16X2, 1, 8, 2, 1, 8>("bf16x2_b64_l256_w8_ks8"),
         make_plan<PREC_BF16X2, 4, 2, 2, 1, 8>("bf16x2_b256_l64_w8_ks8"),
         make_plan<PREC_BF16X2, 3, 4, 1, 1, 8>("bf16x2_b96_l128_w12_ks8"),
     };
-    return prec == NDFT_BF16X2 ? bf16 : f32;
+    return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
 
 std::mutex g_plan_mu;
-int g_plan_override[2] = {-1, -1};
-int g_ksplit_override[2] = {0, 0};
+int g_plan_override[3] = {-1, -1, -1};
+int g_ksplit_override[3] = {0, 0, 0};
 
 // Largest twiddle-table size (N = 2^24: 4096 coarse + 4096 fine entries).
 constexpr int kMaxTableBytes = 8192 * 8;
+// LDS per work-group on gfx950.
+constexpr int kLdsBytes = 160 * 1024;
+
+// Dynamic LDS a plan can take next to its static stage buffers.
+int plan_max_dynamic(const Plan &p) { return std::min(kMaxTableBytes, kLdsBytes - p.static_lds - 256); }
 
 std::once_flag g_attr_once;
 hipError_t g_attr_err = hipSuccess;
 
 void set_kernel_attributes()
 {
-    for (int prec = 0; prec < 2; ++prec)
+    for (int prec = 0; prec < 3; ++prec)
         for (const Plan &p : plans(prec))
             for (int k = 0; k < 3; ++k) {
                 const void *fn = k < 2 ? p.kfn[k] : p.kfn_batched;
-                hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxTableBytes);
+                hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, plan_max_dynamic(p));
                 if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
             }
 }
@@ -319,6 +328,7 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     P.partial = partial;
     void *args[] = {&P};
     size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
+    if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED; // FP8 stages leave less LDS
     dim3 grid((unsigned)((int64_t)L.tiles_b * L.tiles_l * L.ksplit));
     dim3 block((unsigned)L.plan->nt);
     ProfScope prof(stream);
@@ -350,7 +360,15 @@ ndft_status launch_reduce(const Launch &L, const float4 *partial, int64_t n, int
     return check_launch();
 }
 
-bool prec_ok(ndft_prec p) { return p == NDFT_FP32 || p == NDFT_BF16X2; }
+bool prec_ok(ndft_prec p) { return p == NDFT_FP32 || p == NDFT_BF16X2 || p == NDFT_FP8; }
+
+// Table bytes for length n (coarse + fine two-level twiddle table).
+int table_bytes_for(int64_t n)
+{
+    int tb = 0;
+    while ((1LL << (2 * tb)) < n) ++tb;
+    return (int)((cdiv(n, 1LL << tb) + (1LL << tb)) * sizeof(float2));
+}
 
 bool caf_args_ok(int64_t n, int64_t tau0, int64_t n_tau, int64_t n_dop)
 {
@@ -572,7 +590,6 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     if (n < 1 || n > NDFT_MAX_N || batch < 0 || k_count < 1 || k_count > n) return NDFT_E_INVAL;
     if (batch > 0 && (!x || !X || !aligned(x, 8) || !aligned(X, 8))) return NDFT_E_INVAL;
     if (batch * n > ((int64_t)1 << 40)) return NDFT_E_INVAL;
-    if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     if (batch == 0) return NDFT_OK;
     if (batch > INT32_MAX / 2) return NDFT_E_INVAL;
@@ -601,7 +618,6 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
 {
     if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
     if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
-    if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     Launch L = plan_launch((int)prec, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
@@ -699,7 +715,6 @@ ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_p
                                      size_t ws_bytes, ndft_batch *batch)
 {
     if (!batch) return NDFT_E_INVAL;
-    if (prec == NDFT_FP8) return NDFT_E_UNSUPPORTED;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     BatchGeom G;
     ndft_status st = batch_geometry(cpis, n_cpi, (int)prec, chunk, static_cast<char *>(ws), G);
@@ -708,6 +723,7 @@ ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_p
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
     const Plan &P = plans((int)prec)[G.plan];
+    if (G.table_bytes > plan_max_dynamic(P)) return NDFT_E_UNSUPPORTED;
     unsigned long long tag = (++g_batch_seq) ^
         ((unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() << 20);
     // host image of the tables (header .. items), copied in one blocking transfer
@@ -749,7 +765,8 @@ ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool,
     if (!prec_ok((ndft_prec)batch->prec)) return NDFT_E_INVAL;
     if (batch->plan < 0 || batch->plan >= (int)plans(batch->prec).size()) return NDFT_E_INVAL;
     if (batch->n_cpi < 1 || batch->n_cpi > kMaxBatch || batch->grid < 1 || batch->table_bytes < 0 ||
-        batch->table_bytes > kMaxTableBytes || batch->max_red_blocks < 1 || batch->max_prep_blocks < 1)
+        batch->table_bytes > plan_max_dynamic(plans(batch->prec)[batch->plan]) || batch->max_red_blocks < 1 ||
+        batch->max_prep_blocks < 1)
         return NDFT_E_INVAL;
     ndft_status st = ws_ok(ws, ws_bytes, (size_t)batch->ws_bytes);
     if (st != NDFT_OK) return st;

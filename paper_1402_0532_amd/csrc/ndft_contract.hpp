@@ -31,7 +31,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
-enum { PREC_FP32 = 0, PREC_BF16X2 = 1 };
+enum { PREC_FP32 = 0, PREC_BF16X2 = 1, PREC_FP8 = 2 };
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 enum { PROD_LAG = 0, PROD_IDENTITY = 1 };
 
 // Ascending runs of base bins: index idx in [off[k], off[k+1]) is base start[k] + idx - off[k].
@@ -100,6 +101,28 @@ __device__ __forceinline__ void split_pair(float a, float b, uint32_t &hi, uint3
     lo = __builtin_bit_cast(uint32_t, l);
 }
 
+// FP8 (e4m3) form: a value is carried as four e4m3 terms, v = t0 + t1/16 + t2/256 +
+// t3/4096 + O(2^-16 |v|) (each term rounds the remaining residual, scaled by 16^j, to
+// nearest). For two samples with signs (g1, g2) and values (v1, v2) this returns, per
+// term j, the dword of bytes [g1, t_j(v1), g2, t_j(v2)] (SIGN_FIRST, twiddle side) or
+// [t_j(v1), g1, t_j(v2), g2] (lag side), so that byte k of the two sides pairs a sign
+// with a value; the signs are exact in e4m3.
+template <bool SIGN_FIRST>
+__device__ __forceinline__ void fp8_terms_pair(float g1, float v1, float g2, float v2, uint32_t d[4])
+{
+    const int sg = __builtin_amdgcn_cvt_pk_fp8_f32(g1, g2, 0, false);
+    float r1 = v1, r2 = v2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int tv = __builtin_amdgcn_cvt_pk_fp8_f32(r1, r2, 0, false);
+        d[j] = __builtin_amdgcn_perm((uint32_t)tv, (uint32_t)sg, SIGN_FIRST ? 0x05010400u : 0x01050004u);
+        if (j < 3) {
+            r1 = (r1 - __builtin_amdgcn_cvt_f32_fp8(tv, 0)) * 16.0f;
+            r2 = (r2 - __builtin_amdgcn_cvt_f32_fp8(tv, 1)) * 16.0f;
+        }
+    }
+}
+
 template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
 struct ContractCfg {
     static constexpr int NT = 64 * WAVES_B * WAVES_L;
@@ -116,6 +139,7 @@ struct ContractCfg {
     static constexpr int TW_ITERS = (TW_UNITS + NT - 1) / NT;
     static constexpr int LG_ITERS = (LG_UNITS + NT - 1) / NT;
     static_assert(PREC != PREC_BF16X2 || KS % 4 == 0, "BF16 stage is whole 4-sample groups");
+    static_assert(PREC != PREC_FP8 || KS % 16 == 0, "FP8 stage is whole 16-sample groups");
     static_assert(KS % 2 == 0, "pairs of samples");
     static_assert(KS <= kTailPad, "the last stage reads at most KS - 1 samples past the record");
 };
@@ -246,6 +270,18 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
                     A[((s2 * 2 + 0) * 2 + 1) * BT + row] = w2.x;
                     A[((s2 * 2 + 1) * 2 + 0) * BT + row] = (float)g2.t;
                     A[((s2 * 2 + 1) * 2 + 1) * BT + row] = w2.y;
+                } else if (PREC == PREC_FP8) {
+                    // block (16-sample group g, type, term j): 8 dwords per row, dword pair%8
+                    uint32_t *A = reinterpret_cast<uint32_t *>(bufA[buf]);
+                    const int g = pair >> 3, dw = pair & 7;
+                    uint32_t dc[4], dt[4];
+                    fp8_terms_pair<true>((float)g1.c, w1.x, (float)g2.c, w2.x, dc);
+                    fp8_terms_pair<true>((float)g1.t, w1.y, (float)g2.t, w2.y, dt);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        A[((((g * 2 + 0) * 4 + j) * BT) + row) * 8 + dw] = dc[j];
+                        A[((((g * 2 + 1) * 4 + j) * BT) + row) * 8 + dw] = dt[j];
+                    }
                 } else {
                     uint4 *A = reinterpret_cast<uint4 *>(bufA[buf]);
                     int g = pair >> 1, hh = pair & 1;
@@ -295,6 +331,17 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
                     B[((s2 * 2 + 0) * 2 + 1) * LT + col] = z2.sr;
                     B[((s2 * 2 + 1) * 2 + 0) * LT + col] = z2.zi;
                     B[((s2 * 2 + 1) * 2 + 1) * LT + col] = z2.si;
+                } else if (PREC == PREC_FP8) {
+                    uint32_t *B = reinterpret_cast<uint32_t *>(bufB[buf]);
+                    const int g = pair >> 3, dw = pair & 7;
+                    uint32_t dr[4], di[4];
+                    fp8_terms_pair<false>(z1.sr, z1.zr, z2.sr, z2.zr, dr);
+                    fp8_terms_pair<false>(z1.si, z1.zi, z2.si, z2.zi, di);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        B[((((g * 2 + 0) * 4 + j) * LT) + col) * 8 + dw] = dr[j];
+                        B[((((g * 2 + 1) * 4 + j) * LT) + col) * 8 + dw] = di[j];
+                    }
                 } else {
                     uint4 *B = reinterpret_cast<uint4 *>(bufB[buf]);
                     int g = pair >> 1, hh = pair & 1;
@@ -339,6 +386,51 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
                             for (int tb = 0; tb < 2; ++tb)
                                 acc[i][j][ta * 2 + tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                                     a[i][ta], b[j][tb], acc[i][j][ta * 2 + tb], 0, 0, 0);
+            }
+        } else if (PREC == PREC_FP8) {
+            // The f8f6f4 instruction scales the first 16 bytes of every lane with the E8M0
+            // value of the lane in half 0 and the last 16 bytes with that of half 1. Lane
+            // half h takes samples 8h .. 8h+7 of the 16-sample group: term j0 = 2 mm in
+            // bytes 0-15, term j1 = 2 mm + 1 in bytes 16-31; scale 2^(-4 j) restores the term
+            // weight on the twiddle side (the signs themselves are unscaled operands).
+            const uint4 *A = reinterpret_cast<const uint4 *>(bufA[buf]);
+            const uint4 *B = reinterpret_cast<const uint4 *>(bufB[buf]);
+#pragma unroll
+            for (int g = 0; g < KS / 16; ++g) {
+#pragma unroll
+                for (int mm = 0; mm < 2; ++mm) {
+                    const int j0 = 2 * mm, j1 = 2 * mm + 1;
+                    const int scale_a = 127 - 4 * (2 * mm + h);
+                    i32x8 a[WB][2], b[WL][2];
+#pragma unroll
+                    for (int i = 0; i < WB; ++i)
+#pragma unroll
+                        for (int tt = 0; tt < 2; ++tt) {
+                            uint4 lo = A[(((g * 2 + tt) * 4 + j0) * BT + rowA + 32 * i) * 2 + h];
+                            uint4 hi = A[(((g * 2 + tt) * 4 + j1) * BT + rowA + 32 * i) * 2 + h];
+                            a[i][tt] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                                             (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                        }
+#pragma unroll
+                    for (int jj = 0; jj < WL; ++jj)
+#pragma unroll
+                        for (int tt = 0; tt < 2; ++tt) {
+                            uint4 lo = B[(((g * 2 + tt) * 4 + j0) * LT + colB + 32 * jj) * 2 + h];
+                            uint4 hi = B[(((g * 2 + tt) * 4 + j1) * LT + colB + 32 * jj) * 2 + h];
+                            b[jj][tt] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                                              (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                        }
+#pragma unroll
+                    for (int i = 0; i < WB; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < WL; ++jj)
+#pragma unroll
+                            for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+                                for (int tb = 0; tb < 2; ++tb)
+                                    acc[i][jj][ta * 2 + tb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                        a[i][ta], b[jj][tb], acc[i][jj][ta * 2 + tb], 0, 0, 0, scale_a, 0, 127);
+                }
             }
         } else {
             const uint4 *A = reinterpret_cast<const uint4 *>(bufA[buf]);

@@ -66,7 +66,10 @@ def test_caf_rejects_null_misaligned_and_precision():
     assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, None, 0, p, 4096, None) == INVAL
     assert lib.ndft_caf(odd, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == INVAL
     assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, p, 7, p, 4096, None) == INVAL
-    assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, p, 2, p, 4096, None) == UNSUPPORTED
+    # FP8 is a supported form for the surface (here the workspace is too small) ...
+    assert lib.ndft_caf(p, p, 16, 0, 4, 0, 4, p, 2, None, 0, None) == WORKSPACE
+    # ... but the adjoint has no FP8 form
+    assert lib.ndft_caf_backward(p, p, 16, 0, 4, 0, 4, p, p, None, 2, p, 4096, None) == UNSUPPORTED
 
 
 def test_caf_rejects_small_or_misaligned_workspace():
@@ -88,7 +91,7 @@ def test_forward_rejects_bad_args():
     assert lib.ndft_forward(p, p, -1, 8, 0, 8, 0, p, 4096, None) == INVAL
     assert lib.ndft_forward(None, p, 2, 8, 0, 8, 0, p, 4096, None) == INVAL
     assert lib.ndft_forward(p, p, 0, 8, 0, 8, 0, None, 0, None) == 0  # empty batch: no-op
-    assert lib.ndft_forward(p, p, 2, 8, 0, 8, 2, p, 4096, None) == UNSUPPORTED
+    assert lib.ndft_forward(p, p, 2, 8, 0, 8, 9, p, 4096, None) == INVAL
 
 
 def test_workspace_query_is_consistent():

@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0}  # dense MFMA peaks, MI355X spec sheet
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "fp8": 5000.0}  # dense MFMA peaks, MI355X
 KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_contract.hpp",
                   "paper_1402_0532_amd/csrc/ndft_device.hpp"]
 TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
@@ -55,13 +55,101 @@ def load_traffic(form: str):
     return float(rec[key]) if key in rec else None
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_batched(nd, tune, synth, torch, args):
+    """64 CPIs of uneven length in one persistent launch, replayed from a hipGraph."""
+    import numpy as np
+
+    cpis = synth.config4()
+    surv, ref, descs, olen = nd.pack_batch(cpis)
+    cells = sum(c["n_tau"] * c["n_dop"] for c in cpis)
+    flops = sum(16.0 * c["n"] * c["n_tau"] * c["n_dop"] for c in cpis)
+    s_pool = torch.from_numpy(surv).cuda()
+    r_pool = torch.from_numpy(ref).cuda()
+    out = torch.empty(olen, dtype=torch.complex64, device="cuda")
+    res = {"workload": "64 CPIs, N log-uniform in [1024, 32768], 128-512 delays, Doppler +-N/16",
+           "cells": cells, "algorithmic_flops": flops}
+    for form in ("fp32", "bf16x2"):
+        prec = nd.PRECISIONS[form]
+        if args.no_autotune:
+            bp, rec = nd.BatchPlan(descs, prec), None
+        else:
+            bp, rec = tune.autotune_batch(descs, s_pool, r_pool, out, prec)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            bp.run(s_pool, r_pool, out)
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=st):
+            bp.run(s_pool, r_pool, out)
+        g.replay()
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 4)
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[form] = {"ms_per_batch": ms, "cells_per_s": cells / (ms * 1e-3),
+                     "algorithmic_tflops": flops / (ms * 1e-3) / 1e12, "plan": bp.plan_name,
+                     "items": int(bp.batch.n_items),
+                     "autotune": rec}
+        del g, bp
+    res["speedup_bf16x2_vs_fp32"] = res["fp32"]["ms_per_batch"] / res["bf16x2"]["ms_per_batch"]
+    tune.reset()
+    return res
+
+
+def bench_adjoint(nd, synth, torch, args):
+    """Hand adjoint of the N=8192, 256 x 256 surface (loss sum w |A|^2)."""
+    c = synth.config5()
+    s = torch.from_numpy(c["s"]).cuda()
+    r = torch.from_numpy(c["r"]).cuda()
+    w = torch.from_numpy(c["w"].astype("float32")).cuda()
+    a = (c["tau0"], c["n_tau"], c["p0"], c["n_dop"])
+    res = {"workload": "N=8192, 256 delays x 256 Doppler bins, loss sum w|A|^2"}
+    for form in ("fp32", "bf16x2"):
+        prec = nd.PRECISIONS[form]
+        A = nd.caf(s, r, *a, prec)
+        G = (2.0 * w * A).contiguous()
+        nd.caf_backward(s, r, *a, G, prec)
+        torch.cuda.synchronize()
+        reps = max(5, args.steps)
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            nd.caf_backward(s, r, *a, G, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / reps
+        e0.record()
+        for _ in range(reps):
+            nd.caf(s, r, *a, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_f = e0.elapsed_time(e1) / reps
+        res[form] = {"backward_ms": ms_b, "forward_ms": ms_f}
+    res["speedup_bf16x2_vs_fp32_backward"] = res["fp32"]["backward_ms"] / res["bf16x2"]["backward_ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2"])
-    ap.add_argument("--forms", default="fp32,bf16x2", help="forms to time (comma list)")
+    ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2", "fp8"])
+    ap.add_argument("--forms", default="fp32,bf16x2,fp8", help="forms to time (comma list)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in plan choice")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64 CPIs) and adjoint (N=8192) sections")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -80,6 +168,7 @@ def main():
 
     import paper_1402_0532_amd as nd
     import synth
+    from paper_1402_0532_amd import tune
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -95,8 +184,11 @@ def main():
         forms.append(args.form)
     results = {}
     outs = {}
+    tuned = {}
     for form in forms:
         prec = nd.PRECISIONS[form]
+        if not args.no_autotune:
+            tuned[form] = tune.autotune_caf(s, r, tau0, n_tau, p0, n_dop, prec, use_cache=False)
         ws = torch.empty(nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, prec),
                          dtype=torch.uint8, device=dev)
         out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=dev)
@@ -138,9 +230,8 @@ def main():
             "plan": nd.plan_name(prec, plan),
             "ksplit": ks,
         }
-        if form == "bf16x2":
-            # the split form issues two MFMA passes per algorithmic product
-            results[form]["contract_tflops_issued"] = 2 * achieved
+        if form in tuned:
+            results[form]["autotune"] = {k: tuned[form][k] for k in ("name", "ksplit", "ms", "tried")}
         outs[form] = out.cpu().numpy()
         del ws
 
@@ -182,6 +273,11 @@ def main():
             results[form]["max_l1_rel_err_vs_oracle"] = float(err.max())
             results[form]["err_rows_checked"] = int(len(allrows))
 
+    extras = {}
+    if not args.no_extras:
+        extras["batched"] = bench_batched(nd, tune, synth, torch, args)
+        extras["adjoint"] = bench_adjoint(nd, synth, torch, args)
+
     main_res = results[args.form]
     line = {
         "metric": "ambiguity cells/s (tau x Doppler) at N=65536",
@@ -208,6 +304,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "forms": results,
+        **extras,
         "kernel_source_sha256_16": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)

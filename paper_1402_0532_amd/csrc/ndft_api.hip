@@ -17,6 +17,7 @@
 #include "ndft_backward.hpp"
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
+#include "ndft_surface_bf16.hpp"
 
 using namespace ndft;
 
@@ -96,9 +97,12 @@ BaseMap make_base_map(int64_t n, int64_t p0, int64_t n_bins, int *total)
 struct Plan {
     const char *name;
     int bt, lt, ks, nt;
+    int kgran;               // sample chunks are multiples of this
     int static_lds;
-    const void *kfn[2];     // [PROD_LAG, PROD_IDENTITY]
+    const void *kfn[2];      // [PROD_LAG, PROD_IDENTITY]; nullptr: no such form
     const void *kfn_batched; // persistent lag-product kernel
+    double cost_scale;       // relative cost per padded cell in the built-in choice
+    float sign_scale;        // scale of the input signs the kernels read (1 or 1/2)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -111,11 +115,36 @@ Plan make_plan(const char *name)
     p.lt = Cfg::LT;
     p.ks = KS;
     p.nt = Cfg::NT;
+    p.kgran = KS;
     p.static_lds = 2 * (Cfg::STAGE_A_F4 + Cfg::STAGE_B_F4) * 16;
     p.kfn[0] = reinterpret_cast<const void *>(&contract_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
     p.kfn[1] = reinterpret_cast<const void *>(&contract_kernel<PREC, PROD_IDENTITY, WAVES_B, WAVES_L, WB, WL, KS>);
     p.kfn_batched =
         reinterpret_cast<const void *>(&contract_batched_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
+    p.cost_scale = 1.0 + 64.0 / Cfg::BT + 64.0 / Cfg::LT;
+    p.sign_scale = 1.0f;
+    return p;
+}
+
+// Split-BF16 surface plans with register-built lag operands (lag products only).
+template <int NW, int WB, int WL, int KS, int PF>
+Plan make_surface_plan(const char *name)
+{
+    using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
+    Plan p;
+    p.name = name;
+    p.bt = Cfg::BT;
+    p.lt = Cfg::LT;
+    p.ks = KS;
+    p.nt = Cfg::NT;
+    p.kgran = 2 * KS;
+    p.static_lds = 2 * Cfg::STAGE_A * 16;
+    p.kfn[0] = reinterpret_cast<const void *>(&surface_bf16_kernel<NW, WB, WL, KS, PF>);
+    p.kfn[1] = nullptr;
+    p.kfn_batched = reinterpret_cast<const void *>(&surface_bf16_batched_kernel<NW, WB, WL, KS, PF>);
+    // lag operands are built once per base tile, twiddles once per delay tile
+    p.cost_scale = 0.35 * (1.0 + 24.0 / Cfg::BT + 8.0 / Cfg::LT);
+    p.sign_scale = 0.5f;
     return p;
 }
 
@@ -137,6 +166,10 @@ const std::vector<Plan> &plans(int prec)
         make_plan<PREC_BF16X2, 1, 8, 2, 1, 8>("bf16x2_b64_l256_w8_ks8"),
         make_plan<PREC_BF16X2, 4, 2, 2, 1, 8>("bf16x2_b256_l64_w8_ks8"),
         make_plan<PREC_BF16X2, 3, 4, 1, 1, 8>("bf16x2_b96_l128_w12_ks8"),
+        make_surface_plan<4, 3, 1, 32, 4>("bf16x2r_b96_l128_w4_ks32"),
+        make_surface_plan<4, 2, 2, 32, 2>("bf16x2r_b64_l256_w4_ks32"),
+        make_surface_plan<8, 2, 1, 32, 2>("bf16x2r_b64_l256_w8_ks32"),
+        make_surface_plan<4, 3, 1, 16, 4>("bf16x2r_b96_l128_w4_ks16"),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -162,6 +195,7 @@ void set_kernel_attributes()
         for (const Plan &p : plans(prec))
             for (int k = 0; k < 3; ++k) {
                 const void *fn = k < 2 ? p.kfn[k] : p.kfn_batched;
+                if (!fn) continue;
                 hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, plan_max_dynamic(p));
                 if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
             }
@@ -173,7 +207,7 @@ struct Launch {
     int ksplit, kchunk;
     int tiles_b, tiles_l;
     int n_bases, n_bases_pad, n_cols_pad;
-    int tb, n_coarse;
+    int tb, n_coarse, tw_exact;
     BaseMap bm;
     size_t part_bytes; // split-K partials
     size_t ws_bytes;   // partials + signed copies of the inputs
@@ -199,7 +233,32 @@ int pick_ksplit(int tiles, int64_t n, int ks, int cus)
     return best;
 }
 
-Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins, int64_t signed_elems)
+// Two-level table for length n within max_bytes of LDS: fine size 2^tb >= sqrt(n) by
+// default. The exact form needs every quadrant point m in {n/4, n/2, 3n/4} that is an
+// integer to have m mod 2^tb = 0 (2^tb divides n/4, resp. n/2 for n = 2 mod 4; any tb
+// for odd n) and n <= 2^20; tb is lowered to get it when the coarse table still fits.
+void choose_table(int64_t n, int max_bytes, int *tb_out, int *n_coarse_out, int *exact_out)
+{
+    int tb = 0;
+    while ((1LL << (2 * tb)) < n) ++tb;
+    int exact = 0;
+    if (n <= (1 << 20)) {
+        int v = 0;
+        while (((n >> v) & 1) == 0) ++v;
+        const int cap = n % 4 == 0 ? v - 2 : (n % 2 == 0 ? v - 1 : 62);
+        const int t = std::min(tb, cap);
+        if ((cdiv(n, 1LL << t) + (1LL << t)) * (int64_t)sizeof(float2) <= max_bytes) {
+            tb = t;
+            exact = 1;
+        }
+    }
+    *tb_out = tb;
+    *n_coarse_out = (int)cdiv(n, 1LL << tb);
+    *exact_out = exact;
+}
+
+Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
+                   int64_t signed_elems)
 {
     Launch L;
     std::memset(&L, 0, sizeof(L));
@@ -212,16 +271,16 @@ Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bi
         ko = g_ksplit_override[prec];
     }
     const std::vector<Plan> &ps = plans(prec);
-    if (pi < 0 || pi >= (int)ps.size()) {
-        // built-in choice: padded matrix-core work plus operand generation (a tile
-        // generates one twiddle row per base and one lag column per delay, shared by
-        // the other dimension), then the earlier plan
+    if (pi < 0 || pi >= (int)ps.size() || !ps[pi].kfn[prod]) {
+        // built-in choice: padded matrix-core work times the plan's operand-generation
+        // overhead, then the earlier plan
         double best = -1.0;
         pi = 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
+            if (!ps[k].kfn[prod]) continue;
             double rows = (double)(cdiv(L.n_bases, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
-            double cost = rows * cols * (1.0 + 64.0 / ps[k].bt + 64.0 / ps[k].lt);
+            double cost = rows * cols * ps[k].cost_scale;
             if (best < 0 || cost < best * 0.999) {
                 best = cost;
                 pi = k;
@@ -233,14 +292,12 @@ Launch plan_launch(int prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bi
     L.tiles_l = (int)cdiv(n_cols, L.plan->lt);
     L.n_bases_pad = L.tiles_b * L.plan->bt;
     L.n_cols_pad = L.tiles_l * L.plan->lt;
-    int max_split = (int)std::max<int64_t>(1, cdiv(n, L.plan->ks));
-    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, L.plan->ks, device_cu_count());
-    L.kchunk = (int)(cdiv(cdiv(n, L.ksplit), L.plan->ks) * L.plan->ks);
+    const int gran = L.plan->kgran;
+    int max_split = (int)std::max<int64_t>(1, cdiv(n, gran));
+    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, gran, device_cu_count());
+    L.kchunk = (int)(cdiv(cdiv(n, L.ksplit), gran) * gran);
     L.ksplit = (int)cdiv(n, L.kchunk); // no empty chunks
-    int tb = 0;
-    while ((1LL << (2 * tb)) < n) ++tb; // 2^tb >= sqrt(n)
-    L.tb = tb;
-    L.n_coarse = (int)cdiv(n, 1LL << tb);
+    choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
     L.part_bytes = align256((size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad * sizeof(float4));
     L.ws_bytes = L.part_bytes + align256((size_t)signed_elems * sizeof(float4));
     return L;
@@ -293,12 +350,12 @@ ndft_status check_launch()
 }
 
 ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, int64_t ostride, int64_t lead,
-                        hipStream_t stream)
+                        float g, hipStream_t stream)
 {
     int64_t count = rows * ostride;
     if (count == 0) return NDFT_OK;
     hipLaunchKernelGGL(sign_prep_kernel, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, stream, x, out, (int)n,
-                       (long long)rows, (long long)ostride, (int)lead);
+                       (long long)rows, (long long)ostride, (int)lead, g);
     return check_launch();
 }
 
@@ -319,6 +376,7 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     P.bm = L.bm;
     P.tb = L.tb;
     P.n_coarse = L.n_coarse;
+    P.tw_exact = L.tw_exact;
     P.kchunk = L.kchunk;
     P.ksplit = L.ksplit;
     P.tiles_b = L.tiles_b;
@@ -329,6 +387,7 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     void *args[] = {&P};
     size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
     if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED; // FP8 stages leave less LDS
+    if (!L.plan->kfn[prod]) return NDFT_E_UNSUPPORTED;
     dim3 grid((unsigned)((int64_t)L.tiles_b * L.tiles_l * L.ksplit));
     dim3 block((unsigned)L.plan->nt);
     ProfScope prof(stream);
@@ -449,7 +508,7 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
                 make_base_map(cpis[c].n, cpis[c].p0, cpis[c].n_dop, &nb);
                 double rows = (double)(cdiv(nb, ps[k].bt) * ps[k].bt);
                 double cols = (double)(cdiv(cpis[c].n_tau, ps[k].lt) * ps[k].lt);
-                cost += rows * cols * (double)cpis[c].n * (1.0 + 64.0 / ps[k].bt + 64.0 / ps[k].lt);
+                cost += rows * cols * (double)cpis[c].n * ps[k].cost_scale;
             }
             if (best < 0 || cost < best * 0.999) {
                 best = cost;
@@ -459,7 +518,7 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
     }
     const Plan &P = ps[pi];
     G.plan = pi;
-    G.chunk = (int)(cdiv(chunk > 0 ? chunk : kDefaultChunk, P.ks) * P.ks);
+    G.chunk = (int)(cdiv(chunk > 0 ? chunk : kDefaultChunk, P.kgran) * P.kgran);
     G.params.resize(n_cpi);
     G.red.resize(n_cpi);
     G.outoff.resize(n_cpi);
@@ -497,11 +556,8 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
         C.n_cols = (int)d.n_tau;
         C.tau0 = (int)d.tau0;
         C.n_bases = nb;
-        int tb = 0;
-        while ((1LL << (2 * tb)) < d.n) ++tb;
-        C.tb = tb;
-        C.n_coarse = (int)cdiv(d.n, 1LL << tb);
-        G.table_bytes = std::max(G.table_bytes, (int)((C.n_coarse + (1 << tb)) * sizeof(float2)));
+        choose_table(d.n, plan_max_dynamic(P), &C.tb, &C.n_coarse, &C.tw_exact);
+        G.table_bytes = std::max(G.table_bytes, (int)((C.n_coarse + (1 << C.tb)) * sizeof(float2)));
         C.kchunk = G.chunk;
         C.ksplit = (int)cdiv(d.n, G.chunk);
         C.tiles_b = (int)cdiv(nb, P.bt);
@@ -531,9 +587,9 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
         R.n_bins = (int)d.n_dop;
         G.outoff[c] = (long long)d.out_off;
         G.prep[2 * c] = PrepDesc{(long long)d.surv_off, base ? reinterpret_cast<float4 *>(base + s4_off) : nullptr,
-                                 (int)d.n, 0, (long long)(d.n + kTailPad)};
+                                 (int)d.n, 0, (long long)(d.n + kTailPad), P.sign_scale};
         G.prep[2 * c + 1] = PrepDesc{(long long)d.ref_off, base ? reinterpret_cast<float4 *>(base + r4_off) : nullptr,
-                                     (int)d.n, (int)d.n, (long long)(2 * d.n + kTailPad)};
+                                     (int)d.n, (int)d.n, (long long)(2 * d.n + kTailPad), P.sign_scale};
         G.max_prep_blocks = std::max(G.max_prep_blocks, (int)std::min<int64_t>(cdiv(2 * d.n + kTailPad, 256), 1024));
         G.max_red_blocks =
             std::max(G.max_red_blocks, (int)std::min<int64_t>(cdiv((int64_t)C.n_cols * nb, 256), 4096));
@@ -581,7 +637,7 @@ const char *ndft_version(void) { return "ndft-mi355x 0.1 (gfx950)"; }
 size_t ndft_forward_workspace(int64_t batch, int64_t n, int64_t k0, int64_t k_count, ndft_prec prec)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || batch < 1 || k_count < 1 || k_count > n) return 0;
-    return plan_launch((int)prec, n, batch, k0, k_count, batch * (n + kTailPad)).ws_bytes;
+    return plan_launch((int)prec, PROD_IDENTITY, n, batch, k0, k_count, batch * (n + kTailPad)).ws_bytes;
 }
 
 ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int64_t k0, int64_t k_count,
@@ -593,13 +649,13 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     if (batch == 0) return NDFT_OK;
     if (batch > INT32_MAX / 2) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, batch, k0, k_count, batch * (n + kTailPad));
+    Launch L = plan_launch((int)prec, PROD_IDENTITY, n, batch, k0, k_count, batch * (n + kTailPad));
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float4 *part = reinterpret_cast<float4 *>(ws);
     float4 *x4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
-    st = launch_prep(reinterpret_cast<const float2 *>(x), x4, n, batch, n + kTailPad, 0, s);
+    st = launch_prep(reinterpret_cast<const float2 *>(x), x4, n, batch, n + kTailPad, 0, L.plan->sign_scale, s);
     if (st != NDFT_OK) return st;
     st = launch_contract(L, PROD_IDENTITY, x4, nullptr, n + kTailPad, n, batch, 0, part, s);
     if (st != NDFT_OK) return st;
@@ -609,7 +665,7 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
 size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
 {
     if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
-    return plan_launch((int)prec, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad).ws_bytes;
+    return plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad).ws_bytes;
 }
 
 ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
@@ -619,15 +675,16 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
     if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
+    Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float4 *part = reinterpret_cast<float4 *>(ws);
     float4 *s4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
     float4 *r4 = s4 + n + kTailPad; // n zeros, then the reference, then a zero tail
-    st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, s);
-    if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, s);
+    const float g = L.plan->sign_scale;
+    st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, g, s);
+    if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
     if (st != NDFT_OK) return st;
     st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s);
     if (st != NDFT_OK) return st;
@@ -835,7 +892,7 @@ ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t p0,
                           int32_t *ksplit)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || n_cols < 1 || n_bins < 1 || n_bins > n) return NDFT_E_INVAL;
-    Launch L = plan_launch((int)prec, n, n_cols, p0, n_bins, 0);
+    Launch L = plan_launch((int)prec, PROD_LAG, n, n_cols, p0, n_bins, 0);
     if (plan) *plan = (int32_t)(L.plan - plans((int)prec).data());
     if (ksplit) *ksplit = L.ksplit;
     return NDFT_OK;

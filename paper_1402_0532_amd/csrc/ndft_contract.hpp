@@ -51,8 +51,9 @@ __device__ __forceinline__ int base_of(const BaseMap &bm, int idx)
     return b;
 }
 
-// Zero samples after the end of every signed row (covers the last stage's tail).
-constexpr int kTailPad = 16;
+// Zero samples after the end of every signed row (covers the reads of the last stages
+// and the prefetch past them).
+constexpr int kTailPad = 128;
 
 struct ContractParams {
     const float4 *s4;     // signed samples (re, im, sign re, sign im), each row followed
@@ -67,6 +68,8 @@ struct ContractParams {
     int n_bases;
     BaseMap bm;
     int tb, n_coarse;     // two-level twiddle table: fine size 2^tb, coarse entries
+    int tw_exact;         // table reaches every quadrant point with fine index 0 (see
+                          // ndft_surface_bf16.hpp): its products there are exact
     int kchunk, ksplit;   // samples per chunk (multiple of KS), number of chunks
     int tiles_b, tiles_l;
     int n_bases_pad, n_cols_pad;
@@ -76,14 +79,15 @@ struct ContractParams {
 // Pack each complex sample with its exact component signs (read by the producers):
 // rows of n samples from x (row stride n) go to out with row stride `ostride`, starting
 // `lead` elements into each output row; every other output element is zero.
+// Signs are scaled by g (1, or 1/2 for the register-lag surface kernel).
 __global__ __launch_bounds__(256) void sign_prep_kernel(const float2 *__restrict__ x, float4 *__restrict__ out,
-                                                        int n, long long rows, long long ostride, int lead)
+                                                        int n, long long rows, long long ostride, int lead, float g)
 {
     long long k = (long long)blockIdx.x * 256 + threadIdx.x;
     if (k >= rows * ostride) return;
     long long row = k / ostride;
     long long j = k - row * ostride - lead;
-    out[k] = (j >= 0 && j < n) ? with_signs(x[row * n + j]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    out[k] = (j >= 0 && j < n) ? with_signs(x[row * n + j], g) : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
@@ -93,11 +97,15 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
 }
 
 // bf16 pairs of (a, b) and of their remainders: a = hi.x + lo.x + O(2^-18 |a|).
+// (The high parts are read back from the packed word: a BF16 is the upper half of the
+// FP32 with the same value.)
 __device__ __forceinline__ void split_pair(float a, float b, uint32_t &hi, uint32_t &lo)
 {
     bf16x2v h = {(__bf16)a, (__bf16)b};
-    bf16x2v l = {(__bf16)(a - (float)h[0]), (__bf16)(b - (float)h[1])};
     hi = __builtin_bit_cast(uint32_t, h);
+    const float ha = __uint_as_float(hi << 16);
+    const float hb = __uint_as_float(hi & 0xffff0000u);
+    bf16x2v l = {(__bf16)(a - ha), (__bf16)(b - hb)};
     lo = __builtin_bit_cast(uint32_t, l);
 }
 
@@ -644,6 +652,7 @@ struct PrepDesc {
     float4 *out;
     int n, lead;
     long long ostride;
+    float g; // sign scale
 };
 
 __global__ __launch_bounds__(256) void prep_batched_kernel(const BatchHeader *hdr, const PrepDesc *pd,
@@ -656,7 +665,7 @@ __global__ __launch_bounds__(256) void prep_batched_kernel(const BatchHeader *hd
     x += D.src_off;
     for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < D.ostride; k += (long long)gridDim.x * 256) {
         long long j = k - D.lead;
-        D.out[k] = (j >= 0 && j < D.n) ? with_signs(x[j]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        D.out[k] = (j >= 0 && j < D.n) ? with_signs(x[j], D.g) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 

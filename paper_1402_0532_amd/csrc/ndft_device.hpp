@@ -59,10 +59,12 @@ struct Lag {
     float sr, si; // exact sign of each component, in {-1, 0, +1}
 };
 
-// Sample packed with its exact component signs: (re, im, sign re, sign im).
-__device__ __forceinline__ float4 with_signs(float2 x)
+// Sample packed with its exact component signs: (re, im, g sign re, g sign im). The
+// kernels use g = 1, or g = 1/2 where they want every Eq. (1) operator halved (an exact
+// scaling: each operator value x g sign(y) + y g sign(x) is then half the exact one).
+__device__ __forceinline__ float4 with_signs(float2 x, float g = 1.0f)
 {
-    return make_float4(x.x, x.y, sgnf(x.x), sgnf(x.y));
+    return make_float4(x.x, x.y, g * sgnf(x.x), g * sgnf(x.y));
 }
 
 // Lag product from signed samples s = (s_r, s_i, sgn s_r, sgn s_i), r likewise.
@@ -138,21 +140,29 @@ __device__ __forceinline__ float2 twiddle_value(const float2 *__restrict__ coars
     return make_float2(c, t);
 }
 
-// Fill the two-level table (all threads of the block take part; caller syncs).
+// Fill the two-level table (all threads of the block take part; caller syncs). The fine
+// entries are multiplied by fine_scale (a power of two: the products are scaled exactly).
 __device__ __forceinline__ void build_twiddle_tables(float2 *coarse, float2 *fine, int n, int tb,
-                                                     int n_coarse, int tid, int nthreads)
+                                                     int n_coarse, int tid, int nthreads, float fine_scale = 1.0f)
 {
     int nf = 1 << tb;
     for (int idx = tid; idx < n_coarse + nf; idx += nthreads) {
         long long m = idx < n_coarse ? ((long long)idx << tb) : (long long)(idx - n_coarse);
-        double x = 2.0 * (double)m / (double)n; // angle / pi
-        double sn, cs;
-        sincospi(x, &sn, &cs);
-        float2 w = make_float2((float)cs, (float)(-sn));
+        float2 w;
+        if ((4 * m) % n == 0) { // quadrant points: exactly 1, -j, -1, +j
+            const int q = (int)((4 * m) / n) & 3;
+            w = q == 0 ? make_float2(1.f, 0.f)
+                       : (q == 1 ? make_float2(0.f, -1.f) : (q == 2 ? make_float2(-1.f, 0.f) : make_float2(0.f, 1.f)));
+        } else {
+            double x = 2.0 * (double)m / (double)n; // angle / pi
+            double sn, cs;
+            sincospi(x, &sn, &cs);
+            w = make_float2((float)cs, (float)(-sn));
+        }
         if (idx < n_coarse)
             coarse[idx] = w;
         else
-            fine[idx - n_coarse] = w;
+            fine[idx - n_coarse] = make_float2(w.x * fine_scale, w.y * fine_scale);
     }
 }
 

@@ -1,0 +1,451 @@
+// Split-BF16 surface kernel with the lag-product operand built in registers.
+//
+// The sums are those of the shared-operand contraction (ndft_contract.hpp): for base bin
+// b and delay l, U = A1.B1, X = A1.B2, Y = A2.B1, V = A2.B2 over the samples, with twiddle
+// rows A1 = (Sc, C), A2 = (St, T) and lag columns B1 = (z_r, sigma_r), B2 = (z_i, sigma_i)
+// (Eq. (12a) through the identity a(x)b = csgn(a) b + a csgn(b)). What changes is where
+// the operands live:
+//   * a work-group is NW waves; wave w owns delays c0 + 32 WL w .. and ALL BT = 32 WB
+//     bases of the tile, so a lag-product column is used by exactly one wave: each lane
+//     computes its own B fragment (two samples of one delay) in registers, straight from
+//     the signed inputs, and never writes it to LDS;
+//   * the twiddle operand (shared by every wave) is generated cooperatively into a
+//     double-buffered LDS stage, one stage of KS samples ahead of the matrix cores.
+// LDS traffic per matrix instruction is then one A fragment (the B side needs none),
+// and every lane does the same operand work.
+//
+// Signs. A lag component z (FP32, one rounding of the exact sum of two Eq. (1)
+// operators) carries the exact sign whenever it is non-zero. The kernel takes the sign
+// operand from the rounded BF16 high part of z (a few bit operations per pair): exact
+// wherever that high part is non-zero. Lanes where a high part is zero (z = 0 or below
+// the BF16 range) are flagged per 4-sample group; after the stage, flagged groups are
+// recomputed with the exact comparison of the two operator magnitudes (FP64 TwoSum) and
+// the difference of the sign operands is added with extra matrix instructions.
+// Differences are 0 or +-2 (see Scaling), exact in BF16, and columns that are exactly zero get exact
+// zeros (the difference is zero, nothing is added).
+//
+// Twiddle values come from the two-level table. With TWX (exact table) the table is
+// chosen so that every quadrant point m in {0, N/4, N/2, 3N/4} that is an integer is
+// reached with a fine index of 0; the table product is then exactly 0 / +-1 there, and
+// elsewhere its error (a few FP32 ulp) is far below the smallest non-zero |cos|, |sin|
+// (about 1.5 / N; the host allows TWX for N <= 2^20), so the sign operands again come
+// from the rounded high parts. Without TWX, signs come from integer quadrant tests.
+#pragma once
+
+#include <type_traits>
+
+#include "ndft_contract.hpp"
+
+namespace ndft {
+
+// Scaling. Both operands carry their sign terms as +-2 and their value terms halved:
+// the prep stores input signs as +-1/2 (so every Eq. (1) operator, hence z, comes out
+// exactly halved) and the fine twiddle table holds W^r / 2. Products Sc' z' = (2 Sc)(z/2)
+// and C' sigma' = (C/2)(2 sigma) are the exact terms. The point is the BF16 pattern of
+// +-2, 0x4000: it is one bit of the rounded high part moved into place.
+
+// Sign operands of a BF16 pair v: +-2 where a half is non-zero, +-0 where it is zero.
+// The return value's bits 15 and 31 flag the non-zero halves.
+__device__ __forceinline__ uint32_t bf16_signs2(uint32_t v, uint32_t &sig)
+{
+    // a half in [1, 0x7fff] plus 0x7fff sets its bit 15 (no carry between halves)
+    const uint32_t t = (v & 0x7fff7fffu) + 0x7fff7fffu;
+    sig = ((t >> 1) & 0x40004000u) | (v & 0x80008000u);
+    return t;
+}
+
+// Lag products of two samples from half-signed inputs (z/2, the operations of
+// lag_product4) in the split-BF16 column layout: B1 = (z_r hi pair, z_r lo pair, sign
+// pair, sign pair), B2 likewise for z_i. Returns bits 15 and 31 set when all four high
+// parts are non-zero.
+__device__ __forceinline__ uint32_t lag_pair_operands(const float4 &s1, const float4 &s2, const float4 &r1,
+                                                      const float4 &r2, uint4 &B1, uint4 &B2)
+{
+    const float zr1 = fmaf(s1.x, r1.z, r1.x * s1.z) + fmaf(s1.y, r1.w, r1.y * s1.w);
+    const float zi1 = fmaf(s1.y, r1.z, r1.x * s1.w) - fmaf(r1.y, s1.z, s1.x * r1.w);
+    const float zr2 = fmaf(s2.x, r2.z, r2.x * s2.z) + fmaf(s2.y, r2.w, r2.y * s2.w);
+    const float zi2 = fmaf(s2.y, r2.z, r2.x * s2.w) - fmaf(r2.y, s2.z, s2.x * r2.w);
+    split_pair(zr1, zr2, B1.x, B1.y);
+    const uint32_t tr = bf16_signs2(B1.x, B1.z);
+    B1.w = B1.z;
+    split_pair(zi1, zi2, B2.x, B2.y);
+    const uint32_t ti = bf16_signs2(B2.x, B2.z);
+    B2.w = B2.z;
+    return tr & ti;
+}
+
+// Sign-operand corrections of a flagged pair: exact sign operands (2 csgn z) minus the
+// ones taken from the high parts, as BF16 pairs in {0, +-2} (only the sign dwords are
+// non-zero). Returns whether any is non-zero.
+__device__ __forceinline__ bool lag_pair_sign_fix(const float4 &s1, const float4 &s2, const float4 &r1,
+                                                  const float4 &r2, uint4 &D1, uint4 &D2)
+{
+    const Lag e1 = lag_product4(s1, r1); // values z/2, exact signs
+    const Lag e2 = lag_product4(s2, r2);
+    uint32_t hr, lr, hi, li, gr, gi;
+    split_pair(e1.zr, e2.zr, hr, lr);
+    split_pair(e1.zi, e2.zi, hi, li);
+    (void)bf16_signs2(hr, gr);
+    (void)bf16_signs2(hi, gi);
+    const float dr1 = 2.0f * e1.sr - __uint_as_float(gr << 16);
+    const float dr2 = 2.0f * e2.sr - __uint_as_float(gr & 0xffff0000u);
+    const float di1 = 2.0f * e1.si - __uint_as_float(gi << 16);
+    const float di2 = 2.0f * e2.si - __uint_as_float(gi & 0xffff0000u);
+    const uint32_t pr = pack_bf16x2(dr1, dr2), pi = pack_bf16x2(di1, di2);
+    D1 = make_uint4(0u, 0u, pr, pr);
+    D2 = make_uint4(0u, 0u, pi, pi);
+    return (dr1 != 0.0f) | (dr2 != 0.0f) | (di1 != 0.0f) | (di2 != 0.0f);
+}
+
+// Empty instruction that reads and redefines the four registers (no code is emitted):
+// later arithmetic on v stays after it.
+__device__ __forceinline__ void pin(float4 &v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
+// (a + b) mod n for 0 <= a, b < n < 2^31: the unsigned minimum of x and x - n.
+__device__ __forceinline__ int add_mod(int a, int b, int n)
+{
+    const unsigned x = (unsigned)(a + b);
+    return (int)min(x, x - (unsigned)n);
+}
+
+template <int NW, int WB, int WL, int KS, int PF>
+struct SurfCfg {
+    static constexpr int NT = 64 * NW;
+    static constexpr int BT = 32 * WB;
+    static constexpr int LT = 32 * WL * NW;
+    static constexpr int G = KS / 4;             // 4-sample matrix steps per stage
+    static constexpr int STAGE_A = KS * BT;      // uint4 per stage buffer
+    static constexpr int TW_UNITS = BT * KS / 2; // (base row, sample pair) per stage
+    static constexpr int TWI = (TW_UNITS + NT - 1) / NT;
+    static_assert(KS % 8 == 0, "a stage is an even number of 4-sample steps");
+    static_assert(G % PF == 0, "input buffers rotate within a stage");
+    static_assert(TWI <= G, "at most one twiddle unit per step");
+    static_assert(2 * KS + 4 * PF + 4 <= kTailPad, "the last stage pair and its prefetch stay in the zero tail");
+    static_assert(PF >= 2, "inputs of step g + 1 are read while step g + PF is fetched");
+};
+
+template <int NW, int WB, int WL, int KS, int PF, bool TWX>
+__device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const int kc, const int tile_b,
+                                                  const int tile_l,
+                                                  uint4 (*bufA)[SurfCfg<NW, WB, WL, KS, PF>::STAGE_A],
+                                                  float2 *tables)
+{
+    using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
+    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, TWI = Cfg::TWI;
+    // vector instructions per slot (lag operands ~45 per column block, a twiddle unit
+    // ~35) spread over the slot's matrix instructions
+    constexpr int VALU_PER_MFMA = (45 * WL + 35 * TWI / G + 4 * WB * WL - 1) / (4 * WB * WL);
+
+    float2 *coarse = tables;
+    float2 *fine = tables + P.n_coarse;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int h = lane >> 5;
+    const int l32 = lane & 31;
+    const int n = P.n;
+    const int b0 = tile_b * BT;
+    const int c0 = tile_l * LT;
+    const int k_begin = kc * P.kchunk;
+    const int k_end = min(n, k_begin + P.kchunk);
+    // chunks are whole stage pairs except the last one of the record, which reads the
+    // zero tail past n
+    const int npair = k_end > k_begin ? (k_end - k_begin + 2 * KS - 1) / (2 * KS) : 0;
+
+    build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, NT, 0.5f); // W / 2
+
+    // ---- twiddle units: (base row, sample pair) -> LDS slot, base, m of the pair ----
+    int tw_off[TWI], tw_b[TWI], tw_m[TWI], tw_dm[TWI];
+#pragma unroll
+    for (int it = 0; it < TWI; ++it) {
+        const int u = min(tid + it * NT, Cfg::TW_UNITS - 1);
+        const int row = u % BT, pair = u / BT;
+        tw_off[it] = (((pair >> 1) * 2) * 2 + (pair & 1)) * BT + row; // A1; A2 at + 2 BT
+        const int b = base_of(P.bm, b0 + row);
+        tw_b[it] = b;
+        tw_m[it] = (int)(((long long)b * (k_begin + 2 * pair)) % n);
+        tw_dm[it] = (int)(((long long)b * KS) % n);
+    }
+
+    // ---- lag operand sources: lane (h, l32), column block j: delay d_j ----
+    // sample i = k_begin + off + 2h (+1): s4[i], r4[n + i - d_j]
+    const float4 *sp = P.s4 + k_begin + 2 * h;
+    const float4 *rp[WL];
+#pragma unroll
+    for (int j = 0; j < WL; ++j) {
+        const int col = min(c0 + (wave * WL + j) * 32 + l32, P.n_cols - 1); // padding repeats
+        rp[j] = P.r4 + (n - (P.tau0 + col)) + k_begin + 2 * h;
+    }
+
+    f32x16 acc[WB][WL][4];
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WL; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][t][e] = 0.0f;
+
+    // A twiddle unit is fetched (four table entries, issued together at the start of a
+    // stage so their LDS latency is hidden) and later finished (operands to LDS).
+    struct TwFetch {
+        float2 a1, b1, a2, b2; // coarse and fine entries of m1 and m2
+        int m2;
+    };
+    TwFetch twf[TWI];
+    auto tw_fetch = [&](int it) {
+        const int m1 = tw_m[it];
+        const int m2 = add_mod(m1, tw_b[it], n);
+        const int mask = (1 << P.tb) - 1;
+        twf[it].a1 = coarse[m1 >> P.tb];
+        twf[it].b1 = fine[m1 & mask];
+        twf[it].a2 = coarse[m2 >> P.tb];
+        twf[it].b2 = fine[m2 & mask];
+        twf[it].m2 = m2;
+    };
+    auto tw_finish = [&](uint4 *buf, int it) {
+        if (Cfg::TW_UNITS % NT == 0 || tid + it * NT < Cfg::TW_UNITS) {
+            const TwFetch &f = twf[it];
+            const int m1 = tw_m[it];
+            // W / 2 (the fine table is halved)
+            float2 w1 = make_float2(fmaf(f.a1.x, f.b1.x, -f.a1.y * f.b1.y), fmaf(f.a1.x, f.b1.y, f.a1.y * f.b1.x));
+            float2 w2 = make_float2(fmaf(f.a2.x, f.b2.x, -f.a2.y * f.b2.y), fmaf(f.a2.x, f.b2.y, f.a2.y * f.b2.x));
+            uint4 a1, a2;
+            if (TWX) {
+                split_pair(w1.x, w2.x, a1.z, a1.w);
+                (void)bf16_signs2(a1.z, a1.x);
+                split_pair(w1.y, w2.y, a2.z, a2.w);
+                (void)bf16_signs2(a2.z, a2.x);
+            } else {
+                const TwSign g1 = twiddle_sign(m1, n), g2 = twiddle_sign(f.m2, n);
+                w1.x = g1.c ? w1.x : 0.0f;
+                w1.y = g1.t ? w1.y : 0.0f;
+                w2.x = g2.c ? w2.x : 0.0f;
+                w2.y = g2.t ? w2.y : 0.0f;
+                a1.x = pack_bf16x2(2.0f * (float)g1.c, 2.0f * (float)g2.c);
+                split_pair(w1.x, w2.x, a1.z, a1.w);
+                a2.x = pack_bf16x2(2.0f * (float)g1.t, 2.0f * (float)g2.t);
+                split_pair(w1.y, w2.y, a2.z, a2.w);
+            }
+            a1.y = a1.x;
+            a2.y = a2.x;
+            buf[tw_off[it]] = a1;
+            buf[tw_off[it] + 2 * BT] = a2;
+            tw_m[it] = add_mod(m1, tw_dm[it], n);
+        }
+    };
+
+    struct In {
+        float4 s1, s2, r1[WL], r2[WL];
+    };
+    In in[PF];
+    auto load_in = [&](In &x, int off) {
+        x.s1 = sp[off];
+        x.s2 = sp[off + 1];
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            x.r1[j] = rp[j][off];
+            x.r2[j] = rp[j][off + 1];
+        }
+    };
+
+    // A fragments of one 4-sample step: base block i, operand t (A1, A2)
+    struct AFrag {
+        bf16x8 a[WB][2];
+    };
+    auto load_a = [&](const uint4 *buf, int g, AFrag &f) {
+#pragma unroll
+        for (int i = 0; i < WB; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                f.a[i][t] = __builtin_bit_cast(bf16x8, buf[((g * 2 + t) * 2 + h) * BT + 32 * i + l32]);
+    };
+    auto mfma_step = [&](const AFrag &f, const uint4 (&B1)[WL], const uint4 (&B2)[WL]) {
+#pragma unroll
+        for (int i = 0; i < WB; ++i)
+#pragma unroll
+            for (int j = 0; j < WL; ++j) {
+                const bf16x8 b1 = __builtin_bit_cast(bf16x8, B1[j]);
+                const bf16x8 b2 = __builtin_bit_cast(bf16x8, B2[j]);
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b1, acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b2, acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b1, acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b2, acc[i][j][3], 0, 0, 0);
+            }
+    };
+
+    // Lag operands of one step from its inputs; returns 1 when some lane needs repair.
+    // The inputs are first passed through an empty volatile asm: that fixes the point
+    // where the wait for their loads happens (instruction selection would otherwise
+    // move the arithmetic up to the loads and shorten the prefetch distance).
+    struct BFrag {
+        uint4 b1[WL], b2[WL];
+    };
+    auto lag_step = [&](In &x, BFrag &f) -> uint32_t {
+        pin(x.s1);
+        pin(x.s2);
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            pin(x.r1[j]);
+            pin(x.r2[j]);
+        }
+        uint32_t nzall = 0x80008000u;
+#pragma unroll
+        for (int j = 0; j < WL; ++j) nzall &= lag_pair_operands(x.s1, x.s2, x.r1[j], x.r2[j], f.b1[j], f.b2[j]);
+        return __builtin_amdgcn_ballot_w64(nzall != 0x80008000u) != 0 ? 1u : 0u;
+    };
+
+    // Exact-sign repair of the flagged steps of one stage (rare: zero lag components).
+    auto repair = [&](const uint4 *buf, int kst, uint32_t bits) {
+        while (bits) {
+            const int g = __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int off = kst + 4 * g;
+            const float4 s1 = sp[off], s2 = sp[off + 1];
+            BFrag D;
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < WL; ++j)
+                any |= lag_pair_sign_fix(s1, s2, rp[j][off], rp[j][off + 1], D.b1[j], D.b2[j]);
+            if (__builtin_amdgcn_ballot_w64(any)) {
+                AFrag f;
+                load_a(buf, g, f);
+                mfma_step(f, D.b1, D.b2);
+            }
+        }
+    };
+
+    // Software pipeline over the 4-sample steps g of a stage (slot g): fetch the inputs
+    // of step g + PF, read the A fragments of step g + 1, build the lag operands of step
+    // g + 1, emit a twiddle unit of the next stage, and run the matrix step g on operands
+    // prepared in slot g - 1. Scheduling barriers keep each slot's loads at its start so
+    // they stay PF - 1 slots ahead of their use.
+    AFrag fa[2];
+    BFrag fb[2];
+    uint32_t rare_next = 0; // repair flag of step 0 of the next stage
+    auto stage = [&](auto cbc, auto kstc) {
+        constexpr int CB = decltype(cbc)::value;
+        constexpr int KST = decltype(kstc)::value;
+        uint4 *cur = bufA[CB];
+        uint4 *nxt = bufA[CB ^ 1];
+        uint32_t rare = rare_next;
+        load_a(cur, 0, fa[0]);
+#pragma unroll
+        for (int it = 0; it < TWI; ++it) tw_fetch(it);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            load_in(in[g % PF], KST + 4 * (g + PF));
+            if (g + 1 < G) load_a(cur, g + 1, fa[(g + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t r = lag_step(in[(g + 1) % PF], fb[(g + 1) & 1]);
+            if (g + 1 < G)
+                rare |= r << (g + 1);
+            else
+                rare_next = r;
+#pragma unroll
+            for (int it = 0; it < TWI; ++it)
+                if ((it * G) / TWI == g) tw_finish(nxt, it);
+            mfma_step(fa[g & 1], fb[g & 1].b1, fb[g & 1].b2);
+            // order inside the slot: each matrix instruction followed by a run of vector
+            // instructions (the matrix core works while they issue)
+#pragma unroll
+            for (int k = 0; k < 4 * WB * WL; ++k) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, VALU_PER_MFMA, 0); // VALU
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (rare) repair(cur, KST, rare);
+        __syncthreads();
+    };
+
+    __syncthreads(); // tables ready
+    if (npair > 0) {
+#pragma unroll
+        for (int it = 0; it < TWI; ++it) {
+            tw_fetch(it);
+            tw_finish(bufA[0], it);
+        }
+#pragma unroll
+        for (int p = 0; p < PF; ++p) load_in(in[p], 4 * p);
+        rare_next = lag_step(in[0], fb[0]);
+        __syncthreads();
+        for (int p = 0; p < npair; ++p) {
+            stage(std::integral_constant<int, 0>(), std::integral_constant<int, 0>());
+            stage(std::integral_constant<int, 1>(), std::integral_constant<int, KS>());
+            sp += 2 * KS;
+#pragma unroll
+            for (int j = 0; j < WL; ++j) rp[j] += 2 * KS;
+        }
+    }
+
+    // ---- partial sums of this chunk: lane holds rows 8*(e/4) + 4*h + e%4, column l32 ----
+    float4 *out = P.partial + (long long)kc * P.n_cols_pad * P.n_bases_pad;
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            const int col = c0 + (wave * WL + j) * 32 + l32;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = b0 + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+                float4 v;
+                v.x = acc[i][j][0][e]; // U = A1.B1
+                v.y = acc[i][j][3][e]; // V = A2.B2
+                v.z = acc[i][j][1][e]; // X = A1.B2
+                v.w = acc[i][j][2][e]; // Y = A2.B1
+                out[(long long)col * P.n_bases_pad + row] = v;
+            }
+        }
+}
+
+// One tile per work-group: blockIdx.x = (tile_l * tiles_b + tile_b) * ksplit + kc.
+template <int NW, int WB, int WL, int KS, int PF>
+__global__ __launch_bounds__(64 * NW, 1) void surface_bf16_kernel(ContractParams P)
+{
+    using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
+    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    extern __shared__ float2 tables[];
+    int bid = blockIdx.x;
+    const int kc = bid % P.ksplit;
+    bid /= P.ksplit;
+    if (P.tw_exact)
+        surface_bf16_tile<NW, WB, WL, KS, PF, true>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, tables);
+    else
+        surface_bf16_tile<NW, WB, WL, KS, PF, false>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, tables);
+}
+
+// Persistent form over a batch (same queue protocol as contract_batched_kernel).
+template <int NW, int WB, int WL, int KS, int PF>
+__global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchHeader *hdr,
+                                                                          const ContractParams *params,
+                                                                          const int4 *items,
+                                                                          unsigned long long tag, int plan_id)
+{
+    using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
+    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ int s_item;
+    extern __shared__ float2 tables[];
+    if (hdr->tag != tag || hdr->plan_id != plan_id) return;
+    const int n_items = hdr->n_items;
+    for (;;) {
+        __syncthreads(); // every thread has read s_item and finished with the LDS buffers
+        if (threadIdx.x == 0) s_item = atomicAdd(&hdr->counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const ContractParams P = params[__builtin_amdgcn_readfirstlane(w.x)];
+        if (P.tw_exact)
+            surface_bf16_tile<NW, WB, WL, KS, PF, true>(P, w.w, w.y, w.z, bufA, tables);
+        else
+            surface_bf16_tile<NW, WB, WL, KS, PF, false>(P, w.w, w.y, w.z, bufA, tables);
+    }
+}
+
+} // namespace ndft

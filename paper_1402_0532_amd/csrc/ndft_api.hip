@@ -103,6 +103,7 @@ struct Plan {
     const void *kfn_batched; // persistent lag-product kernel
     double cost_scale;       // relative cost per padded cell in the built-in choice
     float sign_scale;        // scale of the input signs the kernels read (1 or 1/2)
+    const void *planes_kfn;  // twiddle plane builder (nullptr: twiddles made in the kernel)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -123,11 +124,13 @@ Plan make_plan(const char *name)
         reinterpret_cast<const void *>(&contract_batched_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
     p.cost_scale = 1.0 + 64.0 / Cfg::BT + 64.0 / Cfg::LT;
     p.sign_scale = 1.0f;
+    p.planes_kfn = nullptr;
     return p;
 }
 
-// Split-BF16 surface plans with register-built lag operands (lag products only).
-template <int NW, int WB, int WL, int KS, int PF>
+// Split-BF16 surface plans with register-built lag operands (lag products only); with
+// PLANES the twiddle operand is precomputed into the workspace by a builder kernel.
+template <int NW, int WB, int WL, int KS, int PF, bool PLANES = false>
 Plan make_surface_plan(const char *name)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
@@ -138,13 +141,16 @@ Plan make_surface_plan(const char *name)
     p.ks = KS;
     p.nt = Cfg::NT;
     p.kgran = 2 * KS;
-    p.static_lds = 2 * Cfg::STAGE_A * 16;
-    p.kfn[0] = reinterpret_cast<const void *>(&surface_bf16_kernel<NW, WB, WL, KS, PF>);
+    p.static_lds = 2 * Cfg::STAGE_A * 16 + 2 * Cfg::WIN * 16 + 16;
+    p.kfn[0] = PLANES ? reinterpret_cast<const void *>(&surface_bf16_planes_kernel<NW, WB, WL, KS, PF>)
+                      : reinterpret_cast<const void *>(&surface_bf16_kernel<NW, WB, WL, KS, PF>);
     p.kfn[1] = nullptr;
-    p.kfn_batched = reinterpret_cast<const void *>(&surface_bf16_batched_kernel<NW, WB, WL, KS, PF>);
-    // lag operands are built once per base tile, twiddles once per delay tile
-    p.cost_scale = 0.35 * (1.0 + 24.0 / Cfg::BT + 8.0 / Cfg::LT);
+    p.kfn_batched =
+        PLANES ? nullptr : reinterpret_cast<const void *>(&surface_bf16_batched_kernel<NW, WB, WL, KS, PF>);
+    // lag operands are built once per base tile, twiddles once per delay tile (or once)
+    p.cost_scale = (PLANES ? 0.25 : 0.35) * (1.0 + 24.0 / Cfg::BT + (PLANES ? 0.0 : 8.0 / Cfg::LT));
     p.sign_scale = 0.5f;
+    p.planes_kfn = PLANES ? reinterpret_cast<const void *>(&plane_build_kernel<Cfg::BT, KS>) : nullptr;
     return p;
 }
 
@@ -170,6 +176,10 @@ const std::vector<Plan> &plans(int prec)
         make_surface_plan<4, 2, 2, 32, 2>("bf16x2r_b64_l256_w4_ks32"),
         make_surface_plan<8, 2, 1, 32, 2>("bf16x2r_b64_l256_w8_ks32"),
         make_surface_plan<4, 3, 1, 16, 4>("bf16x2r_b96_l128_w4_ks16"),
+        make_surface_plan<4, 3, 1, 16, 4, true>("bf16x2p_b96_l128_w4_ks16"),
+        make_surface_plan<4, 3, 1, 32, 4, true>("bf16x2p_b96_l128_w4_ks32"),
+        make_surface_plan<4, 2, 2, 32, 2, true>("bf16x2p_b64_l256_w4_ks32"),
+        make_surface_plan<8, 2, 1, 32, 2, true>("bf16x2p_b64_l256_w8_ks32"),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -193,8 +203,8 @@ void set_kernel_attributes()
 {
     for (int prec = 0; prec < 3; ++prec)
         for (const Plan &p : plans(prec))
-            for (int k = 0; k < 3; ++k) {
-                const void *fn = k < 2 ? p.kfn[k] : p.kfn_batched;
+            for (int k = 0; k < 4; ++k) {
+                const void *fn = k < 2 ? p.kfn[k] : (k == 2 ? p.kfn_batched : p.planes_kfn);
                 if (!fn) continue;
                 hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, plan_max_dynamic(p));
                 if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
@@ -210,7 +220,11 @@ struct Launch {
     int tb, n_coarse, tw_exact;
     BaseMap bm;
     size_t part_bytes; // split-K partials
-    size_t ws_bytes;   // partials + signed copies of the inputs
+    size_t ws_bytes;   // partials + signed copies of the inputs (+ twiddle planes)
+    long long plane_stages; // planes: stage blocks per base tile
+    size_t plane_bytes;
+    size_t plane_off;       // offset of the planes in the workspace
+    int grp_stride;
 };
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -300,6 +314,14 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
     L.part_bytes = align256((size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad * sizeof(float4));
     L.ws_bytes = L.part_bytes + align256((size_t)signed_elems * sizeof(float4));
+    if (L.plan->planes_kfn) {
+        // every stage a chunk can reach, the one after the last included (prefetch)
+        L.plane_stages = 2 * cdiv(n, 2LL * L.plan->ks) + 1;
+        L.plane_bytes = align256((size_t)L.tiles_b * L.plane_stages * L.plan->bt * L.plan->ks * sizeof(uint4));
+        L.plane_off = L.ws_bytes;
+        L.ws_bytes += L.plane_bytes;
+        L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
+    }
     return L;
 }
 
@@ -360,7 +382,8 @@ ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, i
 }
 
 ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const float4 *r4, long long col_stride,
-                            int64_t n, int64_t n_cols, int64_t tau0, float4 *partial, hipStream_t stream)
+                            int64_t n, int64_t n_cols, int64_t tau0, float4 *partial, hipStream_t stream,
+                            uint4 *planes = nullptr)
 {
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
@@ -390,6 +413,28 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     if (!L.plan->kfn[prod]) return NDFT_E_UNSUPPORTED;
     dim3 grid((unsigned)((int64_t)L.tiles_b * L.tiles_l * L.ksplit));
     dim3 block((unsigned)L.plan->nt);
+    if (L.plan->planes_kfn) {
+        if (!planes) return NDFT_E_INVAL;
+        P.planes = planes;
+        P.plane_stages = L.plane_stages;
+        P.grp_stride = L.grp_stride;
+        PlaneBuildParams Q;
+        std::memset(&Q, 0, sizeof(Q));
+        Q.planes = planes;
+        Q.plane_stages = L.plane_stages;
+        Q.n = (int)n;
+        Q.tb = L.tb;
+        Q.n_coarse = L.n_coarse;
+        Q.tw_exact = L.tw_exact;
+        Q.stages_per_block = 16;
+        Q.bm = L.bm;
+        void *qargs[] = {&Q};
+        dim3 qgrid((unsigned)cdiv(L.plane_stages, Q.stages_per_block), (unsigned)L.tiles_b);
+        if (hipLaunchKernel(L.plan->planes_kfn, qgrid, dim3(256), qargs, shmem, stream) != hipSuccess)
+            return NDFT_E_HIP;
+        grid = dim3((unsigned)((int64_t)L.tiles_l * L.grp_stride));
+        shmem = 0;
+    }
     ProfScope prof(stream);
     hipError_t e = hipLaunchKernel(L.plan->kfn[prod], grid, block, args, shmem, stream);
     prof.stop();
@@ -498,10 +543,11 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
         std::lock_guard<std::mutex> lk(g_plan_mu);
         pi = g_plan_override[prec];
     }
-    if (pi < 0 || pi >= (int)ps.size()) {
+    if (pi < 0 || pi >= (int)ps.size() || !ps[pi].kfn_batched) {
         double best = -1.0;
         pi = 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
+            if (!ps[k].kfn_batched) continue;
             double cost = 0.0;
             for (int c = 0; c < n_cpi; ++c) {
                 int nb;
@@ -686,7 +732,8 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, g, s);
     if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
     if (st != NDFT_OK) return st;
-    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s);
+    uint4 *planes = L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
+    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }
@@ -820,7 +867,9 @@ ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool,
     if (!batch || !surv_pool || !ref_pool || !out_pool) return NDFT_E_INVAL;
     if (!aligned(surv_pool, 8) || !aligned(ref_pool, 8) || !aligned(out_pool, 8)) return NDFT_E_INVAL;
     if (!prec_ok((ndft_prec)batch->prec)) return NDFT_E_INVAL;
-    if (batch->plan < 0 || batch->plan >= (int)plans(batch->prec).size()) return NDFT_E_INVAL;
+    if (batch->plan < 0 || batch->plan >= (int)plans(batch->prec).size() ||
+        !plans(batch->prec)[batch->plan].kfn_batched)
+        return NDFT_E_INVAL;
     if (batch->n_cpi < 1 || batch->n_cpi > kMaxBatch || batch->grid < 1 || batch->table_bytes < 0 ||
         batch->table_bytes > plan_max_dynamic(plans(batch->prec)[batch->plan]) || batch->max_red_blocks < 1 ||
         batch->max_prep_blocks < 1)

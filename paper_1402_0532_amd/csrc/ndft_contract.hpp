@@ -74,6 +74,11 @@ struct ContractParams {
     int tiles_b, tiles_l;
     int n_bases_pad, n_cols_pad;
     float4 *partial;      // [ksplit][n_cols_pad][n_bases_pad] of (U, V, X, Y)
+    // precomputed twiddle operand (register-lag surface kernels with planes): per base
+    // tile, `plane_stages` consecutive stage blocks in the LDS order of a stage
+    const uint4 *planes;
+    long long plane_stages;
+    int grp_stride;       // block order: tile_l * grp_stride + (tile_b * ksplit + kc)
 };
 
 // Pack each complex sample with its exact component signs (read by the producers):

@@ -38,6 +38,8 @@
 
 namespace ndft {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4))); // plain 16-byte loads/stores
+
 // Scaling. Both operands carry their sign terms as +-2 and their value terms halved:
 // the prep stores input signs as +-1/2 (so every Eq. (1) operator, hence z, comes out
 // exactly halved) and the fine twiddle table holds W^r / 2. Products Sc' z' = (2 Sc)(z/2)
@@ -52,6 +54,36 @@ __device__ __forceinline__ uint32_t bf16_signs2(uint32_t v, uint32_t &sig)
     const uint32_t t = (v & 0x7fff7fffu) + 0x7fff7fffu;
     sig = ((t >> 1) & 0x40004000u) | (v & 0x80008000u);
     return t;
+}
+
+// Twiddle operands of base row b for the sample pair (i, i + 1), m1 = b i mod N,
+// m2 = b (i + 1) mod N, from the four table entries (coarse and fine of m1 and m2; the
+// fine table holds W / 2): A1 = (Sc pair, Sc pair, C hi pair, C lo pair) and A2 = (St
+// pair, St pair, T hi pair, T lo pair), sign operands +-2 (see Scaling).
+template <bool TWX>
+__device__ __forceinline__ void twiddle_pair_operands(float2 a1, float2 b1, float2 a2, float2 b2, int m1, int m2,
+                                                      int n, uint4 &A1, uint4 &A2)
+{
+    float2 w1 = make_float2(fmaf(a1.x, b1.x, -a1.y * b1.y), fmaf(a1.x, b1.y, a1.y * b1.x));
+    float2 w2 = make_float2(fmaf(a2.x, b2.x, -a2.y * b2.y), fmaf(a2.x, b2.y, a2.y * b2.x));
+    if (TWX) {
+        split_pair(w1.x, w2.x, A1.z, A1.w);
+        (void)bf16_signs2(A1.z, A1.x);
+        split_pair(w1.y, w2.y, A2.z, A2.w);
+        (void)bf16_signs2(A2.z, A2.x);
+    } else {
+        const TwSign g1 = twiddle_sign(m1, n), g2 = twiddle_sign(m2, n);
+        w1.x = g1.c ? w1.x : 0.0f;
+        w1.y = g1.t ? w1.y : 0.0f;
+        w2.x = g2.c ? w2.x : 0.0f;
+        w2.y = g2.t ? w2.y : 0.0f;
+        A1.x = pack_bf16x2(2.0f * (float)g1.c, 2.0f * (float)g2.c);
+        split_pair(w1.x, w2.x, A1.z, A1.w);
+        A2.x = pack_bf16x2(2.0f * (float)g1.t, 2.0f * (float)g2.t);
+        split_pair(w1.y, w2.y, A2.z, A2.w);
+    }
+    A1.y = A1.x;
+    A2.y = A2.x;
 }
 
 // Lag products of two samples from half-signed inputs (z/2, the operations of
@@ -97,11 +129,23 @@ __device__ __forceinline__ bool lag_pair_sign_fix(const float4 &s1, const float4
     return (dr1 != 0.0f) | (dr2 != 0.0f) | (di1 != 0.0f) | (di2 != 0.0f);
 }
 
-// Empty instruction that reads and redefines the four registers (no code is emitted):
-// later arithmetic on v stays after it.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// Empty instructions that read and redefine a whole register tuple (no code is emitted):
+// arithmetic on the value stays after them. Instruction selection would otherwise hoist
+// the arithmetic of a later pipeline slot up to the load that feeds it.
 __device__ __forceinline__ void pin(float4 &v)
 {
-    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+    f32x4v t = __builtin_bit_cast(f32x4v, v);
+    asm volatile("" : "+v"(t));
+    v = __builtin_bit_cast(float4, t);
+}
+__device__ __forceinline__ void pin(float2 &v)
+{
+    f32x2v t = __builtin_bit_cast(f32x2v, v);
+    asm volatile("" : "+v"(t));
+    v = __builtin_bit_cast(float2, t);
 }
 
 // (a + b) mod n for 0 <= a, b < n < 2^31: the unsigned minimum of x and x - n.
@@ -120,27 +164,41 @@ struct SurfCfg {
     static constexpr int STAGE_A = KS * BT;      // uint4 per stage buffer
     static constexpr int TW_UNITS = BT * KS / 2; // (base row, sample pair) per stage
     static constexpr int TWI = (TW_UNITS + NT - 1) / NT;
+    // input windows of a stage in LDS: surveillance samples k0 .. k0 + KS + 7 and the
+    // reference samples every delay of the tile needs for them
+    static constexpr int WS = KS + 8;
+    static constexpr int WR = KS + 8 + LT - 1;
+    static constexpr int WIN = WS + WR;
+    static constexpr int WIN_ITERS = (WIN + NT - 1) / NT;
     static_assert(KS % 8 == 0, "a stage is an even number of 4-sample steps");
-    static_assert(G % PF == 0, "input buffers rotate within a stage");
     static_assert(TWI <= G, "at most one twiddle unit per step");
-    static_assert(2 * KS + 4 * PF + 4 <= kTailPad, "the last stage pair and its prefetch stay in the zero tail");
-    static_assert(PF >= 2, "inputs of step g + 1 are read while step g + PF is fetched");
+    static_assert(2 * KS + 8 <= kTailPad, "the last stage pair and its window stay in the zero tail");
 };
 
-template <int NW, int WB, int WL, int KS, int PF, bool TWX>
+// Twiddle source of a tile: generated in the kernel from the table with integer signs
+// (TW_GEN) or with signs from the exact table (TW_GEN_EXACT), or copied from planes
+// precomputed by plane_build_kernel (TW_PLANES).
+enum { TW_GEN = 0, TW_GEN_EXACT = 1, TW_PLANES = 2 };
+
+template <int NW, int WB, int WL, int KS, int PF, int TWM>
 __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const int kc, const int tile_b,
                                                   const int tile_l,
                                                   uint4 (*bufA)[SurfCfg<NW, WB, WL, KS, PF>::STAGE_A],
-                                                  float2 *tables)
+                                                  float4 (*win)[SurfCfg<NW, WB, WL, KS, PF>::WIN], float2 *tables)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
-    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, TWI = Cfg::TWI;
+    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G;
+    constexpr bool TWX = TWM == TW_GEN_EXACT;
+    constexpr bool PLANES = TWM == TW_PLANES;
+    constexpr int TWI = PLANES ? 0 : Cfg::TWI;  // generated twiddle units per thread
+    constexpr int PLI = Cfg::STAGE_A / NT;       // plane uint4 per thread per stage
+    static_assert(!PLANES || Cfg::STAGE_A % NT == 0, "plane stages split evenly");
     // vector instructions per slot (lag operands ~45 per column block, a twiddle unit
     // ~35) spread over the slot's matrix instructions
     constexpr int VALU_PER_MFMA = (45 * WL + 35 * TWI / G + 4 * WB * WL - 1) / (4 * WB * WL);
 
     float2 *coarse = tables;
-    float2 *fine = tables + P.n_coarse;
+    float2 *fine = PLANES ? nullptr : tables + P.n_coarse;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -156,10 +214,10 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     // zero tail past n
     const int npair = k_end > k_begin ? (k_end - k_begin + 2 * KS - 1) / (2 * KS) : 0;
 
-    build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, NT, 0.5f); // W / 2
+    if (!PLANES) build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, NT, 0.5f); // W / 2
 
     // ---- twiddle units: (base row, sample pair) -> LDS slot, base, m of the pair ----
-    int tw_off[TWI], tw_b[TWI], tw_m[TWI], tw_dm[TWI];
+    int tw_off[TWI > 0 ? TWI : 1], tw_b[TWI > 0 ? TWI : 1], tw_m[TWI > 0 ? TWI : 1], tw_dm[TWI > 0 ? TWI : 1];
 #pragma unroll
     for (int it = 0; it < TWI; ++it) {
         const int u = min(tid + it * NT, Cfg::TW_UNITS - 1);
@@ -172,14 +230,38 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     }
 
     // ---- lag operand sources: lane (h, l32), column block j: delay d_j ----
-    // sample i = k_begin + off + 2h (+1): s4[i], r4[n + i - d_j]
+    // sample i = k_begin + off + 2h (+1): s4[i], r4[n + i - d_j] (global: exact-sign repair)
     const float4 *sp = P.s4 + k_begin + 2 * h;
     const float4 *rp[WL];
+    // the same samples in the stage window: Ws[i - k0], Wr[i - k0 + (dmax - d_j)]
+    const int dmax = P.tau0 + min(c0 + LT - 1, P.n_cols - 1);
+    int roff[WL];
 #pragma unroll
     for (int j = 0; j < WL; ++j) {
         const int col = min(c0 + (wave * WL + j) * 32 + l32, P.n_cols - 1); // padding repeats
         rp[j] = P.r4 + (n - (P.tau0 + col)) + k_begin + 2 * h;
+        roff[j] = Cfg::WS + dmax - (P.tau0 + col) + 2 * h;
     }
+    // one load per lane per stage: entry e < WS is s4[k0 + e], else r4[n + k0 - dmax + e - WS]
+    // (indices past WIN repeat the last entry and are not stored)
+    auto win_load = [&](int k0, float4 (&wv)[Cfg::WIN_ITERS]) {
+#pragma unroll
+        for (int it = 0; it < Cfg::WIN_ITERS; ++it) {
+            const int e = min(tid + it * NT, Cfg::WIN - 1);
+            const float4 *src = e < Cfg::WS ? P.s4 + k0 + e : P.r4 + (n + k0 - dmax) + (e - Cfg::WS);
+            wv[it] = *src;
+        }
+    };
+    auto win_store = [&](float4 *w, const float4 (&wv)[Cfg::WIN_ITERS]) {
+#pragma unroll
+        for (int it = 0; it < Cfg::WIN_ITERS; ++it)
+            if (Cfg::WIN % NT == 0 || tid + it * NT < Cfg::WIN) w[tid + it * NT] = wv[it];
+    };
+
+    // planes of this base tile, from the first stage of this chunk
+    const u32x4 *pl_src =
+        PLANES ? reinterpret_cast<const u32x4 *>(P.planes) + ((long long)tile_b * P.plane_stages + k_begin / KS) * Cfg::STAGE_A + tid
+               : nullptr;
 
     f32x16 acc[WB][WL][4];
 #pragma unroll
@@ -197,7 +279,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
         float2 a1, b1, a2, b2; // coarse and fine entries of m1 and m2
         int m2;
     };
-    TwFetch twf[TWI];
+    TwFetch twf[TWI > 0 ? TWI : 1];
     auto tw_fetch = [&](int it) {
         const int m1 = tw_m[it];
         const int m2 = add_mod(m1, tw_b[it], n);
@@ -210,30 +292,14 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     };
     auto tw_finish = [&](uint4 *buf, int it) {
         if (Cfg::TW_UNITS % NT == 0 || tid + it * NT < Cfg::TW_UNITS) {
-            const TwFetch &f = twf[it];
+            TwFetch &f = twf[it];
+            pin(f.a1);
+            pin(f.b1);
+            pin(f.a2);
+            pin(f.b2);
             const int m1 = tw_m[it];
-            // W / 2 (the fine table is halved)
-            float2 w1 = make_float2(fmaf(f.a1.x, f.b1.x, -f.a1.y * f.b1.y), fmaf(f.a1.x, f.b1.y, f.a1.y * f.b1.x));
-            float2 w2 = make_float2(fmaf(f.a2.x, f.b2.x, -f.a2.y * f.b2.y), fmaf(f.a2.x, f.b2.y, f.a2.y * f.b2.x));
             uint4 a1, a2;
-            if (TWX) {
-                split_pair(w1.x, w2.x, a1.z, a1.w);
-                (void)bf16_signs2(a1.z, a1.x);
-                split_pair(w1.y, w2.y, a2.z, a2.w);
-                (void)bf16_signs2(a2.z, a2.x);
-            } else {
-                const TwSign g1 = twiddle_sign(m1, n), g2 = twiddle_sign(f.m2, n);
-                w1.x = g1.c ? w1.x : 0.0f;
-                w1.y = g1.t ? w1.y : 0.0f;
-                w2.x = g2.c ? w2.x : 0.0f;
-                w2.y = g2.t ? w2.y : 0.0f;
-                a1.x = pack_bf16x2(2.0f * (float)g1.c, 2.0f * (float)g2.c);
-                split_pair(w1.x, w2.x, a1.z, a1.w);
-                a2.x = pack_bf16x2(2.0f * (float)g1.t, 2.0f * (float)g2.t);
-                split_pair(w1.y, w2.y, a2.z, a2.w);
-            }
-            a1.y = a1.x;
-            a2.y = a2.x;
+            twiddle_pair_operands<TWX>(f.a1, f.b1, f.a2, f.b2, m1, f.m2, n, a1, a2);
             buf[tw_off[it]] = a1;
             buf[tw_off[it] + 2 * BT] = a2;
             tw_m[it] = add_mod(m1, tw_dm[it], n);
@@ -243,14 +309,14 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     struct In {
         float4 s1, s2, r1[WL], r2[WL];
     };
-    In in[PF];
-    auto load_in = [&](In &x, int off) {
-        x.s1 = sp[off];
-        x.s2 = sp[off + 1];
+    In in[2];
+    auto read_in = [&](const float4 *w, In &x, int q) { // step q of the window's stage
+        x.s1 = w[4 * q + 2 * h];
+        x.s2 = w[4 * q + 2 * h + 1];
 #pragma unroll
         for (int j = 0; j < WL; ++j) {
-            x.r1[j] = rp[j][off];
-            x.r2[j] = rp[j][off + 1];
+            x.r1[j] = w[roff[j] + 4 * q];
+            x.r2[j] = w[roff[j] + 4 * q + 1];
         }
     };
 
@@ -280,9 +346,6 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     };
 
     // Lag operands of one step from its inputs; returns 1 when some lane needs repair.
-    // The inputs are first passed through an empty volatile asm: that fixes the point
-    // where the wait for their loads happens (instruction selection would otherwise
-    // move the arithmetic up to the loads and shorten the prefetch distance).
     struct BFrag {
         uint4 b1[WL], b2[WL];
     };
@@ -320,29 +383,46 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
         }
     };
 
-    // Software pipeline over the 4-sample steps g of a stage (slot g): fetch the inputs
-    // of step g + PF, read the A fragments of step g + 1, build the lag operands of step
-    // g + 1, emit a twiddle unit of the next stage, and run the matrix step g on operands
-    // prepared in slot g - 1. Scheduling barriers keep each slot's loads at its start so
-    // they stay PF - 1 slots ahead of their use.
+    // Software pipeline over the 4-sample steps g of a stage (slot g): read the inputs of
+    // step g + 2 from the stage window (LDS), read the A fragments of step g + 1, build the
+    // lag operands of step g + 1, emit a twiddle unit of the next stage, and run the matrix
+    // step g on operands prepared in slot g - 1. The next stage's window is fetched from
+    // global memory at the start of the stage (one load per lane) and stored at its end.
+    // Scheduling barriers keep each slot's reads at its start.
     AFrag fa[2];
     BFrag fb[2];
     uint32_t rare_next = 0; // repair flag of step 0 of the next stage
+    int kpair = 0;          // first sample of the current stage pair, from k_begin
     auto stage = [&](auto cbc, auto kstc) {
         constexpr int CB = decltype(cbc)::value;
         constexpr int KST = decltype(kstc)::value;
         uint4 *cur = bufA[CB];
         uint4 *nxt = bufA[CB ^ 1];
+        const float4 *curw = win[CB];
         uint32_t rare = rare_next;
         load_a(cur, 0, fa[0]);
+        float4 wv[Cfg::WIN_ITERS]; // next stage's window
+        win_load(k_begin + KST + KS + kpair, wv);
+        u32x4 plv[PLANES ? PLI : 1]; // next stage's plane block
+        if (PLANES) {
 #pragma unroll
-        for (int it = 0; it < TWI; ++it) tw_fetch(it);
+            for (int k = 0; k < PLI; ++k) plv[k] = pl_src[k * NT];
+            pl_src += Cfg::STAGE_A;
+        }
+        // twiddle unit it is finished in slot (it G) / TWI and its table entries are read
+        // one slot earlier (unit 0: here)
+#pragma unroll
+        for (int it = 0; it < TWI; ++it)
+            if ((it * G) / TWI == 0) tw_fetch(it);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            load_in(in[g % PF], KST + 4 * (g + PF));
+            read_in(curw, in[g & 1], g + 2); // steps G, G + 1 are in this window too
             if (g + 1 < G) load_a(cur, g + 1, fa[(g + 1) & 1]);
+#pragma unroll
+            for (int it = 0; it < TWI; ++it)
+                if ((it * G) / TWI == g + 1) tw_fetch(it);
             __builtin_amdgcn_sched_barrier(0);
-            const uint32_t r = lag_step(in[(g + 1) % PF], fb[(g + 1) & 1]);
+            const uint32_t r = lag_step(in[(g + 1) & 1], fb[(g + 1) & 1]);
             if (g + 1 < G)
                 rare |= r << (g + 1);
             else
@@ -360,6 +440,12 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+        if (PLANES) {
+            u32x4 *dst = reinterpret_cast<u32x4 *>(nxt) + tid;
+#pragma unroll
+            for (int k = 0; k < PLI; ++k) dst[k * NT] = plv[k];
+        }
+        win_store(win[CB ^ 1], wv);
         if (rare) repair(cur, KST, rare);
         __syncthreads();
     };
@@ -371,14 +457,26 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             tw_fetch(it);
             tw_finish(bufA[0], it);
         }
+        if (PLANES) {
+            u32x4 *dst = reinterpret_cast<u32x4 *>(bufA[0]) + tid;
 #pragma unroll
-        for (int p = 0; p < PF; ++p) load_in(in[p], 4 * p);
-        rare_next = lag_step(in[0], fb[0]);
+            for (int k = 0; k < PLI; ++k) dst[k * NT] = pl_src[k * NT];
+            pl_src += Cfg::STAGE_A;
+        }
+        {
+            float4 wv[Cfg::WIN_ITERS];
+            win_load(k_begin, wv);
+            win_store(win[0], wv);
+        }
         __syncthreads();
+        read_in(win[0], in[0], 0);
+        read_in(win[0], in[1], 1);
+        rare_next = lag_step(in[0], fb[0]);
         for (int p = 0; p < npair; ++p) {
             stage(std::integral_constant<int, 0>(), std::integral_constant<int, 0>());
             stage(std::integral_constant<int, 1>(), std::integral_constant<int, KS>());
             sp += 2 * KS;
+            kpair += 2 * KS;
 #pragma unroll
             for (int j = 0; j < WL; ++j) rp[j] += 2 * KS;
         }
@@ -410,14 +508,81 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_kernel(ContractParams
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
     __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ float4 win[2][Cfg::WIN];
     extern __shared__ float2 tables[];
     int bid = blockIdx.x;
     const int kc = bid % P.ksplit;
     bid /= P.ksplit;
     if (P.tw_exact)
-        surface_bf16_tile<NW, WB, WL, KS, PF, true>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, tables);
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, win,
+                                                            tables);
     else
-        surface_bf16_tile<NW, WB, WL, KS, PF, false>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, tables);
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, win, tables);
+}
+
+// Twiddle operand from planes. Block order keeps the delay tiles that share a plane
+// stream on one XCD (blocks are dealt to the XCDs in turn, so blockIdx mod 8 picks it):
+// blockIdx = tile_l * grp_stride + (tile_b * ksplit + kc), grp_stride a multiple of 8;
+// indices past the last group exit at once.
+template <int NW, int WB, int WL, int KS, int PF>
+__global__ __launch_bounds__(64 * NW, 1) void surface_bf16_planes_kernel(ContractParams P)
+{
+    using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
+    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ float4 win[2][Cfg::WIN];
+    const int grp = blockIdx.x % P.grp_stride;
+    const int tile_l = blockIdx.x / P.grp_stride;
+    if (grp >= P.tiles_b * P.ksplit) return;
+    surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES>(P, grp % P.ksplit, grp / P.ksplit, tile_l, bufA, win, nullptr);
+}
+
+// Precompute the twiddle planes: thread t of a block owns units (row, pair) t, t + 256,
+// ... of the stage layout and walks `stages_per_block` consecutive stages of base tile
+// blockIdx.y, so m = b i mod N advances by b KS mod N per stage.
+struct PlaneBuildParams {
+    uint4 *planes;
+    long long plane_stages;
+    int n, tb, n_coarse, tw_exact;
+    int stages_per_block;
+    BaseMap bm;
+};
+
+template <int BT, int KS>
+__global__ __launch_bounds__(256) void plane_build_kernel(PlaneBuildParams Q)
+{
+    extern __shared__ float2 tables[];
+    constexpr int STAGE_A = KS * BT;
+    constexpr int UNITS = BT * KS / 2;
+    float2 *coarse = tables;
+    float2 *fine = tables + Q.n_coarse;
+    const int n = Q.n;
+    build_twiddle_tables(coarse, fine, n, Q.tb, Q.n_coarse, threadIdx.x, 256, 0.5f);
+    __syncthreads();
+    const long long s0 = (long long)blockIdx.x * Q.stages_per_block;
+    const long long s1 = min(s0 + Q.stages_per_block, Q.plane_stages);
+    const int mask = (1 << Q.tb) - 1;
+    for (int u = threadIdx.x; u < UNITS; u += 256) {
+        const int row = u % BT, pair = u / BT;
+        const int off = (((pair >> 1) * 2) * 2 + (pair & 1)) * BT + row;
+        const int b = base_of(Q.bm, blockIdx.y * BT + row);
+        int m1 = (int)(((long long)b * (s0 * KS + 2 * pair)) % n);
+        const int dm = (int)(((long long)b * KS) % n);
+        uint4 *dst = Q.planes + ((long long)blockIdx.y * Q.plane_stages + s0) * STAGE_A + off;
+        for (long long st = s0; st < s1; ++st) {
+            const int m2 = add_mod(m1, b, n);
+            uint4 a1, a2;
+            if (Q.tw_exact)
+                twiddle_pair_operands<true>(coarse[m1 >> Q.tb], fine[m1 & mask], coarse[m2 >> Q.tb], fine[m2 & mask],
+                                            m1, m2, n, a1, a2);
+            else
+                twiddle_pair_operands<false>(coarse[m1 >> Q.tb], fine[m1 & mask], coarse[m2 >> Q.tb], fine[m2 & mask],
+                                             m1, m2, n, a1, a2);
+            dst[0] = a1;
+            dst[2 * BT] = a2;
+            dst += STAGE_A;
+            m1 = add_mod(m1, dm, n);
+        }
+    }
 }
 
 // Persistent form over a batch (same queue protocol as contract_batched_kernel).
@@ -429,6 +594,7 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchH
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
     __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ float4 win[2][Cfg::WIN];
     __shared__ int s_item;
     extern __shared__ float2 tables[];
     if (hdr->tag != tag || hdr->plan_id != plan_id) return;
@@ -442,9 +608,9 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchH
         const int4 w = items[it];
         const ContractParams P = params[__builtin_amdgcn_readfirstlane(w.x)];
         if (P.tw_exact)
-            surface_bf16_tile<NW, WB, WL, KS, PF, true>(P, w.w, w.y, w.z, bufA, tables);
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT>(P, w.w, w.y, w.z, bufA, win, tables);
         else
-            surface_bf16_tile<NW, WB, WL, KS, PF, false>(P, w.w, w.y, w.z, bufA, tables);
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN>(P, w.w, w.y, w.z, bufA, win, tables);
     }
 }
 

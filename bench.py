@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2", "fp8"])
     ap.add_argument("--forms", default="fp32,bf16x2,fp8", help="forms to time (comma list)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in plan choice")
+    ap.add_argument("--plan", action="append", default=[], metavar="FORM=NAME:KSPLIT",
+                    help="force a tile plan and split count for a form (no autotuning for it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 CPIs) and adjoint (N=8192) sections")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -186,9 +188,20 @@ def main():
     results = {}
     outs = {}
     tuned = {}
+    forced = {}
+    for spec in args.plan:
+        form, rest = spec.split("=", 1)
+        name, ks = rest.split(":")
+        forced[form] = (name, int(ks))
     for form in forms:
         prec = nd.PRECISIONS[form]
-        if not args.no_autotune:
+        if form in forced:
+            name, ks = forced[form]
+            idx = [k for k in range(nd.plan_count(prec)) if nd.plan_name(prec, k) == name]
+            if not idx:
+                sys.exit("bench.py: no plan %r for form %s" % (name, form))
+            nd.set_plan(prec, idx[0], ks)
+        elif not args.no_autotune:
             tuned[form] = tune.autotune_caf(s, r, tau0, n_tau, p0, n_dop, prec, use_cache=False)
         ws = torch.empty(nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, prec),
                          dtype=torch.uint8, device=dev)

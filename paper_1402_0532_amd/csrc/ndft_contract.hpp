@@ -108,7 +108,11 @@ __device__ __forceinline__ void split_pair(float a, float b, uint32_t &hi, uint3
 {
     bf16x2v h = {(__bf16)a, (__bf16)b};
     hi = __builtin_bit_cast(uint32_t, h);
-    const float ha = __uint_as_float(hi << 16);
+    // the shift is written out so the compiler takes it from the packed word instead of
+    // converting a again
+    uint32_t ha_bits;
+    asm("v_lshlrev_b32 %0, 16, %1" : "=v"(ha_bits) : "v"(hi));
+    const float ha = __uint_as_float(ha_bits);
     const float hb = __uint_as_float(hi & 0xffff0000u);
     bf16x2v l = {(__bf16)(a - ha), (__bf16)(b - hb)};
     lo = __builtin_bit_cast(uint32_t, l);

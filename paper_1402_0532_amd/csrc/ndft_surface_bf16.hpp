@@ -230,17 +230,16 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     }
 
     // ---- lag operand sources: lane (h, l32), column block j: delay d_j ----
-    // sample i = k_begin + off + 2h (+1): s4[i], r4[n + i - d_j] (global: exact-sign repair)
-    const float4 *sp = P.s4 + k_begin + 2 * h;
-    const float4 *rp[WL];
-    // the same samples in the stage window: Ws[i - k0], Wr[i - k0 + (dmax - d_j)]
+    // sample i (pair i, i + 1; i = k0 + 4q + 2h in step q of the stage starting at k0):
+    // s4[i] and r4[n + i - d_j], read from the stage window as Ws[i - k0] and
+    // Wr[i - k0 + (dmax - d_j)]
     const int dmax = P.tau0 + min(c0 + LT - 1, P.n_cols - 1);
-    int roff[WL];
+    int roff[WL], valid0[WL];
 #pragma unroll
     for (int j = 0; j < WL; ++j) {
         const int col = min(c0 + (wave * WL + j) * 32 + l32, P.n_cols - 1); // padding repeats
-        rp[j] = P.r4 + (n - (P.tau0 + col)) + k_begin + 2 * h;
         roff[j] = Cfg::WS + dmax - (P.tau0 + col) + 2 * h;
+        valid0[j] = k_begin + 2 * h + 1 - (P.tau0 + col); // >= -sfirst: pair reaches the delay
     }
     // one load per lane per stage: entry e < WS is s4[k0 + e], else r4[n + k0 - dmax + e - WS]
     // (indices past WIN repeat the last entry and are not stored)
@@ -349,7 +348,10 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     struct BFrag {
         uint4 b1[WL], b2[WL];
     };
-    auto lag_step = [&](In &x, BFrag &f) -> uint32_t {
+    // A lane's pair lies wholly before its delay when i + 1 < d: then r reads the zero
+    // padding, z = 0 exactly and no repair is needed; such lanes are not flagged (i is the
+    // pair's first sample, `sfirst` the step's first sample relative to k_begin).
+    auto lag_step = [&](In &x, BFrag &f, int sfirst) -> uint32_t {
         pin(x.s1);
         pin(x.s2);
 #pragma unroll
@@ -357,24 +359,29 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             pin(x.r1[j]);
             pin(x.r2[j]);
         }
-        uint32_t nzall = 0x80008000u;
+        uint64_t flag = 0; // lanes (as ballots, so the test stays in scalar registers)
 #pragma unroll
-        for (int j = 0; j < WL; ++j) nzall &= lag_pair_operands(x.s1, x.s2, x.r1[j], x.r2[j], f.b1[j], f.b2[j]);
-        return __builtin_amdgcn_ballot_w64(nzall != 0x80008000u) != 0 ? 1u : 0u;
+        for (int j = 0; j < WL; ++j) {
+            const uint32_t nz = lag_pair_operands(x.s1, x.s2, x.r1[j], x.r2[j], f.b1[j], f.b2[j]);
+            flag |= __builtin_amdgcn_ballot_w64((nz & 0x80008000u) != 0x80008000u) &
+                    __builtin_amdgcn_ballot_w64(sfirst + valid0[j] >= 0);
+        }
+        return flag != 0 ? 1u : 0u;
     };
 
-    // Exact-sign repair of the flagged steps of one stage (rare: zero lag components).
-    auto repair = [&](const uint4 *buf, int kst, uint32_t bits) {
+    // Exact-sign repair of the flagged steps of one stage (rare: zero lag components), from
+    // the stage's input window.
+    auto repair = [&](const uint4 *buf, const float4 *w, uint32_t bits) {
         while (bits) {
             const int g = __builtin_ctz(bits);
             bits &= bits - 1;
-            const int off = kst + 4 * g;
-            const float4 s1 = sp[off], s2 = sp[off + 1];
+            In x;
+            read_in(w, x, g);
             BFrag D;
             bool any = false;
 #pragma unroll
             for (int j = 0; j < WL; ++j)
-                any |= lag_pair_sign_fix(s1, s2, rp[j][off], rp[j][off + 1], D.b1[j], D.b2[j]);
+                any |= lag_pair_sign_fix(x.s1, x.s2, x.r1[j], x.r2[j], D.b1[j], D.b2[j]);
             if (__builtin_amdgcn_ballot_w64(any)) {
                 AFrag f;
                 load_a(buf, g, f);
@@ -422,7 +429,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             for (int it = 0; it < TWI; ++it)
                 if ((it * G) / TWI == g + 1) tw_fetch(it);
             __builtin_amdgcn_sched_barrier(0);
-            const uint32_t r = lag_step(in[(g + 1) & 1], fb[(g + 1) & 1]);
+            const uint32_t r = lag_step(in[(g + 1) & 1], fb[(g + 1) & 1], kpair + KST + 4 * (g + 1));
             if (g + 1 < G)
                 rare |= r << (g + 1);
             else
@@ -446,7 +453,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             for (int k = 0; k < PLI; ++k) dst[k * NT] = plv[k];
         }
         win_store(win[CB ^ 1], wv);
-        if (rare) repair(cur, KST, rare);
+        if (rare) repair(cur, curw, rare);
         __syncthreads();
     };
 
@@ -471,14 +478,11 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
         __syncthreads();
         read_in(win[0], in[0], 0);
         read_in(win[0], in[1], 1);
-        rare_next = lag_step(in[0], fb[0]);
+        rare_next = lag_step(in[0], fb[0], 0);
         for (int p = 0; p < npair; ++p) {
             stage(std::integral_constant<int, 0>(), std::integral_constant<int, 0>());
             stage(std::integral_constant<int, 1>(), std::integral_constant<int, KS>());
-            sp += 2 * KS;
             kpair += 2 * KS;
-#pragma unroll
-            for (int j = 0; j < WL; ++j) rp[j] += 2 * KS;
         }
     }
 

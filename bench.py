@@ -75,10 +75,10 @@ def bench_batched(nd, tune, synth, torch, args):
            "cells": cells, "algorithmic_flops": flops}
     for form in ("fp32", "bf16x2"):
         prec = nd.PRECISIONS[form]
-        if args.no_autotune:
-            bp, rec = nd.BatchPlan(descs, prec), None
-        else:
+        if args.autotune:
             bp, rec = tune.autotune_batch(descs, s_pool, r_pool, out, prec)
+        else:
+            bp, rec = nd.BatchPlan(descs, prec), None
         g = torch.cuda.CUDAGraph()
         st = torch.cuda.Stream()
         st.wait_stream(torch.cuda.current_stream())
@@ -148,7 +148,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2", "fp8"])
     ap.add_argument("--forms", default="fp32,bf16x2,fp8", help="forms to time (comma list)")
-    ap.add_argument("--no-autotune", action="store_true", help="use the built-in plan choice")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every plan and split first and use the fastest (default: the library's "
+                         "built-in choice, the plan a caller gets without tuning)")
     ap.add_argument("--plan", action="append", default=[], metavar="FORM=NAME:KSPLIT",
                     help="force a tile plan and split count for a form (no autotuning for it)")
     ap.add_argument("--no-extras", action="store_true",
@@ -201,7 +203,7 @@ def main():
             if not idx:
                 sys.exit("bench.py: no plan %r for form %s" % (name, form))
             nd.set_plan(prec, idx[0], ks)
-        elif not args.no_autotune:
+        elif args.autotune:
             tuned[form] = tune.autotune_caf(s, r, tau0, n_tau, p0, n_dop, prec, use_cache=False)
         ws = torch.empty(nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, prec),
                          dtype=torch.uint8, device=dev)

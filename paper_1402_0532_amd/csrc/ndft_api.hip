@@ -102,8 +102,10 @@ struct Plan {
     const void *kfn[2];      // [PROD_LAG, PROD_IDENTITY]; nullptr: no such form
     const void *kfn_batched; // persistent lag-product kernel
     double cost_scale;       // relative cost per padded cell in the built-in choice
+    double row_cost_cols;    // per padded base row, in cells (the plane builder's pass)
     float sign_scale;        // scale of the input signs the kernels read (1 or 1/2)
     const void *planes_kfn;  // twiddle plane builder (nullptr: twiddles made in the kernel)
+    bool raw_inputs;         // reads complex64 inputs itself (no sign-prep launches)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -123,8 +125,10 @@ Plan make_plan(const char *name)
     p.kfn_batched =
         reinterpret_cast<const void *>(&contract_batched_kernel<PREC, PROD_LAG, WAVES_B, WAVES_L, WB, WL, KS>);
     p.cost_scale = 1.0 + 64.0 / Cfg::BT + 64.0 / Cfg::LT;
+    p.row_cost_cols = 0.0;
     p.sign_scale = 1.0f;
     p.planes_kfn = nullptr;
+    p.raw_inputs = false;
     return p;
 }
 
@@ -147,10 +151,13 @@ Plan make_surface_plan(const char *name)
     p.kfn[1] = nullptr;
     p.kfn_batched =
         PLANES ? nullptr : reinterpret_cast<const void *>(&surface_bf16_batched_kernel<NW, WB, WL, KS, PF>);
-    // lag operands are built once per base tile, twiddles once per delay tile (or once)
-    p.cost_scale = (PLANES ? 0.25 : 0.35) * (1.0 + 24.0 / Cfg::BT + (PLANES ? 0.0 : 8.0 / Cfg::LT));
+    // lag operands are built once per base tile; twiddles once per delay tile (6% more
+    // per cell, measured) or once into planes (a builder pass worth ~100 delay columns)
+    p.cost_scale = 0.25 * (1.0 + 24.0 / Cfg::BT) * (PLANES ? 1.0 : 1.06);
+    p.row_cost_cols = PLANES ? 100.0 : 0.0;
     p.sign_scale = 0.5f;
     p.planes_kfn = PLANES ? reinterpret_cast<const void *>(&plane_build_kernel<Cfg::BT, KS>) : nullptr;
+    p.raw_inputs = true;
     return p;
 }
 
@@ -173,13 +180,11 @@ const std::vector<Plan> &plans(int prec)
         make_plan<PREC_BF16X2, 4, 2, 2, 1, 8>("bf16x2_b256_l64_w8_ks8"),
         make_plan<PREC_BF16X2, 3, 4, 1, 1, 8>("bf16x2_b96_l128_w12_ks8"),
         make_surface_plan<4, 3, 1, 32, 4>("bf16x2r_b96_l128_w4_ks32"),
-        make_surface_plan<4, 2, 2, 32, 2>("bf16x2r_b64_l256_w4_ks32"),
-        make_surface_plan<8, 2, 1, 32, 2>("bf16x2r_b64_l256_w8_ks32"),
         make_surface_plan<4, 3, 1, 16, 4>("bf16x2r_b96_l128_w4_ks16"),
+        make_surface_plan<4, 4, 1, 16, 4>("bf16x2r_b128_l128_w4_ks16"),
         make_surface_plan<4, 3, 1, 16, 4, true>("bf16x2p_b96_l128_w4_ks16"),
         make_surface_plan<4, 3, 1, 32, 4, true>("bf16x2p_b96_l128_w4_ks32"),
-        make_surface_plan<4, 2, 2, 32, 2, true>("bf16x2p_b64_l256_w4_ks32"),
-        make_surface_plan<8, 2, 1, 32, 2, true>("bf16x2p_b64_l256_w8_ks32"),
+        make_surface_plan<4, 4, 1, 16, 4, true>("bf16x2p_b128_l128_w4_ks16"),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -218,7 +223,9 @@ struct Launch {
     int tiles_b, tiles_l;
     int n_bases, n_bases_pad, n_cols_pad;
     int tb, n_coarse, tw_exact;
-    BaseMap bm;
+    BaseMap bm;        // every base, in partial-row order (reduction)
+    BaseMap bm_tile;   // bases of the matrix rows: bm without base 0 when row0 = 1
+    int row0;          // 1: base 0 is summed on the vector units into partial row 0
     size_t part_bytes; // split-K partials
     size_t ws_bytes;   // partials + signed copies of the inputs (+ twiddle planes)
     long long plane_stages; // planes: stage blocks per base tile
@@ -229,20 +236,21 @@ struct Launch {
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Split-K count: minimises the rounds of work-groups over the compute units per unit of
+// tile work, times 1 + k/256 for the partial sums each chunk adds (written, then read by
+// the reduction); the smaller count on ties.
 int pick_ksplit(int tiles, int64_t n, int ks, int cus)
 {
     int max_k = (int)std::max<int64_t>(1, cdiv(n, 8LL * ks)); // at least ~8 stages per chunk
     int best = 1;
-    double best_eff = -1.0;
+    double best_cost = -1.0;
     for (int k = 1; k <= max_k; ++k) {
-        int64_t w = (int64_t)tiles * k;
-        int64_t waves = cdiv(w, cus);
-        double eff = (double)w / (double)(waves * cus);
-        if (eff > best_eff + 0.05) {
-            best_eff = eff;
+        const double rounds = (double)cdiv((int64_t)tiles * k, cus);
+        const double cost = rounds / k * (1.0 + k / 256.0);
+        if (best_cost < 0.0 || cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
             best = k;
         }
-        if (best_eff >= 0.9) break;
     }
     return best;
 }
@@ -271,6 +279,31 @@ void choose_table(int64_t n, int max_bytes, int *tb_out, int *n_coarse_out, int 
     *exact_out = exact;
 }
 
+// Base 0 goes to the vector units (partial row 0) when the register-lag kernels run the
+// lag product, base 0 is in the set and the other bases fill whole tiles: one base would
+// otherwise cost a whole padded tile row.
+int zero_row(const Plan &p, int prod, const BaseMap &bm, int n_bases)
+{
+    return p.raw_inputs && prod == PROD_LAG && bm.nseg > 0 && bm.start[0] == 0 && n_bases > 1 &&
+                   (n_bases - 1) % p.bt == 0
+               ? 1
+               : 0;
+}
+
+BaseMap drop_first_base(const BaseMap &bm)
+{
+    BaseMap r = bm;
+    if (bm.off[1] - bm.off[0] == 1) { // first run is the single base: remove the run
+        r.nseg = bm.nseg - 1;
+        for (int k = 0; k < 4; ++k) r.start[k] = k + 1 < 4 ? bm.start[k + 1] : 0;
+        for (int k = 0; k < 5; ++k) r.off[k] = k + 1 < 5 ? bm.off[k + 1] - 1 : bm.off[4] - 1;
+    } else {
+        r.start[0] = bm.start[0] + 1;
+        for (int k = 1; k < 5; ++k) r.off[k] = bm.off[k] - 1;
+    }
+    return r;
+}
+
 Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
                    int64_t signed_elems)
 {
@@ -292,9 +325,10 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         pi = 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
             if (!ps[k].kfn[prod]) continue;
-            double rows = (double)(cdiv(L.n_bases, ps[k].bt) * ps[k].bt);
+            const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
+            double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
-            double cost = rows * cols * ps[k].cost_scale;
+            double cost = rows * (cols + ps[k].row_cost_cols) * ps[k].cost_scale;
             if (best < 0 || cost < best * 0.999) {
                 best = cost;
                 pi = k;
@@ -302,9 +336,11 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         }
     }
     L.plan = &ps[pi];
-    L.tiles_b = (int)cdiv(L.n_bases, L.plan->bt);
+    L.row0 = zero_row(*L.plan, prod, L.bm, L.n_bases);
+    L.bm_tile = L.row0 ? drop_first_base(L.bm) : L.bm;
+    L.tiles_b = (int)cdiv(L.n_bases - L.row0, L.plan->bt);
     L.tiles_l = (int)cdiv(n_cols, L.plan->lt);
-    L.n_bases_pad = L.tiles_b * L.plan->bt;
+    L.n_bases_pad = L.row0 + L.tiles_b * L.plan->bt;
     L.n_cols_pad = L.tiles_l * L.plan->lt;
     const int gran = L.plan->kgran;
     int max_split = (int)std::max<int64_t>(1, cdiv(n, gran));
@@ -383,7 +419,7 @@ ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, i
 
 ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const float4 *r4, long long col_stride,
                             int64_t n, int64_t n_cols, int64_t tau0, float4 *partial, hipStream_t stream,
-                            uint4 *planes = nullptr)
+                            uint4 *planes = nullptr, const float2 *s_raw = nullptr, const float2 *r_raw = nullptr)
 {
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
@@ -391,12 +427,15 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     std::memset(&P, 0, sizeof(P));
     P.s4 = s4;
     P.r4 = r4;
+    P.s_raw = s_raw;
+    P.r_raw = r_raw;
     P.col_stride = col_stride;
     P.n = (int)n;
     P.n_cols = (int)n_cols;
     P.tau0 = (int)tau0;
-    P.n_bases = L.n_bases;
-    P.bm = L.bm;
+    P.n_bases = L.n_bases - L.row0;
+    P.bm = L.bm_tile;
+    P.row0 = L.row0;
     P.tb = L.tb;
     P.n_coarse = L.n_coarse;
     P.tw_exact = L.tw_exact;
@@ -427,7 +466,7 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
         Q.n_coarse = L.n_coarse;
         Q.tw_exact = L.tw_exact;
         Q.stages_per_block = 16;
-        Q.bm = L.bm;
+        Q.bm = L.bm_tile;
         void *qargs[] = {&Q};
         dim3 qgrid((unsigned)cdiv(L.plane_stages, Q.stages_per_block), (unsigned)L.tiles_b);
         if (hipLaunchKernel(L.plan->planes_kfn, qgrid, dim3(256), qargs, shmem, stream) != hipSuccess)
@@ -632,6 +671,8 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
         R.p0n = (int)mod_n(d.p0, d.n);
         R.n_bins = (int)d.n_dop;
         G.outoff[c] = (long long)d.out_off;
+        C.s_raw_off = (long long)d.surv_off;
+        C.r_raw_off = (long long)d.ref_off;
         G.prep[2 * c] = PrepDesc{(long long)d.surv_off, base ? reinterpret_cast<float4 *>(base + s4_off) : nullptr,
                                  (int)d.n, 0, (long long)(d.n + kTailPad), P.sign_scale};
         G.prep[2 * c + 1] = PrepDesc{(long long)d.ref_off, base ? reinterpret_cast<float4 *>(base + r4_off) : nullptr,
@@ -728,12 +769,15 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     float4 *part = reinterpret_cast<float4 *>(ws);
     float4 *s4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
     float4 *r4 = s4 + n + kTailPad; // n zeros, then the reference, then a zero tail
-    const float g = L.plan->sign_scale;
-    st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, g, s);
-    if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
-    if (st != NDFT_OK) return st;
+    if (!L.plan->raw_inputs) {
+        const float g = L.plan->sign_scale;
+        st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, g, s);
+        if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
+        if (st != NDFT_OK) return st;
+    }
     uint4 *planes = L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
-    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes);
+    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes,
+                         reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref));
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }
@@ -897,12 +941,15 @@ ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool,
     const Plan &P = plans(batch->prec)[batch->plan];
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, hdr);
     if ((st = check_launch()) != NDFT_OK) return st;
-    hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)batch->max_prep_blocks, (unsigned)(2 * batch->n_cpi)),
-                       dim3(256), 0, s, hdr, prep, reinterpret_cast<const float2 *>(surv_pool),
-                       reinterpret_cast<const float2 *>(ref_pool), tag);
-    if ((st = check_launch()) != NDFT_OK) return st;
+    const float2 *pool_s = reinterpret_cast<const float2 *>(surv_pool);
+    const float2 *pool_r = reinterpret_cast<const float2 *>(ref_pool);
+    if (!P.raw_inputs) {
+        hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)batch->max_prep_blocks, (unsigned)(2 * batch->n_cpi)),
+                           dim3(256), 0, s, hdr, prep, pool_s, pool_r, tag);
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
     {
-        void *args[] = {&hdr, &params, &items, &tag, &plan_id};
+        void *args[] = {&hdr, &params, &items, &tag, &plan_id, &pool_s, &pool_r};
         ProfScope prof(s);
         hipError_t e = hipLaunchKernel(P.kfn_batched, dim3((unsigned)batch->grid), dim3((unsigned)P.nt), args,
                                        (size_t)batch->table_bytes, s);

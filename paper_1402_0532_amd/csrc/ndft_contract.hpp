@@ -79,6 +79,16 @@ struct ContractParams {
     const uint4 *planes;
     long long plane_stages;
     int grp_stride;       // block order: tile_l * grp_stride + (tile_b * ksplit + kc)
+    // register-lag surface kernels: 1 when base 0 (twiddle 1 at every sample) is summed on
+    // the vector units of the tiles with tile_b = 0 and stored in partial row 0; the matrix
+    // rows (bm without base 0) then start at row 1
+    int row0;
+    // register-lag surface kernels read the complex64 inputs directly (signs are made
+    // while a stage window is loaded): s_raw[n], r_raw[n]; batched launches set them from
+    // the pools and these offsets
+    const float2 *s_raw;
+    const float2 *r_raw;
+    long long s_raw_off, r_raw_off;
 };
 
 // Pack each complex sample with its exact component signs (read by the producers):

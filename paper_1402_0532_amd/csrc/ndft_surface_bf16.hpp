@@ -41,7 +41,7 @@ namespace ndft {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4))); // plain 16-byte loads/stores
 
 // Scaling. Both operands carry their sign terms as +-2 and their value terms halved:
-// the prep stores input signs as +-1/2 (so every Eq. (1) operator, hence z, comes out
+// the stage windows hold input signs as +-1/2 (so every Eq. (1) operator, hence z, comes out
 // exactly halved) and the fine twiddle table holds W^r / 2. Products Sc' z' = (2 Sc)(z/2)
 // and C' sigma' = (C/2)(2 sigma) are the exact terms. The point is the BF16 pattern of
 // +-2, 0x4000: it is one bit of the rounded high part moved into place.
@@ -180,11 +180,16 @@ struct SurfCfg {
 // precomputed by plane_build_kernel (TW_PLANES).
 enum { TW_GEN = 0, TW_GEN_EXACT = 1, TW_PLANES = 2 };
 
-template <int NW, int WB, int WL, int KS, int PF, int TWM>
+// Z0: this tile also sums base 0 (see ContractParams::row0). With W^0 = 1 every Eq. (6)
+// product is z + csgn z, so the row is the column sum of the lag operands weighted like
+// a twiddle row (2 on the value parts, 1/2 on the sign parts: the scaling above), done
+// with BF16 dot products on the operands the matrix step consumes.
+template <int NW, int WB, int WL, int KS, int PF, int TWM, bool Z0>
 __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const int kc, const int tile_b,
                                                   const int tile_l,
                                                   uint4 (*bufA)[SurfCfg<NW, WB, WL, KS, PF>::STAGE_A],
-                                                  float4 (*win)[SurfCfg<NW, WB, WL, KS, PF>::WIN], float2 *tables)
+                                                  float4 (*win)[SurfCfg<NW, WB, WL, KS, PF>::WIN], float2 *tables,
+                                                  const float2 *s_raw, const float2 *r_raw)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
     constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G;
@@ -195,7 +200,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     static_assert(!PLANES || Cfg::STAGE_A % NT == 0, "plane stages split evenly");
     // vector instructions per slot (lag operands ~45 per column block, a twiddle unit
     // ~35) spread over the slot's matrix instructions
-    constexpr int VALU_PER_MFMA = (45 * WL + 35 * TWI / G + 4 * WB * WL - 1) / (4 * WB * WL);
+    constexpr int VALU_PER_MFMA = (45 * WL + 35 * TWI / G + (Z0 ? 6 * WL : 0) + 4 * WB * WL - 1) / (4 * WB * WL);
 
     float2 *coarse = tables;
     float2 *fine = PLANES ? nullptr : tables + P.n_coarse;
@@ -231,8 +236,8 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
 
     // ---- lag operand sources: lane (h, l32), column block j: delay d_j ----
     // sample i (pair i, i + 1; i = k0 + 4q + 2h in step q of the stage starting at k0):
-    // s4[i] and r4[n + i - d_j], read from the stage window as Ws[i - k0] and
-    // Wr[i - k0 + (dmax - d_j)]
+    // s[i] and r[i - d_j] (zero outside [0, n)), read from the stage window as Ws[i - k0]
+    // and Wr[i - k0 + (dmax - d_j)]
     const int dmax = P.tau0 + min(c0 + LT - 1, P.n_cols - 1);
     int roff[WL], valid0[WL];
 #pragma unroll
@@ -241,20 +246,24 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
         roff[j] = Cfg::WS + dmax - (P.tau0 + col) + 2 * h;
         valid0[j] = k_begin + 2 * h + 1 - (P.tau0 + col); // >= -sfirst: pair reaches the delay
     }
-    // one load per lane per stage: entry e < WS is s4[k0 + e], else r4[n + k0 - dmax + e - WS]
-    // (indices past WIN repeat the last entry and are not stored)
-    auto win_load = [&](int k0, float4 (&wv)[Cfg::WIN_ITERS]) {
+    // One complex64 load per lane per stage: entry e < WS is s[k0 + e], else r[m] with
+    // m = k0 - dmax + e - WS; samples outside [0, n) are zero (r[m < 0] = 0, s past the
+    // record), so the loaded index is clamped and the value replaced. Indices past WIN
+    // repeat the last entry and are not stored. The store adds the half-scaled signs.
+    auto win_load = [&](int k0, float2 (&wv)[Cfg::WIN_ITERS]) {
 #pragma unroll
         for (int it = 0; it < Cfg::WIN_ITERS; ++it) {
             const int e = min(tid + it * NT, Cfg::WIN - 1);
-            const float4 *src = e < Cfg::WS ? P.s4 + k0 + e : P.r4 + (n + k0 - dmax) + (e - Cfg::WS);
-            wv[it] = *src;
+            const bool is_s = e < Cfg::WS;
+            const int idx = is_s ? k0 + e : k0 - dmax + (e - Cfg::WS);
+            const float2 v = (is_s ? s_raw : r_raw)[min(max(idx, 0), n - 1)];
+            wv[it] = (idx >= 0 && idx < n) ? v : make_float2(0.0f, 0.0f);
         }
     };
-    auto win_store = [&](float4 *w, const float4 (&wv)[Cfg::WIN_ITERS]) {
+    auto win_store = [&](float4 *w, const float2 (&wv)[Cfg::WIN_ITERS]) {
 #pragma unroll
         for (int it = 0; it < Cfg::WIN_ITERS; ++it)
-            if (Cfg::WIN % NT == 0 || tid + it * NT < Cfg::WIN) w[tid + it * NT] = wv[it];
+            if (Cfg::WIN % NT == 0 || tid + it * NT < Cfg::WIN) w[tid + it * NT] = with_signs(wv[it], 0.5f);
     };
 
     // planes of this base tile, from the first stage of this chunk
@@ -344,6 +353,23 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             }
     };
 
+    // base-0 row: per column block, U (real lag parts) and X (imaginary), over the lane's
+    // samples; the two halves h are added at the end
+    float z0u[WL], z0x[WL];
+#pragma unroll
+    for (int j = 0; j < WL; ++j) z0u[j] = z0x[j] = 0.0f;
+    const bf16x2v w_val = {(__bf16)2.0f, (__bf16)2.0f}, w_sgn = {(__bf16)0.5f, (__bf16)0.5f};
+    auto dot2 = [](uint32_t v, bf16x2v w, float c) {
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, v), w, c, false);
+    };
+    auto z0_step = [&](const uint4 (&B1)[WL], const uint4 (&B2)[WL]) {
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            z0u[j] = dot2(B1[j].z, w_sgn, dot2(B1[j].y, w_val, dot2(B1[j].x, w_val, z0u[j])));
+            z0x[j] = dot2(B2[j].z, w_sgn, dot2(B2[j].y, w_val, dot2(B2[j].x, w_val, z0x[j])));
+        }
+    };
+
     // Lag operands of one step from its inputs; returns 1 when some lane needs repair.
     struct BFrag {
         uint4 b1[WL], b2[WL];
@@ -386,6 +412,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
                 AFrag f;
                 load_a(buf, g, f);
                 mfma_step(f, D.b1, D.b2);
+                if (Z0) z0_step(D.b1, D.b2); // value parts of D are 0
             }
         }
     };
@@ -408,7 +435,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
         const float4 *curw = win[CB];
         uint32_t rare = rare_next;
         load_a(cur, 0, fa[0]);
-        float4 wv[Cfg::WIN_ITERS]; // next stage's window
+        float2 wv[Cfg::WIN_ITERS]; // next stage's window
         win_load(k_begin + KST + KS + kpair, wv);
         u32x4 plv[PLANES ? PLI : 1]; // next stage's plane block
         if (PLANES) {
@@ -438,6 +465,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             for (int it = 0; it < TWI; ++it)
                 if ((it * G) / TWI == g) tw_finish(nxt, it);
             mfma_step(fa[g & 1], fb[g & 1].b1, fb[g & 1].b2);
+            if (Z0) z0_step(fb[g & 1].b1, fb[g & 1].b2);
             // order inside the slot: each matrix instruction followed by a run of vector
             // instructions (the matrix core works while they issue)
 #pragma unroll
@@ -471,7 +499,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             pl_src += Cfg::STAGE_A;
         }
         {
-            float4 wv[Cfg::WIN_ITERS];
+            float2 wv[Cfg::WIN_ITERS];
             win_load(k_begin, wv);
             win_store(win[0], wv);
         }
@@ -488,6 +516,15 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
 
     // ---- partial sums of this chunk: lane holds rows 8*(e/4) + 4*h + e%4, column l32 ----
     float4 *out = P.partial + (long long)kc * P.n_cols_pad * P.n_bases_pad;
+    if (Z0) {
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            const float u = z0u[j] + __shfl_xor(z0u[j], 32);
+            const float x = z0x[j] + __shfl_xor(z0x[j], 32);
+            const int col = c0 + (wave * WL + j) * 32 + l32;
+            if (h == 0) out[(long long)col * P.n_bases_pad] = make_float4(u, 0.0f, x, 0.0f);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < WB; ++i)
 #pragma unroll
@@ -495,7 +532,7 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             const int col = c0 + (wave * WL + j) * 32 + l32;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int row = b0 + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int row = P.row0 + b0 + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
                 float4 v;
                 v.x = acc[i][j][0][e]; // U = A1.B1
                 v.y = acc[i][j][3][e]; // V = A2.B2
@@ -517,11 +554,22 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_kernel(ContractParams
     int bid = blockIdx.x;
     const int kc = bid % P.ksplit;
     bid /= P.ksplit;
-    if (P.tw_exact)
-        surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, win,
-                                                            tables);
-    else
-        surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN>(P, kc, bid % P.tiles_b, bid / P.tiles_b, bufA, win, tables);
+    const int tile_b = bid % P.tiles_b, tile_l = bid / P.tiles_b;
+    if (P.row0 && tile_b == 0) {
+        if (P.tw_exact)
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, true>(P, kc, tile_b, tile_l, bufA, win, tables,
+                                                                      P.s_raw, P.r_raw);
+        else
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, true>(P, kc, tile_b, tile_l, bufA, win, tables, P.s_raw,
+                                                                P.r_raw);
+    } else {
+        if (P.tw_exact)
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, kc, tile_b, tile_l, bufA, win, tables,
+                                                                       P.s_raw, P.r_raw);
+        else
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, kc, tile_b, tile_l, bufA, win, tables,
+                                                                 P.s_raw, P.r_raw);
+    }
 }
 
 // Twiddle operand from planes. Block order keeps the delay tiles that share a plane
@@ -537,7 +585,13 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_planes_kernel(Contrac
     const int grp = blockIdx.x % P.grp_stride;
     const int tile_l = blockIdx.x / P.grp_stride;
     if (grp >= P.tiles_b * P.ksplit) return;
-    surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES>(P, grp % P.ksplit, grp / P.ksplit, tile_l, bufA, win, nullptr);
+    const int tile_b = grp / P.ksplit;
+    if (P.row0 && tile_b == 0)
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, true>(P, grp % P.ksplit, tile_b, tile_l, bufA, win,
+                                                               nullptr, P.s_raw, P.r_raw);
+    else
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, false>(P, grp % P.ksplit, tile_b, tile_l, bufA, win,
+                                                                nullptr, P.s_raw, P.r_raw);
 }
 
 // Precompute the twiddle planes: thread t of a block owns units (row, pair) t, t + 256,
@@ -589,12 +643,14 @@ __global__ __launch_bounds__(256) void plane_build_kernel(PlaneBuildParams Q)
     }
 }
 
-// Persistent form over a batch (same queue protocol as contract_batched_kernel).
+// Persistent form over a batch (same queue protocol as contract_batched_kernel); the
+// inputs come straight from the pools (no sign-prep pass).
 template <int NW, int WB, int WL, int KS, int PF>
 __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchHeader *hdr,
                                                                           const ContractParams *params,
                                                                           const int4 *items,
-                                                                          unsigned long long tag, int plan_id)
+                                                                          unsigned long long tag, int plan_id,
+                                                                          const float2 *pool_s, const float2 *pool_r)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
     __shared__ uint4 bufA[2][Cfg::STAGE_A];
@@ -611,10 +667,12 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchH
         if (it >= n_items) break;
         const int4 w = items[it];
         const ContractParams P = params[__builtin_amdgcn_readfirstlane(w.x)];
+        const float2 *s_raw = pool_s + P.s_raw_off, *r_raw = pool_r + P.r_raw_off;
         if (P.tw_exact)
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT>(P, w.w, w.y, w.z, bufA, win, tables);
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, w.w, w.y, w.z, bufA, win, tables, s_raw,
+                                                                       r_raw);
         else
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN>(P, w.w, w.y, w.z, bufA, win, tables);
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, w.w, w.y, w.z, bufA, win, tables, s_raw, r_raw);
     }
 }
 

@@ -51,6 +51,7 @@ def _store(key: str, value: dict) -> None:
 
 def _time(fn, reps: int) -> float:
     fn()
+    fn()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -67,7 +68,7 @@ def caf_key(prec, n, tau0, n_tau, p0, n_dop) -> str:
 
 
 def autotune_caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
-                 prec=0, reps: int = 5, splits=None, use_cache: bool = True) -> dict:
+                 prec=0, reps: int = 10, splits=None, use_cache: bool = True) -> dict:
     """Best (plan, ksplit) for this surface; applies it with set_plan and returns it."""
     p = _prec(prec)
     n = s.shape[0]
@@ -82,7 +83,9 @@ def autotune_caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: in
     for plan in range(plan_count(p)):
         set_plan(p, plan, 0)
         _, ks0 = get_plan(p, n, n_tau, p0, n_dop)
-        cands = sorted(set(splits or [ks0, max(1, ks0 // 2), 2 * ks0]))
+        # the library's count (a cost model of the rounds over the compute units), its
+        # neighbours and half / double of it
+        cands = sorted(set(splits or [ks0, max(1, ks0 - 1), ks0 + 1, max(1, ks0 // 2), 2 * ks0]))
         for ks in cands:
             set_plan(p, plan, ks)
             try:

@@ -5,7 +5,8 @@ forced here (ndft_set_plan, with split-K counts) over shapes that reach its code
 powers of two and odd lengths, N = 2 mod 4, a length whose twiddle table cannot be made
 exact at the quadrant points (integer sign path), ragged delay and bin tiles, ragged
 sample chunks, exact zeros and lag products whose FP32 value cancels to 0 while the exact
-value does not (the exact-sign repair of the register-lag kernels), and batches.
+value does not (the exact-sign repair of the register-lag kernels), base sets of one
+tile multiple plus base 0 (which those kernels sum on the vector units), and batches.
 Tolerance as in test_gpu_parity (l1-relative per output; exact zeros where the scale is 0).
 """
 import numpy as np
@@ -62,6 +63,8 @@ SHAPES = [
     (65540, 0, 3, -2, 5, 2, "gauss"),          # quadrant points off the table grid
     (1200, 0, 40, -30, 64, 5, "cancel"),       # FP32 cancellation, zeros
     (17, 0, 17, 0, 17, 0, "int_zeros"),        # shorter than one stage
+    (4096, 5, 200, -128, 256, 0, "gauss"),     # 129 bases: base 0 apart for 64/128-row tiles
+    (1200, 0, 40, -96, 192, 5, "cancel"),      # 97 bases: base 0 apart for 96-row tiles
 ]
 
 _ORACLE = {}

@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "fp8": 5000.0}  # dense MFMA peaks, MI355X
 KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_contract.hpp",
                   "paper_1402_0532_amd/csrc/ndft_device.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_surface_bf16.hpp"]
+                  "paper_1402_0532_amd/csrc/ndft_surface_bf16.hpp",
+                  "paper_1402_0532_amd/csrc/ndft_signsplit.hpp"]
 TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
 
 

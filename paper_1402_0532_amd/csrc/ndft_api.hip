@@ -17,6 +17,7 @@
 #include "ndft_backward.hpp"
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
+#include "ndft_signsplit.hpp"
 #include "ndft_surface_bf16.hpp"
 
 using namespace ndft;
@@ -106,6 +107,8 @@ struct Plan {
     float sign_scale;        // scale of the input signs the kernels read (1 or 1/2)
     const void *planes_kfn;  // twiddle plane builder (nullptr: twiddles made in the kernel)
     bool raw_inputs;         // reads complex64 inputs itself (no sign-prep launches)
+    const void *lag_kfn;     // sign-split plans: the lag / twiddle-sign kernel (lsum_kernel)
+    int stage_a;             // plane uint4 per stage (plane plans)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -129,6 +132,8 @@ Plan make_plan(const char *name)
     p.sign_scale = 1.0f;
     p.planes_kfn = nullptr;
     p.raw_inputs = false;
+    p.lag_kfn = nullptr;
+    p.stage_a = 0;
     return p;
 }
 
@@ -158,6 +163,37 @@ Plan make_surface_plan(const char *name)
     p.sign_scale = 0.5f;
     p.planes_kfn = PLANES ? reinterpret_cast<const void *>(&plane_build_kernel<Cfg::BT, KS>) : nullptr;
     p.raw_inputs = true;
+    p.lag_kfn = nullptr;
+    p.stage_a = Cfg::STAGE_A;
+    return p;
+}
+
+// Sign-split split-BF16 plans: lsum_kernel (twiddle-sign part, lag sign codes, base 0) and
+// dsum_kernel (twiddles against the lag signs) over twiddle planes.
+template <int NW, int WB, int KS>
+Plan make_split_plan(const char *name)
+{
+    using Cfg = DsumCfg<NW, WB, KS>;
+    Plan p;
+    p.name = name;
+    p.bt = Cfg::BT;
+    p.lt = Cfg::LT;
+    p.ks = KS;
+    p.nt = Cfg::NT;
+    p.kgran = 2 * KS;
+    p.static_lds = 2 * Cfg::STAGE_A * 16;
+    p.kfn[0] = reinterpret_cast<const void *>(&dsum_kernel<NW, WB, KS>);
+    p.kfn[1] = nullptr;
+    p.kfn_batched = nullptr;
+    // half the matrix work of the combined form; the twiddle-sign part costs in proportion
+    // to the sign runs (see split_cost)
+    p.cost_scale = 0.25 * (1.0 + 24.0 / Cfg::BT) * 0.5;
+    p.row_cost_cols = 50.0;
+    p.sign_scale = 0.5f;
+    p.planes_kfn = reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
+    p.raw_inputs = true;
+    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel);
+    p.stage_a = Cfg::STAGE_A;
     return p;
 }
 
@@ -185,6 +221,8 @@ const std::vector<Plan> &plans(int prec)
         make_surface_plan<4, 3, 1, 16, 4, true>("bf16x2p_b96_l128_w4_ks16"),
         make_surface_plan<4, 3, 1, 32, 4, true>("bf16x2p_b96_l128_w4_ks32"),
         make_surface_plan<4, 4, 1, 16, 4, true>("bf16x2p_b128_l128_w4_ks16"),
+        make_split_plan<4, 4, 32>("bf16x2s_b128_l128_w4_ks32"),
+        make_split_plan<4, 3, 32>("bf16x2s_b96_l128_w4_ks32"),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -226,6 +264,10 @@ struct Launch {
     BaseMap bm;        // every base, in partial-row order (reduction)
     BaseMap bm_tile;   // bases of the matrix rows: bm without base 0 when row0 = 1
     int row0;          // 1: base 0 is summed on the vector units into partial row 0
+    int ksT;           // sign-split: lsum_kernel chunks (partial planes after the ksplit ones)
+    long long kchunkT; // sign-split: samples per lsum_kernel chunk
+    long long k_codes; // sign-split: samples covered by the sign codes (n rounded up)
+    size_t code_off;   // sign-split: offset of the sign codes in the workspace
     size_t part_bytes; // split-K partials
     size_t ws_bytes;   // partials + signed copies of the inputs (+ twiddle planes)
     long long plane_stages; // planes: stage blocks per base tile
@@ -279,11 +321,20 @@ void choose_table(int64_t n, int max_bytes, int *tb_out, int *n_coarse_out, int 
     *exact_out = exact;
 }
 
+// Largest base of a base map (bases ascend).
+int max_base(const BaseMap &bm, int n_bases)
+{
+    if (bm.nseg == 0) return 0;
+    const int k = bm.nseg - 1;
+    return bm.start[k] + (n_bases - bm.off[k]) - 1;
+}
+
 // Base 0 goes to the vector units (partial row 0) when the register-lag kernels run the
 // lag product, base 0 is in the set and the other bases fill whole tiles: one base would
 // otherwise cost a whole padded tile row.
 int zero_row(const Plan &p, int prod, const BaseMap &bm, int n_bases)
 {
+    if (p.lag_kfn) return bm.nseg > 0 && bm.start[0] == 0 ? 1 : 0; // base 0 always apart
     return p.raw_inputs && prod == PROD_LAG && bm.nseg > 0 && bm.start[0] == 0 && n_bases > 1 &&
                    (n_bases - 1) % p.bt == 0
                ? 1
@@ -302,6 +353,14 @@ BaseMap drop_first_base(const BaseMap &bm)
         for (int k = 1; k < 5; ++k) r.off[k] = bm.off[k] - 1;
     }
     return r;
+}
+
+// lsum_kernel base groups (blockIdx.z): kLsumBases base rows each, after row 0 when base 0
+// is present (summed apart)
+int64_t lsum_groups(const Launch &L)
+{
+    const int has0 = L.bm.nseg > 0 && L.bm.start[0] == 0;
+    return std::max<int64_t>(1, cdiv(L.n_bases - has0, kLsumBases));
 }
 
 Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
@@ -325,6 +384,9 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         pi = 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
             if (!ps[k].kfn[prod]) continue;
+            // sign-split: the twiddle-sign part walks ~4 b C / N sign runs per base b and
+            // chunk of C samples; taken only while that stays about one per chunk
+            if (ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
             const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
             double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
@@ -344,19 +406,35 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     L.n_cols_pad = L.tiles_l * L.plan->lt;
     const int gran = L.plan->kgran;
     int max_split = (int)std::max<int64_t>(1, cdiv(n, gran));
-    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, gran, device_cu_count());
+    const int cus = device_cu_count();
+    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, gran, cus);
     L.kchunk = (int)(cdiv(cdiv(n, L.ksplit), gran) * gran);
     L.ksplit = (int)cdiv(n, L.kchunk); // no empty chunks
+    if (L.tiles_b == 0) L.ksplit = 0;  // sign-split with base 0 only: no matrix part
     choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
-    L.part_bytes = align256((size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad * sizeof(float4));
+    if (L.plan->lag_kfn) {
+        // lsum_kernel: blocks of kLsumDelays delays x kLsumBases bases x a sample range of
+        // whole chunks; about two blocks per compute unit
+        L.k_codes = cdiv(n, kLsumChunk) * kLsumChunk;
+        const int64_t nck = L.k_codes / kLsumChunk;
+        const int64_t blocks = cdiv(n_cols, kLsumDelays) * lsum_groups(L);
+        int64_t ks = std::min<int64_t>(nck, std::max<int64_t>(1, cdiv(2LL * cus, blocks)));
+        L.kchunkT = cdiv(nck, ks) * kLsumChunk;
+        L.ksT = (int)cdiv(L.k_codes, L.kchunkT);
+    }
+    L.part_bytes = align256((size_t)(L.ksplit + L.ksT) * L.n_cols_pad * L.n_bases_pad * sizeof(float4));
     L.ws_bytes = L.part_bytes + align256((size_t)signed_elems * sizeof(float4));
     if (L.plan->planes_kfn) {
         // every stage a chunk can reach, the one after the last included (prefetch)
-        L.plane_stages = 2 * cdiv(n, 2LL * L.plan->ks) + 1;
-        L.plane_bytes = align256((size_t)L.tiles_b * L.plane_stages * L.plan->bt * L.plan->ks * sizeof(uint4));
+        L.plane_stages = L.plan->lag_kfn ? L.k_codes / L.plan->ks + 1 : 2 * cdiv(n, 2LL * L.plan->ks) + 1;
+        L.plane_bytes = align256((size_t)L.tiles_b * L.plane_stages * L.plan->stage_a * sizeof(uint4));
         L.plane_off = L.ws_bytes;
         L.ws_bytes += L.plane_bytes;
         L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
+    }
+    if (L.plan->lag_kfn) {
+        L.code_off = L.ws_bytes;
+        L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
     }
     return L;
 }
@@ -481,13 +559,90 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     return check_launch();
 }
 
+// Sign-split form: twiddle planes, lsum_kernel (twiddle-sign part, sign codes, base 0),
+// dsum_kernel (twiddles against the lag signs); the reduction follows.
+ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t n_cols,
+                         int64_t tau0, float4 *partial, void *ws, hipStream_t stream)
+{
+    std::call_once(g_attr_once, set_kernel_attributes);
+    if (g_attr_err != hipSuccess) return NDFT_E_HIP;
+    uint32_t *codes = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + L.code_off);
+    uint4 *planes = reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off);
+    const size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
+    if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED;
+    if (L.tiles_b > 0) {
+        DplaneParams Q;
+        std::memset(&Q, 0, sizeof(Q));
+        Q.planes = planes;
+        Q.plane_stages = L.plane_stages;
+        Q.n = (int)n;
+        Q.tb = L.tb;
+        Q.n_coarse = L.n_coarse;
+        Q.stages_per_block = 16;
+        Q.bm = L.bm_tile;
+        void *qargs[] = {&Q};
+        dim3 qgrid((unsigned)cdiv(L.plane_stages, Q.stages_per_block), (unsigned)L.tiles_b);
+        if (hipLaunchKernel(L.plan->planes_kfn, qgrid, dim3(256), qargs, shmem, stream) != hipSuccess)
+            return NDFT_E_HIP;
+    }
+    {
+        LsumParams T;
+        std::memset(&T, 0, sizeof(T));
+        T.s = surv;
+        T.r = ref;
+        T.n = (int)n;
+        T.n_cols = (int)n_cols;
+        T.tau0 = (int)tau0;
+        T.bm = L.bm;
+        T.n_bases = L.n_bases;
+        T.n_bases_pad = L.n_bases_pad;
+        T.n_cols_pad = L.n_cols_pad;
+        T.kchunk = L.kchunkT;
+        T.k_end = L.k_codes;
+        T.codes = codes;
+        T.part = partial + (size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad;
+        void *targs[] = {&T};
+        dim3 tgrid((unsigned)cdiv(n_cols, kLsumDelays), (unsigned)L.ksT, (unsigned)lsum_groups(L));
+        if (hipLaunchKernel(L.plan->lag_kfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
+    }
+    ndft_status st = check_launch();
+    if (st != NDFT_OK || L.tiles_b == 0) return st;
+    ContractParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.n = (int)n;
+    P.n_cols = (int)n_cols;
+    P.tau0 = (int)tau0;
+    P.n_bases = L.n_bases - L.row0;
+    P.bm = L.bm_tile;
+    P.row0 = L.row0;
+    P.kchunk = L.kchunk;
+    P.ksplit = L.ksplit;
+    P.tiles_b = L.tiles_b;
+    P.tiles_l = L.tiles_l;
+    P.n_bases_pad = L.n_bases_pad;
+    P.n_cols_pad = L.n_cols_pad;
+    P.partial = partial;
+    P.planes = planes;
+    P.plane_stages = L.plane_stages;
+    P.grp_stride = L.grp_stride;
+    const uint32_t *ccodes = codes;
+    long long code_stages = L.k_codes / 32;
+    void *args[] = {&P, &ccodes, &code_stages};
+    ProfScope prof(stream);
+    hipError_t e = hipLaunchKernel(L.plan->kfn[PROD_LAG], dim3((unsigned)((int64_t)L.tiles_l * L.grp_stride)),
+                                   dim3((unsigned)L.plan->nt), args, 0, stream);
+    prof.stop();
+    if (e != hipSuccess) return NDFT_E_HIP;
+    return check_launch();
+}
+
 ndft_status launch_reduce(const Launch &L, const float4 *partial, int64_t n, int64_t n_cols, int64_t p0,
                           int64_t n_bins, float2 *out, hipStream_t stream)
 {
     ReduceParams R;
     std::memset(&R, 0, sizeof(R));
     R.partial = partial;
-    R.ksplit = L.ksplit;
+    R.ksplit = L.ksplit + L.ksT; // sign-split: lsum_kernel's planes follow the matrix ones
     R.n_cols_pad = L.n_cols_pad;
     R.n_bases_pad = L.n_bases_pad;
     R.n_cols = (int)n_cols;
@@ -775,9 +930,15 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
         if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
         if (st != NDFT_OK) return st;
     }
-    uint4 *planes = L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
-    st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes,
-                         reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref));
+    if (L.plan->lag_kfn) {
+        st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
+                          tau0, part, ws, s);
+    } else {
+        uint4 *planes =
+            L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
+        st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes,
+                             reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref));
+    }
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }

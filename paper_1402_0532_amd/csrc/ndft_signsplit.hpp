@@ -1,0 +1,517 @@
+// Sign-split form of the split-BF16 cross-ambiguity surface (Eq. (12a)).
+//
+// With the complex operator of Eq. (6) written as a (x) b = csgn(a) b + a csgn(b) (plain
+// complex products), every term of A(d, p) = sum_k z_k (x) W^{pk} (z_k the lag product of
+// delay d, W = e^{-2 pi j / N}) splits into two sums:
+//   T(d, p) = sum_k csgn(W^{pk}) z_k   -- the twiddle signs, ternary and piecewise constant
+//                                         in k (they change where pk mod N crosses a
+//                                         multiple of N/4), against the FP32 lag values;
+//   D(d, p) = sum_k W^{pk} csgn(z_k)   -- the twiddles against the exact lag signs.
+// T is evaluated run by run from prefix sums of z over chunks of samples (lsum_kernel, on
+// the vector units: a handful of runs per base and chunk instead of one term per sample);
+// D is a contraction on the matrix cores (dsum_kernel) of BF16 hi + lo twiddles against
+// the lag signs, which lsum_kernel writes as 2-bit codes. Half the matrix work of the
+// combined form, and no lag arithmetic in the matrix loop. Base 0 (twiddle 1) is done
+// entirely in lsum_kernel: its D part is the plain sum of the signs.
+//
+// Both kernels write float4 (U, V, X, Y) partial planes of the same layout, so one
+// reduction adds them: A[+b] = (U - V, X + Y), A[-b] = (U + V, X - Y) with
+//   U = sum Re(c) Re(v), V = sum Im(c) Im(v), X = sum Re(c) Im(v), Y = sum Im(c) Re(v)
+// for the coefficient c (csgn W or W) and the value v (z or csgn z) of each part.
+#pragma once
+
+#include "ndft_contract.hpp"
+#include "ndft_device.hpp"
+#include "ndft_surface_bf16.hpp"
+
+namespace ndft {
+
+// ------------------------------------------------------------------------------------
+// lag signs as codes
+// ------------------------------------------------------------------------------------
+// One 32-bit word per (delay, 4 consecutive samples k0..k3): two bits (sign, non-zero) per
+// sign, placed so that masking the word (after a shift by 0, 2, 4, 6) gives the BF16 pair
+// of +-2 / 0 sign operands directly: sign re of k0 at bits 15:14, k1 at 31:30, k2 at
+// 13:12, k3 at 29:28; sign im of k0 at 11:10, k1 at 27:26, k2 at 9:8, k3 at 25:24.
+// Layout: [32-sample stage][delay column (padded)][half h][step q] words, where the word
+// (h, q) covers samples stage*32 + 8q + 4h + 0..3 (the samples lane half h of a matrix
+// step q consumes).
+__device__ __forceinline__ uint32_t sign_field(float s)
+{
+    return s == 0.0f ? 0u : (s < 0.0f ? 3u : 1u);
+}
+
+// ------------------------------------------------------------------------------------
+// twiddle-sign runs
+// ------------------------------------------------------------------------------------
+// csgn(W^m) for m = b k mod N from the quarter of m: q = floor(4m / N) and whether m is
+// exactly q N / 4 (then one of the parts is exactly 0):
+//   q = 0: (+1, -1), exact (+1,  0)      q = 2: (-1, +1), exact (-1,  0)
+//   q = 1: (-1, -1), exact ( 0, -1)      q = 3: (+1, +1), exact ( 0, +1)
+// Re from cos(2 pi m / N), Im from -sin(2 pi m / N).
+struct SignRun {
+    float sc, st;
+    int len; // samples until the quarter (or the exact point) changes, >= 1; capped at cap + 1
+};
+
+// rinv = 1 / (4 b) rounded; the quotient is only needed up to cap <= 2^12, where the
+// float estimate is within one of the exact ceiling and one check on each side fixes it.
+__device__ __forceinline__ SignRun sign_run(unsigned m, unsigned b, unsigned n, float rinv, unsigned cap)
+{
+    const unsigned m4 = 4u * m; // < 4 N <= 2^26
+    const unsigned q = (m4 >= n) + (m4 >= 2u * n) + (m4 >= 3u * n);
+    const bool exact = m4 == q * n;
+    SignRun r;
+    r.sc = (q == 0 || q == 3) ? 1.0f : -1.0f;
+    r.st = q < 2 ? -1.0f : 1.0f;
+    if (exact) {
+        if (q & 1) r.sc = 0.0f;
+        else r.st = 0.0f;
+    }
+    if (b == 0) {
+        r.len = (int)cap + 1; // m stays 0
+    } else if (exact) {
+        r.len = 1;
+    } else {
+        // first sample with 4 m >= (q + 1) N: ceil(num / den)
+        const unsigned num = (q + 1u) * n - m4, den = 4u * b;
+        if ((unsigned long long)num > (unsigned long long)cap * den) {
+            r.len = (int)cap + 1;
+        } else {
+            unsigned j = (unsigned)((float)num * rinv);
+            j += j * den < num;
+            j -= j > 1u && (j - 1u) * den >= num;
+            r.len = (int)j;
+        }
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------------------------
+// lsum_kernel: lag products, sign codes and the T part (plus base 0 entirely)
+// ------------------------------------------------------------------------------------
+struct LsumParams {
+    const float2 *s, *r;      // complex64 inputs, n samples each
+    int n, n_cols, tau0;
+    BaseMap bm;               // every base, in partial-row order
+    int n_bases;
+    int n_bases_pad, n_cols_pad; // partial plane layout
+    long long kchunk;         // samples per block (multiple of the chunk), k range of blockIdx.y
+    long long k_end;          // samples covered by the codes (n rounded up to the chunk)
+    uint32_t *codes;          // sign codes, see above
+    float4 *part;             // this kernel's partial planes: [blockIdx.y][n_cols_pad][n_bases_pad]
+};
+
+constexpr int kLsumDelays = 16;   // delays per block
+constexpr int kLsumChunk = 256;   // samples per chunk (prefix sums in LDS)
+constexpr int kLsumBases = 256;   // base rows per block
+
+// LDS index with one pad entry per 16: a thread works on 16 consecutive samples, so the
+// lanes of a wave access entries 16 apart; the pad spreads them over the banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// Blocks: blockIdx.x = 16 delays, blockIdx.y = range of whole chunks, blockIdx.z = 256
+// base rows (after row 0 when base 0 is present: base 0 is summed apart from the chunk
+// totals by one thread per delay). For the run sums a thread takes 8 of the delays and two
+// base rows i and M - 1 - i of the group's M rows: the rows ascend in b and the runs per
+// chunk grow with b, so every thread walks about as many runs as any other.
+__global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
+{
+    constexpr int DT = kLsumDelays, C = kLsumChunk;
+    constexpr int SPT = DT * C / 256; // samples per thread
+    static_assert(SPT == 16, "four code words per thread");
+    constexpr int RW = C + DT - 1;
+    constexpr int WIN = C + RW;                   // window entries (s, then r)
+    constexpr int WIT = (WIN + 255) / 256;        // window loads per thread
+    __shared__ float4 sw[C + C / 16];             // s with signs (padded index)
+    __shared__ float4 rw[RW + RW / 16 + 1];       // r with signs, the block's delays
+    __shared__ float2 pre[DT][C + 1 + (C + 1) / 16 + 1]; // prefix sums of z within the chunk
+
+    const int tid = threadIdx.x;
+    const int n = L.n;
+    const int c0 = blockIdx.x * DT;
+    const int dmin = L.tau0 + c0;
+    const long long kb = (long long)blockIdx.y * L.kchunk;
+    const long long ke = min(kb + L.kchunk, L.k_end);
+
+    // z work: delay dl, samples o0 .. o0 + 15 of the chunk
+    const int dl = tid >> 4, grp = tid & 15, o0 = grp * SPT;
+    const int col = c0 + dl;
+
+    // base work: delays dh * 8 .. + 7, base rows i and M - 1 - i of the group
+    constexpr int DH = DT / 2;
+    const int has0 = L.bm.nseg > 0 && L.bm.start[0] == 0;
+    const int row_base = has0 + blockIdx.z * kLsumBases;
+    const int M = min(kLsumBases, L.n_bases - row_base);
+    const int pi = tid & 127, dh = tid >> 7;
+    int bi[2];
+    bool own[2];
+    unsigned bb[2], mc[2], dmc[2];
+    float rinv[2];
+    bi[0] = row_base + pi;
+    bi[1] = row_base + M - 1 - pi;
+    own[0] = pi < M && pi <= M - 1 - pi;
+    own[1] = pi < M - 1 - pi;
+    float acc[2][DH][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const unsigned b = (unsigned)base_of(L.bm, min(max(bi[j], 0), L.n_bases - 1));
+        bb[j] = b;
+        rinv[j] = b > 0 ? 1.0f / (float)(4 * b) : 0.0f;
+        mc[j] = (unsigned)(((long long)b * kb) % n);
+        dmc[j] = (unsigned)(((long long)b * C) % n);
+#pragma unroll
+        for (int d = 0; d < DH; ++d)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[j][d][t] = 0.0f;
+    }
+    float u0 = 0.0f, x0 = 0.0f; // base 0 of delay dl (grp = 0)
+
+    // windows of a chunk (zero outside [0, n)): s[k0 + i], then r[k0 - dmax + i]
+    auto win_load = [&](long long k0, float2 (&v)[WIT]) {
+#pragma unroll
+        for (int it = 0; it < WIT; ++it) {
+            const int i = tid + it * 256;
+            const long long idx = i < C ? k0 + i : k0 - (dmin + DT - 1) + (i - C);
+            v[it] = make_float2(0.0f, 0.0f);
+            if (i < WIN && idx >= 0 && idx < n) v[it] = (i < C ? L.s : L.r)[idx];
+        }
+    };
+    auto win_store = [&](const float2 (&v)[WIT]) {
+#pragma unroll
+        for (int it = 0; it < WIT; ++it) {
+            const int i = tid + it * 256;
+            if (i < C)
+                sw[lpad(i)] = with_signs(v[it]);
+            else if (i < WIN)
+                rw[lpad(i - C)] = with_signs(v[it]);
+        }
+    };
+
+    {
+        float2 v[WIT];
+        win_load(kb, v);
+        win_store(v);
+    }
+    __syncthreads();
+    for (long long k0 = kb; k0 < ke; k0 += C) {
+        float2 nv[WIT]; // next chunk's window, in flight during this chunk
+        if (k0 + C < ke) win_load(k0 + C, nv);
+
+        // ---- lag products of (dl, o0 .. o0 + 15): values, exact signs, codes ----
+        float zr[SPT], zi[SPT];
+        uint32_t code[4] = {0u, 0u, 0u, 0u};
+        float ssr = 0.0f, ssi = 0.0f;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const Lag z = lag_product4(sw[lpad(o0 + j)], rw[lpad(o0 + j + (DT - 1 - dl))]);
+            zr[j] = z.zr;
+            zi[j] = z.zi;
+            ssr += z.sr;
+            ssi += z.si;
+            const int w = j >> 2, e = j & 3;
+            const int pos_r = (e & 1) ? 30 - 2 * (e >> 1) : 14 - 2 * (e >> 1); // k0:14 k1:30 k2:12 k3:28
+            code[w] |= sign_field(z.sr) << pos_r;
+            code[w] |= sign_field(z.si) << (pos_r - 4);
+        }
+        if (col < L.n_cols_pad) {
+            const long long k = k0 + o0; // 16-aligned: the words (h, q) and (h, q + 1)
+            const long long st = k >> 5;
+            const int q = (int)((k >> 3) & 3);
+            uint2 *cw = reinterpret_cast<uint2 *>(L.codes + ((st * L.n_cols_pad + col) * 2) * 4 + q);
+            cw[0] = make_uint2(code[0], code[2]); // h = 0: steps q, q + 1
+            cw[2] = make_uint2(code[1], code[3]); // h = 1
+        }
+        // prefix sums: within the thread, then across the 16 threads of the delay
+        float pr = 0.0f, pi = 0.0f;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            pr += zr[j];
+            pi += zi[j];
+            zr[j] = pr;
+            zi[j] = pi;
+        }
+        float er = pr, ei = pi; // inclusive scan of the thread totals
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const float ur = __shfl_up(er, off, 16), ui = __shfl_up(ei, off, 16);
+            if (grp >= off) {
+                er += ur;
+                ei += ui;
+            }
+        }
+        const float tr = __shfl(er, 15, 16), ti = __shfl(ei, 15, 16); // chunk totals
+        er -= pr; // exclusive
+        ei -= pi;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) pre[dl][lpad(o0 + j + 1)] = make_float2(er + zr[j], ei + zi[j]);
+        if (grp == 0) pre[dl][0] = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            ssr += __shfl_xor(ssr, off, 16);
+            ssi += __shfl_xor(ssi, off, 16);
+        }
+        // base 0: W = 1, so the T part is the chunk total of z and the D part that of the signs
+        if (grp == 0) {
+            u0 += tr + ssr;
+            x0 += ti + ssi;
+        }
+        __syncthreads(); // prefix sums complete; the windows are free again
+
+        if (k0 + C < ke) win_store(nv);
+
+        // ---- T part: runs of constant twiddle signs within the chunk ----
+        // sum_runs S_r (P(e_r) - P(e_{r-1})) = S_last P(C) + sum_{inner ends} (S_r - S_{r+1}) P(e_r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (__builtin_amdgcn_ballot_w64(own[j]) == 0) continue;
+            unsigned m = mc[j];
+            SignRun rr = sign_run(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
+            int o = rr.len;
+            while (o < C) { // run ends at o inside the chunk
+                const unsigned mn = m + (unsigned)rr.len * bb[j]; // < 2 N: the run ends in the next quarter
+                m = mn >= (unsigned)n ? mn - (unsigned)n : mn;
+                const SignRun nx = sign_run(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
+                const float dc = rr.sc - nx.sc, dt = rr.st - nx.st;
+#pragma unroll
+                for (int d = 0; d < DH; ++d) {
+                    const float2 p = pre[dh * DH + d][lpad(o)];
+                    acc[j][d][0] = fmaf(dc, p.x, acc[j][d][0]); // U
+                    acc[j][d][2] = fmaf(dc, p.y, acc[j][d][2]); // X
+                    acc[j][d][3] = fmaf(dt, p.x, acc[j][d][3]); // Y
+                    acc[j][d][1] = fmaf(dt, p.y, acc[j][d][1]); // V
+                }
+                rr = nx;
+                o += rr.len;
+            }
+#pragma unroll
+            for (int d = 0; d < DH; ++d) {
+                const float2 p = pre[dh * DH + d][lpad(C)];
+                acc[j][d][0] = fmaf(rr.sc, p.x, acc[j][d][0]);
+                acc[j][d][2] = fmaf(rr.sc, p.y, acc[j][d][2]);
+                acc[j][d][3] = fmaf(rr.st, p.x, acc[j][d][3]);
+                acc[j][d][1] = fmaf(rr.st, p.y, acc[j][d][1]);
+            }
+            mc[j] = (unsigned)add_mod((int)mc[j], (int)dmc[j], n);
+        }
+        __syncthreads(); // next window stored, prefix sums read
+    }
+
+    float4 *out = L.part + (long long)blockIdx.y * L.n_cols_pad * L.n_bases_pad;
+    if (has0 && blockIdx.z == 0 && grp == 0 && col < L.n_cols)
+        out[(long long)col * L.n_bases_pad] = make_float4(u0, 0.0f, x0, 0.0f);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (!own[j]) continue;
+#pragma unroll
+        for (int d = 0; d < DH; ++d) {
+            const int c = c0 + dh * DH + d;
+            if (c < L.n_cols)
+                out[(long long)c * L.n_bases_pad + bi[j]] =
+                    make_float4(acc[j][d][0], acc[j][d][1], acc[j][d][2], acc[j][d][3]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// dsum_kernel: D part on the matrix cores
+// ------------------------------------------------------------------------------------
+// Per 8-sample step, lane (h, l32) of base block i holds the twiddle operand
+// [hi(k0..k3), lo(k0..k3)] of Re W / 2 (A1) or Im W / 2 (A2) for base row 32 i + l32 and
+// samples k0..k3 = step start + 4 h + 0..3, and the sign operand [s(k0..k3), s(k0..k3)]
+// (+-2 / 0) of its delay column: U = A1.B1, X = A1.B2, Y = A2.B1, V = A2.B2 with B1 from
+// the real signs, B2 from the imaginary ones.
+template <int NW, int WB, int KS>
+struct DsumCfg {
+    static constexpr int NT = 64 * NW;
+    static constexpr int BT = 32 * WB;
+    static constexpr int LT = 32 * NW;
+    static constexpr int G = KS / 8;             // 8-sample steps per stage
+    static constexpr int STAGE_A = G * 4 * BT;   // uint4 per stage (step, A1/A2, h, row)
+    static_assert(KS == 32, "one code stage per stage");
+};
+
+struct DplaneParams {
+    uint4 *planes;
+    long long plane_stages;
+    int n, tb, n_coarse;
+    int stages_per_block;
+    BaseMap bm;
+};
+
+// Twiddle planes of the D part: [base tile][stage][step][A1/A2][h][row] uint4, W / 2 in
+// BF16 hi + lo.
+template <int BT, int KS>
+__global__ __launch_bounds__(256) void dplane_build_kernel(DplaneParams Q)
+{
+    extern __shared__ float2 tables[];
+    constexpr int G = KS / 8;
+    constexpr int STAGE_A = G * 4 * BT;
+    constexpr int UNITS = G * 2 * BT; // (step, h, row): four samples, both operands
+    float2 *coarse = tables;
+    float2 *fine = tables + Q.n_coarse;
+    const int n = Q.n;
+    build_twiddle_tables(coarse, fine, n, Q.tb, Q.n_coarse, threadIdx.x, 256, 0.5f); // W / 2
+    __syncthreads();
+    const long long s0 = (long long)blockIdx.x * Q.stages_per_block;
+    const long long s1 = min(s0 + Q.stages_per_block, Q.plane_stages);
+    const int mask = (1 << Q.tb) - 1;
+    for (int u = threadIdx.x; u < UNITS; u += 256) {
+        const int row = u % BT, qh = u / BT, h = qh & 1, q = qh >> 1;
+        const int b = base_of(Q.bm, blockIdx.y * BT + row);
+        int m = (int)(((long long)b * (s0 * KS + 8 * q + 4 * h)) % n);
+        const int dm = (int)(((long long)b * KS) % n);
+        uint4 *dst = Q.planes + ((long long)blockIdx.y * Q.plane_stages + s0) * STAGE_A + ((q * 2) * 2 + h) * BT + row;
+        for (long long st = s0; st < s1; ++st) {
+            float wr[4], wi[4];
+            int mj = m;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 a = coarse[mj >> Q.tb], c = fine[mj & mask];
+                wr[j] = fmaf(a.x, c.x, -a.y * c.y);
+                wi[j] = fmaf(a.x, c.y, a.y * c.x);
+                mj = add_mod(mj, b, n);
+            }
+            uint4 a1, a2;
+            split_pair(wr[0], wr[1], a1.x, a1.z);
+            split_pair(wr[2], wr[3], a1.y, a1.w);
+            split_pair(wi[0], wi[1], a2.x, a2.z);
+            split_pair(wi[2], wi[3], a2.y, a2.w);
+            dst[0] = a1;
+            dst[2 * BT] = a2;
+            dst += STAGE_A;
+            m = add_mod(m, dm, n);
+        }
+    }
+}
+
+// Block order as surface_bf16_planes_kernel: blockIdx = tile_l * grp_stride + (tile_b *
+// ksplit + kc), so the delay tiles reading one plane stream share an XCD. Sample chunks
+// are whole stage pairs; the codes and planes cover n rounded up to the lsum chunk.
+template <int NW, int WB, int KS>
+__global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, const uint32_t *codes,
+                                                         long long code_stages)
+{
+    using Cfg = DsumCfg<NW, WB, KS>;
+    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, STAGE_A = Cfg::STAGE_A;
+    constexpr int PLI = STAGE_A / NT;
+    static_assert(STAGE_A % NT == 0, "plane stages split evenly");
+    __shared__ uint4 bufA0[STAGE_A];
+    __shared__ uint4 bufA1[STAGE_A];
+
+    const int grp = blockIdx.x % P.grp_stride;
+    const int tile_l = blockIdx.x / P.grp_stride;
+    if (grp >= P.tiles_b * P.ksplit) return;
+    const int tile_b = grp / P.ksplit, kc = grp % P.ksplit;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int b0 = tile_b * BT, c0 = tile_l * LT;
+    const int k_begin = kc * P.kchunk;
+    const int k_end = min(P.n, k_begin + P.kchunk);
+    const int npair = k_end > k_begin ? (k_end - k_begin + 2 * KS - 1) / (2 * KS) : 0;
+    const int col = c0 + wave * 32 + l32;
+
+    const uint4 *pl_src = P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
+    // codes of (stage, col, h): one uint4 = the words of steps 0..3
+    const uint4 *cd = reinterpret_cast<const uint4 *>(codes);
+    long long cst = k_begin / 32;
+    auto code_load = [&](long long st) {
+        st = min(st, code_stages - 1); // prefetch past the last stage reads a valid, unused one
+        return cd[(st * P.n_cols_pad + col) * 2 + h];
+    };
+
+    f32x16 acc[WB][4];
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][t][e] = 0.0f;
+
+    struct AFrag {
+        bf16x8 a[WB][2];
+    };
+    auto load_a = [&](const uint4 *buf, int q, AFrag &f) {
+#pragma unroll
+        for (int i = 0; i < WB; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                f.a[i][t] = __builtin_bit_cast(bf16x8, buf[((q * 2 + t) * 2 + h) * BT + 32 * i + l32]);
+    };
+    auto mfma_step = [&](const AFrag &f, uint32_t w) {
+        constexpr uint32_t M = 0xC000C000u;
+        const uint32_t r01 = w & M, r23 = (w << 2) & M, i01 = (w << 4) & M, i23 = (w << 6) & M;
+        const bf16x8 b1 = __builtin_bit_cast(bf16x8, make_uint4(r01, r23, r01, r23));
+        const bf16x8 b2 = __builtin_bit_cast(bf16x8, make_uint4(i01, i23, i01, i23));
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b1, acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b2, acc[i][1], 0, 0, 0);
+            acc[i][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b1, acc[i][2], 0, 0, 0);
+            acc[i][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b2, acc[i][3], 0, 0, 0);
+        }
+    };
+
+    AFrag fa[2];
+    uint4 cw = make_uint4(0u, 0u, 0u, 0u);
+    auto stage = [&](auto cbc) {
+        constexpr int CB = decltype(cbc)::value;
+        // two LDS variables so the compiler tells the plane copy's target from the stage read
+        const uint4 *cur = CB ? bufA1 : bufA0;
+        uint4 *nxt = CB ? bufA0 : bufA1;
+        {
+            uint4 *dst = nxt + __builtin_amdgcn_readfirstlane(wave) * 64;
+#pragma unroll
+            for (int k = 0; k < PLI; ++k)
+                __builtin_amdgcn_global_load_lds(pl_src + k * NT,
+                                                 (__attribute__((address_space(3))) void *)(dst + k * NT), 16, 0, 0);
+            pl_src += STAGE_A;
+        }
+        const uint4 cn = code_load(cst + 1);
+        load_a(cur, 0, fa[0]);
+        const uint32_t cwv[4] = {cw.x, cw.y, cw.z, cw.w};
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            if (q + 1 < G) load_a(cur, q + 1, fa[(q + 1) & 1]);
+            mfma_step(fa[q & 1], cwv[q]);
+        }
+        cw = cn;
+        ++cst;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); // plane block landed before the barrier
+        __syncthreads();
+    };
+
+    if (npair > 0) {
+        {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(pl_src);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(bufA0) + tid;
+#pragma unroll
+            for (int k = 0; k < PLI; ++k) dst[k * NT] = src[k * NT];
+            pl_src += STAGE_A;
+        }
+        cw = code_load(cst);
+        __syncthreads();
+        for (int p = 0; p < npair; ++p) {
+            stage(std::integral_constant<int, 0>());
+            stage(std::integral_constant<int, 1>());
+        }
+    }
+
+    float4 *out = P.partial + (long long)kc * P.n_cols_pad * P.n_bases_pad;
+    if (P.row0 && tile_b == 0 && h == 0) out[(long long)col * P.n_bases_pad] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = P.row0 + b0 + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+            float4 v;
+            v.x = acc[i][0][e]; // U
+            v.y = acc[i][3][e]; // V
+            v.z = acc[i][1][e]; // X
+            v.w = acc[i][2][e]; // Y
+            out[(long long)col * P.n_bases_pad + row] = v;
+        }
+}
+
+} // namespace ndft

@@ -187,7 +187,7 @@ enum { TW_GEN = 0, TW_GEN_EXACT = 1, TW_PLANES = 2 };
 template <int NW, int WB, int WL, int KS, int PF, int TWM, bool Z0>
 __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const int kc, const int tile_b,
                                                   const int tile_l,
-                                                  uint4 (*bufA)[SurfCfg<NW, WB, WL, KS, PF>::STAGE_A],
+                                                  uint4 *bufA0, uint4 *bufA1,
                                                   float4 (*win)[SurfCfg<NW, WB, WL, KS, PF>::WIN], float2 *tables,
                                                   const float2 *s_raw, const float2 *r_raw)
 {
@@ -430,17 +430,23 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
     auto stage = [&](auto cbc, auto kstc) {
         constexpr int CB = decltype(cbc)::value;
         constexpr int KST = decltype(kstc)::value;
-        uint4 *cur = bufA[CB];
-        uint4 *nxt = bufA[CB ^ 1];
+        // two LDS variables (not one array) so the compiler can tell the buffer the plane
+        // copy writes from the one the stage reads
+        uint4 *cur = CB ? bufA1 : bufA0;
+        uint4 *nxt = CB ? bufA0 : bufA1;
         const float4 *curw = win[CB];
         uint32_t rare = rare_next;
         load_a(cur, 0, fa[0]);
         float2 wv[Cfg::WIN_ITERS]; // next stage's window
         win_load(k_begin + KST + KS + kpair, wv);
-        u32x4 plv[PLANES ? PLI : 1]; // next stage's plane block
         if (PLANES) {
+            // next stage's plane block straight into LDS (no registers): the 16 bytes of
+            // lane i of a wave land at dst + 16 i, dst wave-uniform
+            uint4 *dst = nxt + __builtin_amdgcn_readfirstlane(wave) * 64;
 #pragma unroll
-            for (int k = 0; k < PLI; ++k) plv[k] = pl_src[k * NT];
+            for (int k = 0; k < PLI; ++k)
+                __builtin_amdgcn_global_load_lds(pl_src + k * NT,
+                                                 (__attribute__((address_space(3))) void *)(dst + k * NT), 16, 0, 0);
             pl_src += Cfg::STAGE_A;
         }
         // twiddle unit it is finished in slot (it G) / TWI and its table entries are read
@@ -475,13 +481,10 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (PLANES) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(nxt) + tid;
-#pragma unroll
-            for (int k = 0; k < PLI; ++k) dst[k * NT] = plv[k];
-        }
         win_store(win[CB ^ 1], wv);
         if (rare) repair(cur, curw, rare);
+        // the plane copy has landed before the barrier publishes it
+        if (PLANES) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     };
 
@@ -490,10 +493,10 @@ __device__ __forceinline__ void surface_bf16_tile(const ContractParams &P, const
 #pragma unroll
         for (int it = 0; it < TWI; ++it) {
             tw_fetch(it);
-            tw_finish(bufA[0], it);
+            tw_finish(bufA0, it);
         }
         if (PLANES) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(bufA[0]) + tid;
+            u32x4 *dst = reinterpret_cast<u32x4 *>(bufA0) + tid;
 #pragma unroll
             for (int k = 0; k < PLI; ++k) dst[k * NT] = pl_src[k * NT];
             pl_src += Cfg::STAGE_A;
@@ -548,7 +551,8 @@ template <int NW, int WB, int WL, int KS, int PF>
 __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_kernel(ContractParams P)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
-    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ uint4 bufA0[Cfg::STAGE_A];
+    __shared__ uint4 bufA1[Cfg::STAGE_A];
     __shared__ float4 win[2][Cfg::WIN];
     extern __shared__ float2 tables[];
     int bid = blockIdx.x;
@@ -557,17 +561,17 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_kernel(ContractParams
     const int tile_b = bid % P.tiles_b, tile_l = bid / P.tiles_b;
     if (P.row0 && tile_b == 0) {
         if (P.tw_exact)
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, true>(P, kc, tile_b, tile_l, bufA, win, tables,
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, true>(P, kc, tile_b, tile_l, bufA0, bufA1, win, tables,
                                                                       P.s_raw, P.r_raw);
         else
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, true>(P, kc, tile_b, tile_l, bufA, win, tables, P.s_raw,
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, true>(P, kc, tile_b, tile_l, bufA0, bufA1, win, tables, P.s_raw,
                                                                 P.r_raw);
     } else {
         if (P.tw_exact)
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, kc, tile_b, tile_l, bufA, win, tables,
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, kc, tile_b, tile_l, bufA0, bufA1, win, tables,
                                                                        P.s_raw, P.r_raw);
         else
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, kc, tile_b, tile_l, bufA, win, tables,
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, kc, tile_b, tile_l, bufA0, bufA1, win, tables,
                                                                  P.s_raw, P.r_raw);
     }
 }
@@ -580,17 +584,18 @@ template <int NW, int WB, int WL, int KS, int PF>
 __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_planes_kernel(ContractParams P)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
-    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ uint4 bufA0[Cfg::STAGE_A];
+    __shared__ uint4 bufA1[Cfg::STAGE_A];
     __shared__ float4 win[2][Cfg::WIN];
     const int grp = blockIdx.x % P.grp_stride;
     const int tile_l = blockIdx.x / P.grp_stride;
     if (grp >= P.tiles_b * P.ksplit) return;
     const int tile_b = grp / P.ksplit;
     if (P.row0 && tile_b == 0)
-        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, true>(P, grp % P.ksplit, tile_b, tile_l, bufA, win,
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, true>(P, grp % P.ksplit, tile_b, tile_l, bufA0, bufA1, win,
                                                                nullptr, P.s_raw, P.r_raw);
     else
-        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, false>(P, grp % P.ksplit, tile_b, tile_l, bufA, win,
+        surface_bf16_tile<NW, WB, WL, KS, PF, TW_PLANES, false>(P, grp % P.ksplit, tile_b, tile_l, bufA0, bufA1, win,
                                                                 nullptr, P.s_raw, P.r_raw);
 }
 
@@ -653,7 +658,8 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchH
                                                                           const float2 *pool_s, const float2 *pool_r)
 {
     using Cfg = SurfCfg<NW, WB, WL, KS, PF>;
-    __shared__ uint4 bufA[2][Cfg::STAGE_A];
+    __shared__ uint4 bufA0[Cfg::STAGE_A];
+    __shared__ uint4 bufA1[Cfg::STAGE_A];
     __shared__ float4 win[2][Cfg::WIN];
     __shared__ int s_item;
     extern __shared__ float2 tables[];
@@ -669,10 +675,10 @@ __global__ __launch_bounds__(64 * NW, 1) void surface_bf16_batched_kernel(BatchH
         const ContractParams P = params[__builtin_amdgcn_readfirstlane(w.x)];
         const float2 *s_raw = pool_s + P.s_raw_off, *r_raw = pool_r + P.r_raw_off;
         if (P.tw_exact)
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, w.w, w.y, w.z, bufA, win, tables, s_raw,
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN_EXACT, false>(P, w.w, w.y, w.z, bufA0, bufA1, win, tables, s_raw,
                                                                        r_raw);
         else
-            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, w.w, w.y, w.z, bufA, win, tables, s_raw, r_raw);
+            surface_bf16_tile<NW, WB, WL, KS, PF, TW_GEN, false>(P, w.w, w.y, w.z, bufA0, bufA1, win, tables, s_raw, r_raw);
     }
 }
 

@@ -169,8 +169,9 @@ Plan make_surface_plan(const char *name)
 }
 
 // Sign-split split-BF16 plans: lsum_kernel (twiddle-sign part, lag sign codes, base 0) and
-// dsum_kernel (twiddles against the lag signs) over twiddle planes.
-template <int NW, int WB, int KS>
+// dsum_kernel (twiddles against the lag signs), its twiddle operands from planes or (GEN)
+// made in the kernel.
+template <int NW, int WB, int KS, bool GEN>
 Plan make_split_plan(const char *name)
 {
     using Cfg = DsumCfg<NW, WB, KS>;
@@ -182,15 +183,16 @@ Plan make_split_plan(const char *name)
     p.nt = Cfg::NT;
     p.kgran = 2 * KS;
     p.static_lds = 2 * Cfg::STAGE_A * 16;
-    p.kfn[0] = reinterpret_cast<const void *>(&dsum_kernel<NW, WB, KS>);
+    p.kfn[0] = reinterpret_cast<const void *>(&dsum_kernel<NW, WB, KS, GEN>);
     p.kfn[1] = nullptr;
     p.kfn_batched = nullptr;
     // half the matrix work of the combined form; the twiddle-sign part costs in proportion
     // to the sign runs (see split_cost)
-    p.cost_scale = 0.25 * (1.0 + 24.0 / Cfg::BT) * 0.5;
-    p.row_cost_cols = 50.0;
+    // two waves per SIMD (8-wave plans) overlap the operand reads with the matrix work
+    p.cost_scale = 0.25 * (1.0 + 24.0 / Cfg::BT) * 0.5 * (NW == 8 ? 0.8 : 1.0);
+    p.row_cost_cols = GEN ? 0.0 : 50.0;
     p.sign_scale = 0.5f;
-    p.planes_kfn = reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
+    p.planes_kfn = GEN ? nullptr : reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
     p.raw_inputs = true;
     p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel);
     p.stage_a = Cfg::STAGE_A;
@@ -221,8 +223,13 @@ const std::vector<Plan> &plans(int prec)
         make_surface_plan<4, 3, 1, 16, 4, true>("bf16x2p_b96_l128_w4_ks16"),
         make_surface_plan<4, 3, 1, 32, 4, true>("bf16x2p_b96_l128_w4_ks32"),
         make_surface_plan<4, 4, 1, 16, 4, true>("bf16x2p_b128_l128_w4_ks16"),
-        make_split_plan<4, 4, 32>("bf16x2s_b128_l128_w4_ks32"),
-        make_split_plan<4, 3, 32>("bf16x2s_b96_l128_w4_ks32"),
+        make_split_plan<4, 4, 32, false>("bf16x2s_b128_l128_w4_ks32"),
+        make_split_plan<4, 3, 32, false>("bf16x2s_b96_l128_w4_ks32"),
+        make_split_plan<8, 2, 32, false>("bf16x2s_b64_l256_w8_ks32"),
+        make_split_plan<8, 3, 32, false>("bf16x2s_b96_l256_w8_ks32"),
+        make_split_plan<8, 2, 32, true>("bf16x2g_b64_l256_w8_ks32"),
+        make_split_plan<4, 4, 32, true>("bf16x2g_b128_l128_w4_ks32"),
+        make_split_plan<8, 3, 32, true>("bf16x2g_b96_l256_w8_ks32"),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -433,6 +440,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
     }
     if (L.plan->lag_kfn) {
+        L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
         L.code_off = L.ws_bytes;
         L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
     }
@@ -570,7 +578,7 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
     uint4 *planes = reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off);
     const size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
     if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED;
-    if (L.tiles_b > 0) {
+    if (L.tiles_b > 0 && L.plan->planes_kfn) {
         DplaneParams Q;
         std::memset(&Q, 0, sizeof(Q));
         Q.planes = planes;
@@ -625,12 +633,14 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
     P.planes = planes;
     P.plane_stages = L.plane_stages;
     P.grp_stride = L.grp_stride;
+    P.tb = L.tb;
+    P.n_coarse = L.n_coarse;
     const uint32_t *ccodes = codes;
     long long code_stages = L.k_codes / 32;
     void *args[] = {&P, &ccodes, &code_stages};
     ProfScope prof(stream);
     hipError_t e = hipLaunchKernel(L.plan->kfn[PROD_LAG], dim3((unsigned)((int64_t)L.tiles_l * L.grp_stride)),
-                                   dim3((unsigned)L.plan->nt), args, 0, stream);
+                                   dim3((unsigned)L.plan->nt), args, L.plan->planes_kfn ? 0 : shmem, stream);
     prof.stop();
     if (e != hipSuccess) return NDFT_E_HIP;
     return check_launch();

@@ -198,22 +198,57 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         float2 nv[WIT]; // next chunk's window, in flight during this chunk
         if (k0 + C < ke) win_load(k0 + C, nv);
 
-        // ---- lag products of (dl, o0 .. o0 + 15): values, exact signs, codes ----
+        // ---- lag products of (dl, o0 .. o0 + 15): FP32 values (the operations of
+        // lag_product4), their signs as codes ----
         float zr[SPT], zi[SPT];
-        uint32_t code[4] = {0u, 0u, 0u, 0u};
-        float ssr = 0.0f, ssi = 0.0f;
+        float mz = 3.0e38f; // smallest |component|
 #pragma unroll
         for (int j = 0; j < SPT; ++j) {
-            const Lag z = lag_product4(sw[lpad(o0 + j)], rw[lpad(o0 + j + (DT - 1 - dl))]);
-            zr[j] = z.zr;
-            zi[j] = z.zi;
-            ssr += z.sr;
-            ssi += z.si;
-            const int w = j >> 2, e = j & 3;
-            const int pos_r = (e & 1) ? 30 - 2 * (e >> 1) : 14 - 2 * (e >> 1); // k0:14 k1:30 k2:12 k3:28
-            code[w] |= sign_field(z.sr) << pos_r;
-            code[w] |= sign_field(z.si) << (pos_r - 4);
+            const float4 a = sw[lpad(o0 + j)], c = rw[lpad(o0 + j + (DT - 1 - dl))];
+            zr[j] = fmaf(a.x, c.z, c.x * a.z) + fmaf(a.y, c.w, c.y * a.w);
+            zi[j] = fmaf(a.y, c.z, c.x * a.w) - fmaf(c.y, a.z, a.x * c.w);
+            mz = fminf(mz, fminf(fabsf(zr[j]), fabsf(zi[j])));
         }
+        // A normal FP32 value carries the exact sign and so does its BF16 rounding, whose
+        // (sign, non-zero) bits bf16_signs2 moves into the code positions of a sample pair.
+        uint32_t code[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            uint32_t g[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float *z = t < 2 ? zr : zi;
+                const int e = 4 * w + 2 * (t & 1);
+                const bf16x2v hv = {(__bf16)z[e], (__bf16)z[e + 1]};
+                (void)bf16_signs2(__builtin_bit_cast(uint32_t, hv), g[t]);
+            }
+            code[w] = g[0] | (g[1] >> 2) | (g[2] >> 4) | (g[3] >> 6);
+        }
+        // zero or subnormal components (zero padding, integer or cancelling inputs): the
+        // exact signs of lag_product4 for this thread's samples
+        if (__builtin_amdgcn_ballot_w64(!(mz >= 1.17549435e-38f))) {
+            if (!(mz >= 1.17549435e-38f)) {
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    const Lag e = lag_product4(sw[lpad(o0 + j)], rw[lpad(o0 + j + (DT - 1 - dl))]);
+                    const int w = j >> 2, q = j & 3;
+                    const int pos_r = (q & 1) ? 30 - 2 * (q >> 1) : 14 - 2 * (q >> 1); // k0:14 k1:30 k2:12 k3:28
+                    code[w] = (code[w] & ~((3u << pos_r) | (3u << (pos_r - 4)))) | (sign_field(e.sr) << pos_r) |
+                              (sign_field(e.si) << (pos_r - 4));
+                }
+            }
+        }
+        // sums of the signs: non-zero fields minus twice the negative ones
+        int cnr = 0, cgr = 0, cni = 0, cgi = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t neg = code[w] & (code[w] >> 1);
+            cnr += __builtin_popcount(code[w] & 0x50005000u);
+            cgr += __builtin_popcount(neg & 0x50005000u);
+            cni += __builtin_popcount(code[w] & 0x05000500u);
+            cgi += __builtin_popcount(neg & 0x05000500u);
+        }
+        float ssr = (float)(cnr - 2 * cgr), ssi = (float)(cni - 2 * cgi);
         if (col < L.n_cols_pad) {
             const long long k = k0 + o0; // 16-aligned: the words (h, q) and (h, q + 1)
             const long long st = k >> 5;
@@ -328,8 +363,29 @@ struct DsumCfg {
     static constexpr int LT = 32 * NW;
     static constexpr int G = KS / 8;             // 8-sample steps per stage
     static constexpr int STAGE_A = G * 4 * BT;   // uint4 per stage (step, A1/A2, h, row)
+    static constexpr int UNITS = G * 2 * BT;     // (step, h, row): four samples, both operands
     static_assert(KS == 32, "one code stage per stage");
 };
+
+// Twiddle operands of one unit (base b, samples m-th .. of a step half) from the two-level
+// table (fine entries W / 2): A1 = Re, A2 = Im, each [hi(4 samples), lo(4 samples)].
+__device__ __forceinline__ void dsum_unit(const float2 *coarse, const float2 *fine, int tb, int m, int b, int n,
+                                          uint4 &a1, uint4 &a2)
+{
+    const int mask = (1 << tb) - 1;
+    float wr[4], wi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float2 a = coarse[m >> tb], c = fine[m & mask];
+        wr[j] = fmaf(a.x, c.x, -a.y * c.y);
+        wi[j] = fmaf(a.x, c.y, a.y * c.x);
+        m = add_mod(m, b, n);
+    }
+    split_pair(wr[0], wr[1], a1.x, a1.z);
+    split_pair(wr[2], wr[3], a1.y, a1.w);
+    split_pair(wi[0], wi[1], a2.x, a2.z);
+    split_pair(wi[2], wi[3], a2.y, a2.w);
+}
 
 struct DplaneParams {
     uint4 *planes;
@@ -355,7 +411,6 @@ __global__ __launch_bounds__(256) void dplane_build_kernel(DplaneParams Q)
     __syncthreads();
     const long long s0 = (long long)blockIdx.x * Q.stages_per_block;
     const long long s1 = min(s0 + Q.stages_per_block, Q.plane_stages);
-    const int mask = (1 << Q.tb) - 1;
     for (int u = threadIdx.x; u < UNITS; u += 256) {
         const int row = u % BT, qh = u / BT, h = qh & 1, q = qh >> 1;
         const int b = base_of(Q.bm, blockIdx.y * BT + row);
@@ -363,20 +418,8 @@ __global__ __launch_bounds__(256) void dplane_build_kernel(DplaneParams Q)
         const int dm = (int)(((long long)b * KS) % n);
         uint4 *dst = Q.planes + ((long long)blockIdx.y * Q.plane_stages + s0) * STAGE_A + ((q * 2) * 2 + h) * BT + row;
         for (long long st = s0; st < s1; ++st) {
-            float wr[4], wi[4];
-            int mj = m;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float2 a = coarse[mj >> Q.tb], c = fine[mj & mask];
-                wr[j] = fmaf(a.x, c.x, -a.y * c.y);
-                wi[j] = fmaf(a.x, c.y, a.y * c.x);
-                mj = add_mod(mj, b, n);
-            }
             uint4 a1, a2;
-            split_pair(wr[0], wr[1], a1.x, a1.z);
-            split_pair(wr[2], wr[3], a1.y, a1.w);
-            split_pair(wi[0], wi[1], a2.x, a2.z);
-            split_pair(wi[2], wi[3], a2.y, a2.w);
+            dsum_unit(coarse, fine, Q.tb, m, b, n, a1, a2);
             dst[0] = a1;
             dst[2 * BT] = a2;
             dst += STAGE_A;
@@ -388,16 +431,21 @@ __global__ __launch_bounds__(256) void dplane_build_kernel(DplaneParams Q)
 // Block order as surface_bf16_planes_kernel: blockIdx = tile_l * grp_stride + (tile_b *
 // ksplit + kc), so the delay tiles reading one plane stream share an XCD. Sample chunks
 // are whole stage pairs; the codes and planes cover n rounded up to the lsum chunk.
-template <int NW, int WB, int KS>
+// GEN: the twiddle operands are made in the kernel (from a two-level table in LDS, the
+// units of the next stage spread over the threads) instead of copied from planes; the
+// matrix loop leaves the vector units nearly idle, and no plane pass is needed.
+template <int NW, int WB, int KS, bool GEN>
 __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, const uint32_t *codes,
                                                          long long code_stages)
 {
     using Cfg = DsumCfg<NW, WB, KS>;
     constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, STAGE_A = Cfg::STAGE_A;
     constexpr int PLI = STAGE_A / NT;
+    constexpr int UPT = (Cfg::UNITS + NT - 1) / NT; // generated units per thread
     static_assert(STAGE_A % NT == 0, "plane stages split evenly");
     __shared__ uint4 bufA0[STAGE_A];
     __shared__ uint4 bufA1[STAGE_A];
+    extern __shared__ float2 tables[];
 
     const int grp = blockIdx.x % P.grp_stride;
     const int tile_l = blockIdx.x / P.grp_stride;
@@ -412,7 +460,37 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
     const int npair = k_end > k_begin ? (k_end - k_begin + 2 * KS - 1) / (2 * KS) : 0;
     const int col = c0 + wave * 32 + l32;
 
-    const uint4 *pl_src = P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
+    const uint4 *pl_src =
+        GEN ? nullptr : P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
+    // GEN: thread units (step q, half h, row) -> twiddle index m of the unit's first sample
+    float2 *coarse = tables, *fine = tables + P.n_coarse;
+    int un_off[UPT], un_b[UPT], un_m[UPT], un_dm[UPT];
+    if (GEN) {
+        build_twiddle_tables(coarse, fine, P.n, P.tb, P.n_coarse, tid, NT, 0.5f); // W / 2
+#pragma unroll
+        for (int it = 0; it < UPT; ++it) {
+            const int u = min(tid + it * NT, Cfg::UNITS - 1);
+            const int row = u % BT, qh = u / BT, uh = qh & 1, uq = qh >> 1;
+            const int b = base_of(P.bm, b0 + row);
+            un_off[it] = ((uq * 2) * 2 + uh) * BT + row; // A1; A2 at + 2 BT
+            un_b[it] = b;
+            un_m[it] = (int)(((long long)b * (k_begin + 8 * uq + 4 * uh)) % P.n);
+            un_dm[it] = (int)(((long long)b * KS) % P.n);
+        }
+        __syncthreads(); // tables
+    }
+    auto gen = [&](uint4 *buf) { // units of the stage after the last generated one
+#pragma unroll
+        for (int it = 0; it < UPT; ++it) {
+            if (Cfg::UNITS % NT == 0 || tid + it * NT < Cfg::UNITS) {
+                uint4 a1, a2;
+                dsum_unit(coarse, fine, P.tb, un_m[it], un_b[it], P.n, a1, a2);
+                buf[un_off[it]] = a1;
+                buf[un_off[it] + 2 * BT] = a2;
+                un_m[it] = add_mod(un_m[it], un_dm[it], P.n);
+            }
+        }
+    };
     // codes of (stage, col, h): one uint4 = the words of steps 0..3
     const uint4 *cd = reinterpret_cast<const uint4 *>(codes);
     long long cst = k_begin / 32;
@@ -460,7 +538,9 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         // two LDS variables so the compiler tells the plane copy's target from the stage read
         const uint4 *cur = CB ? bufA1 : bufA0;
         uint4 *nxt = CB ? bufA0 : bufA1;
-        {
+        if (GEN) {
+            gen(nxt);
+        } else {
             uint4 *dst = nxt + __builtin_amdgcn_readfirstlane(wave) * 64;
 #pragma unroll
             for (int k = 0; k < PLI; ++k)
@@ -478,12 +558,14 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         }
         cw = cn;
         ++cst;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); // plane block landed before the barrier
+        if (!GEN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); // plane block landed before the barrier
         __syncthreads();
     };
 
     if (npair > 0) {
-        {
+        if (GEN) {
+            gen(bufA0);
+        } else {
             const u32x4 *src = reinterpret_cast<const u32x4 *>(pl_src);
             u32x4 *dst = reinterpret_cast<u32x4 *>(bufA0) + tid;
 #pragma unroll

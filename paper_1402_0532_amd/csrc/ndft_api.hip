@@ -10,6 +10,7 @@
 #include <atomic>
 #include <mutex>
 #include <chrono>
+#include <map>
 #include <utility>
 #include <vector>
 
@@ -172,7 +173,7 @@ Plan make_surface_plan(const char *name)
 // dsum_kernel (twiddles against the lag signs), its twiddle operands from planes or (GEN)
 // made in the kernel.
 template <int NW, int WB, int KS, bool GEN>
-Plan make_split_plan(const char *name)
+Plan make_split_plan(const char *name, double rel_cost)
 {
     using Cfg = DsumCfg<NW, WB, KS>;
     Plan p;
@@ -188,8 +189,10 @@ Plan make_split_plan(const char *name)
     p.kfn_batched = nullptr;
     // half the matrix work of the combined form; the twiddle-sign part costs in proportion
     // to the sign runs (see split_cost)
-    // two waves per SIMD (8-wave plans) overlap the operand reads with the matrix work
-    p.cost_scale = 0.25 * (1.0 + 24.0 / Cfg::BT) * 0.5 * (NW == 8 ? 0.8 : 1.0);
+    // half the matrix work of the combined form, times the plan's measured cost per padded
+    // cell relative to the best (whole call, N = 65536 surface: work-groups per compute
+    // unit and waves per SIMD differ between the tile shapes)
+    p.cost_scale = 0.25 * 0.5 * rel_cost;
     p.row_cost_cols = GEN ? 0.0 : 50.0;
     p.sign_scale = 0.5f;
     p.planes_kfn = GEN ? nullptr : reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
@@ -223,13 +226,14 @@ const std::vector<Plan> &plans(int prec)
         make_surface_plan<4, 3, 1, 16, 4, true>("bf16x2p_b96_l128_w4_ks16"),
         make_surface_plan<4, 3, 1, 32, 4, true>("bf16x2p_b96_l128_w4_ks32"),
         make_surface_plan<4, 4, 1, 16, 4, true>("bf16x2p_b128_l128_w4_ks16"),
-        make_split_plan<4, 4, 32, false>("bf16x2s_b128_l128_w4_ks32"),
-        make_split_plan<4, 3, 32, false>("bf16x2s_b96_l128_w4_ks32"),
-        make_split_plan<8, 2, 32, false>("bf16x2s_b64_l256_w8_ks32"),
-        make_split_plan<8, 3, 32, false>("bf16x2s_b96_l256_w8_ks32"),
-        make_split_plan<8, 2, 32, true>("bf16x2g_b64_l256_w8_ks32"),
-        make_split_plan<4, 4, 32, true>("bf16x2g_b128_l128_w4_ks32"),
-        make_split_plan<8, 3, 32, true>("bf16x2g_b96_l256_w8_ks32"),
+        make_split_plan<4, 4, 32, false>("bf16x2s_b128_l128_w4_ks32", 1.12),
+        make_split_plan<4, 3, 32, false>("bf16x2s_b96_l128_w4_ks32", 1.07),
+        make_split_plan<8, 2, 32, false>("bf16x2s_b64_l256_w8_ks32", 1.10),
+        make_split_plan<8, 3, 32, false>("bf16x2s_b96_l256_w8_ks32", 1.10),
+        make_split_plan<8, 2, 32, true>("bf16x2g_b64_l256_w8_ks32", 1.09),
+        make_split_plan<4, 4, 32, true>("bf16x2g_b128_l128_w4_ks32", 1.11),
+        make_split_plan<8, 3, 32, true>("bf16x2g_b96_l256_w8_ks32", 1.03),
+        make_split_plan<4, 2, 32, true>("bf16x2g_b64_l128_w4_ks32", 1.0),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }
@@ -328,6 +332,23 @@ void choose_table(int64_t n, int max_bytes, int *tb_out, int *n_coarse_out, int 
     *exact_out = exact;
 }
 
+// Work-groups of a plan's main kernel that fit one compute unit together (register and
+// LDS use of the built kernel, from the runtime); 1 when it cannot be queried.
+int plan_occupancy(const Plan &p, int prod, size_t dyn_shmem)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, size_t>, int> cache;
+    const void *fn = p.kfn[prod];
+    if (!fn) return 1;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({fn, dyn_shmem});
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, p.nt, dyn_shmem) != hipSuccess || nb < 1) nb = 1;
+    cache[{fn, dyn_shmem}] = nb;
+    return nb;
+}
+
 // Largest base of a base map (bases ascend).
 int max_base(const BaseMap &bm, int n_bases)
 {
@@ -414,11 +435,14 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     const int gran = L.plan->kgran;
     int max_split = (int)std::max<int64_t>(1, cdiv(n, gran));
     const int cus = device_cu_count();
-    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, gran, cus);
+    choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
+    // work-group slots: compute units times the plan's work-groups per unit
+    const size_t dyn = L.plan->lag_kfn && !L.plan->planes_kfn ? (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2) : 0;
+    const int slots = cus * (L.plan->lag_kfn ? plan_occupancy(*L.plan, prod, dyn) : 1);
+    L.ksplit = ko > 0 ? std::min(ko, max_split) : pick_ksplit(L.tiles_b * L.tiles_l, n, gran, slots);
     L.kchunk = (int)(cdiv(cdiv(n, L.ksplit), gran) * gran);
     L.ksplit = (int)cdiv(n, L.kchunk); // no empty chunks
     if (L.tiles_b == 0) L.ksplit = 0;  // sign-split with base 0 only: no matrix part
-    choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
     if (L.plan->lag_kfn) {
         // lsum_kernel: blocks of kLsumDelays delays x kLsumBases bases x a sample range of
         // whole chunks; about two blocks per compute unit

@@ -234,6 +234,7 @@ const std::vector<Plan> &plans(int prec)
         make_split_plan<4, 4, 32, true>("bf16x2g_b128_l128_w4_ks32", 1.11),
         make_split_plan<8, 3, 32, true>("bf16x2g_b96_l256_w8_ks32", 1.03),
         make_split_plan<4, 2, 32, true>("bf16x2g_b64_l128_w4_ks32", 1.0),
+        make_split_plan<4, 2, 32, false>("bf16x2s_b64_l128_w4_ks32", 0.95),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }

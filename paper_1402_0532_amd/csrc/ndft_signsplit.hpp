@@ -200,29 +200,43 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 
         // ---- lag products of (dl, o0 .. o0 + 15): FP32 values (the operations of
         // lag_product4), their signs as codes ----
+        // In groups of four samples (a scheduling barrier between groups keeps the loads
+        // of one group in registers at a time): the values, their code word, and the
+        // running prefix within the thread (zr, zi end up holding it).
         float zr[SPT], zi[SPT];
-        float mz = 3.0e38f; // smallest |component|
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) {
-            const float4 a = sw[lpad(o0 + j)], c = rw[lpad(o0 + j + (DT - 1 - dl))];
-            zr[j] = fmaf(a.x, c.z, c.x * a.z) + fmaf(a.y, c.w, c.y * a.w);
-            zi[j] = fmaf(a.y, c.z, c.x * a.w) - fmaf(c.y, a.z, a.x * c.w);
-            mz = fminf(mz, fminf(fabsf(zr[j]), fabsf(zi[j])));
-        }
-        // A normal FP32 value carries the exact sign and so does its BF16 rounding, whose
-        // (sign, non-zero) bits bf16_signs2 moves into the code positions of a sample pair.
         uint32_t code[4];
+        float mz = 3.0e38f; // smallest |component|
+        float pr = 0.0f, pi = 0.0f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
+            float vr[4], vi[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 4 * w + e;
+                const float4 a = sw[lpad(o0 + j)], c = rw[lpad(o0 + j + (DT - 1 - dl))];
+                vr[e] = fmaf(a.x, c.z, c.x * a.z) + fmaf(a.y, c.w, c.y * a.w);
+                vi[e] = fmaf(a.y, c.z, c.x * a.w) - fmaf(c.y, a.z, a.x * c.w);
+                mz = fminf(mz, fminf(fabsf(vr[e]), fabsf(vi[e])));
+            }
+            // A normal FP32 value carries the exact sign and so does its BF16 rounding,
+            // whose (sign, non-zero) bits bf16_signs2 moves into the code positions of a pair.
             uint32_t g[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const float *z = t < 2 ? zr : zi;
-                const int e = 4 * w + 2 * (t & 1);
+                const float *z = t < 2 ? vr : vi;
+                const int e = 2 * (t & 1);
                 const bf16x2v hv = {(__bf16)z[e], (__bf16)z[e + 1]};
                 (void)bf16_signs2(__builtin_bit_cast(uint32_t, hv), g[t]);
             }
             code[w] = g[0] | (g[1] >> 2) | (g[2] >> 4) | (g[3] >> 6);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pr += vr[e];
+                pi += vi[e];
+                zr[4 * w + e] = pr;
+                zi[4 * w + e] = pi;
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         // zero or subnormal components (zero padding, integer or cancelling inputs): the
         // exact signs of lag_product4 for this thread's samples
@@ -257,15 +271,7 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             cw[0] = make_uint2(code[0], code[2]); // h = 0: steps q, q + 1
             cw[2] = make_uint2(code[1], code[3]); // h = 1
         }
-        // prefix sums: within the thread, then across the 16 threads of the delay
-        float pr = 0.0f, pi = 0.0f;
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) {
-            pr += zr[j];
-            pi += zi[j];
-            zr[j] = pr;
-            zi[j] = pi;
-        }
+        // prefix sums across the 16 threads of the delay (within the thread: above)
         float er = pr, ei = pi; // inclusive scan of the thread totals
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) {
@@ -356,6 +362,13 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 // samples k0..k3 = step start + 4 h + 0..3, and the sign operand [s(k0..k3), s(k0..k3)]
 // (+-2 / 0) of its delay column: U = A1.B1, X = A1.B2, Y = A2.B1, V = A2.B2 with B1 from
 // the real signs, B2 from the imaginary ones.
+// W^b from the two-level table whose fine entries hold W / 2
+__device__ __forceinline__ float2 twiddle_step(const float2 *coarse, const float2 *fine, int tb, int b)
+{
+    const float2 a = coarse[b >> tb], c = fine[b & ((1 << tb) - 1)];
+    return make_float2(2.0f * fmaf(a.x, c.x, -a.y * c.y), 2.0f * fmaf(a.x, c.y, a.y * c.x));
+}
+
 template <int NW, int WB, int KS>
 struct DsumCfg {
     static constexpr int NT = 64 * NW;
@@ -367,19 +380,24 @@ struct DsumCfg {
     static_assert(KS == 32, "one code stage per stage");
 };
 
-// Twiddle operands of one unit (base b, samples m-th .. of a step half) from the two-level
-// table (fine entries W / 2): A1 = Re, A2 = Im, each [hi(4 samples), lo(4 samples)].
-__device__ __forceinline__ void dsum_unit(const float2 *coarse, const float2 *fine, int tb, int m, int b, int n,
+// Twiddle operands of one unit (base b, four consecutive samples from index m): W^m / 2
+// from the two-level table (fine entries W / 2), the next three by the step wb = W^b
+// (three FP32 complex products: a few ulp, far below the BF16 hi + lo split);
+// A1 = Re, A2 = Im, each [hi(4 samples), lo(4 samples)].
+__device__ __forceinline__ void dsum_unit(const float2 *coarse, const float2 *fine, int tb, int m, float2 wb,
                                           uint4 &a1, uint4 &a2)
 {
     const int mask = (1 << tb) - 1;
     float wr[4], wi[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    {
         const float2 a = coarse[m >> tb], c = fine[m & mask];
-        wr[j] = fmaf(a.x, c.x, -a.y * c.y);
-        wi[j] = fmaf(a.x, c.y, a.y * c.x);
-        m = add_mod(m, b, n);
+        wr[0] = fmaf(a.x, c.x, -a.y * c.y);
+        wi[0] = fmaf(a.x, c.y, a.y * c.x);
+    }
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+        wr[j] = fmaf(wr[j - 1], wb.x, -wi[j - 1] * wb.y);
+        wi[j] = fmaf(wr[j - 1], wb.y, wi[j - 1] * wb.x);
     }
     split_pair(wr[0], wr[1], a1.x, a1.z);
     split_pair(wr[2], wr[3], a1.y, a1.w);
@@ -414,12 +432,13 @@ __global__ __launch_bounds__(256) void dplane_build_kernel(DplaneParams Q)
     for (int u = threadIdx.x; u < UNITS; u += 256) {
         const int row = u % BT, qh = u / BT, h = qh & 1, q = qh >> 1;
         const int b = base_of(Q.bm, blockIdx.y * BT + row);
+        const float2 wb = twiddle_step(coarse, fine, Q.tb, b);
         int m = (int)(((long long)b * (s0 * KS + 8 * q + 4 * h)) % n);
         const int dm = (int)(((long long)b * KS) % n);
         uint4 *dst = Q.planes + ((long long)blockIdx.y * Q.plane_stages + s0) * STAGE_A + ((q * 2) * 2 + h) * BT + row;
         for (long long st = s0; st < s1; ++st) {
             uint4 a1, a2;
-            dsum_unit(coarse, fine, Q.tb, m, b, n, a1, a2);
+            dsum_unit(coarse, fine, Q.tb, m, wb, a1, a2);
             dst[0] = a1;
             dst[2 * BT] = a2;
             dst += STAGE_A;
@@ -464,7 +483,8 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         GEN ? nullptr : P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
     // GEN: thread units (step q, half h, row) -> twiddle index m of the unit's first sample
     float2 *coarse = tables, *fine = tables + P.n_coarse;
-    int un_off[UPT], un_b[UPT], un_m[UPT], un_dm[UPT];
+    int un_off[UPT], un_m[UPT], un_dm[UPT];
+    float2 un_wb[UPT];
     if (GEN) {
         build_twiddle_tables(coarse, fine, P.n, P.tb, P.n_coarse, tid, NT, 0.5f); // W / 2
 #pragma unroll
@@ -473,23 +493,28 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
             const int row = u % BT, qh = u / BT, uh = qh & 1, uq = qh >> 1;
             const int b = base_of(P.bm, b0 + row);
             un_off[it] = ((uq * 2) * 2 + uh) * BT + row; // A1; A2 at + 2 BT
-            un_b[it] = b;
             un_m[it] = (int)(((long long)b * (k_begin + 8 * uq + 4 * uh)) % P.n);
             un_dm[it] = (int)(((long long)b * KS) % P.n);
         }
         __syncthreads(); // tables
-    }
-    auto gen = [&](uint4 *buf) { // units of the stage after the last generated one
 #pragma unroll
         for (int it = 0; it < UPT; ++it) {
-            if (Cfg::UNITS % NT == 0 || tid + it * NT < Cfg::UNITS) {
-                uint4 a1, a2;
-                dsum_unit(coarse, fine, P.tb, un_m[it], un_b[it], P.n, a1, a2);
-                buf[un_off[it]] = a1;
-                buf[un_off[it] + 2 * BT] = a2;
-                un_m[it] = add_mod(un_m[it], un_dm[it], P.n);
-            }
+            const int u = min(tid + it * NT, Cfg::UNITS - 1);
+            un_wb[it] = twiddle_step(coarse, fine, P.tb, base_of(P.bm, b0 + u % BT));
         }
+    }
+    auto gen_unit = [&](uint4 *buf, int it) { // unit it of the stage after the last generated one
+        if (Cfg::UNITS % NT == 0 || tid + it * NT < Cfg::UNITS) {
+            uint4 a1, a2;
+            dsum_unit(coarse, fine, P.tb, un_m[it], un_wb[it], a1, a2);
+            buf[un_off[it]] = a1;
+            buf[un_off[it] + 2 * BT] = a2;
+            un_m[it] = add_mod(un_m[it], un_dm[it], P.n);
+        }
+    };
+    auto gen = [&](uint4 *buf) {
+#pragma unroll
+        for (int it = 0; it < UPT; ++it) gen_unit(buf, it);
     };
     // codes of (stage, col, h): one uint4 = the words of steps 0..3
     const uint4 *cd = reinterpret_cast<const uint4 *>(codes);
@@ -538,9 +563,7 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         // two LDS variables so the compiler tells the plane copy's target from the stage read
         const uint4 *cur = CB ? bufA1 : bufA0;
         uint4 *nxt = CB ? bufA0 : bufA1;
-        if (GEN) {
-            gen(nxt);
-        } else {
+        if (!GEN) {
             uint4 *dst = nxt + __builtin_amdgcn_readfirstlane(wave) * 64;
 #pragma unroll
             for (int k = 0; k < PLI; ++k)
@@ -555,6 +578,12 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         for (int q = 0; q < G; ++q) {
             if (q + 1 < G) load_a(cur, q + 1, fa[(q + 1) & 1]);
             mfma_step(fa[q & 1], cwv[q]);
+            // GEN: the next stage's units while this step's matrix instructions run
+            if (GEN) {
+#pragma unroll
+                for (int it = 0; it < UPT; ++it)
+                    if ((it * G) / UPT == q) gen_unit(nxt, it);
+            }
         }
         cw = cn;
         ++cst;

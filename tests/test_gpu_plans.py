@@ -65,6 +65,8 @@ SHAPES = [
     (17, 0, 17, 0, 17, 0, "int_zeros"),        # shorter than one stage
     (4096, 5, 200, -128, 256, 0, "gauss"),     # 129 bases: base 0 apart for 64/128-row tiles
     (1200, 0, 40, -96, 192, 5, "cancel"),      # 97 bases: base 0 apart for 96-row tiles
+    (2048, 0, 50, 10, 90, 0, "gauss"),         # no base 0 in the window
+    (8192, 2, 70, -33, 66, 3, "int_zeros"),    # sign runs crossing chunk edges, exact zeros
 ]
 
 _ORACLE = {}

@@ -87,6 +87,49 @@ __device__ __forceinline__ SignRun sign_run(unsigned m, unsigned b, unsigned n, 
     return r;
 }
 
+// One part of csgn(W^m) alone: the real part changes only where m crosses N/4 and 3N/4,
+// the imaginary part only where it crosses 0 and N/2 (each exactly 0 on such a point), so
+// each part has half the changes of the pair and a change updates two sums, not four.
+struct PartRun {
+    float s;
+    int len; // samples until this part changes, >= 1; capped at cap + 1
+};
+
+template <int PART> // 0: Re (cos), 1: Im (-sin)
+__device__ __forceinline__ PartRun part_run(unsigned m, unsigned b, unsigned n, float rinv, unsigned cap)
+{
+    const unsigned m4 = 4u * m; // < 4 N <= 2^26
+    const unsigned q = (m4 >= n) + (m4 >= 2u * n) + (m4 >= 3u * n);
+    const bool exact = m4 == q * n;
+    PartRun r;
+    unsigned target; // 4 x the next m (unwrapped) where this part changes
+    if (PART == 0) {
+        r.s = (q == 0 || q == 3) ? 1.0f : -1.0f;
+        if (exact && (q & 1)) r.s = 0.0f; // N/4, 3N/4
+        target = q == 0 ? n : (q < 3 ? 3u * n : 5u * n);
+    } else {
+        r.s = q < 2 ? -1.0f : 1.0f;
+        if (exact && !(q & 1)) r.s = 0.0f; // 0, N/2
+        target = q < 2 ? 2u * n : 4u * n;
+    }
+    if (b == 0) {
+        r.len = (int)cap + 1; // m stays 0
+    } else if (r.s == 0.0f) {
+        r.len = 1;
+    } else {
+        const unsigned num = target - m4, den = 4u * b; // ceil(num / den), needed up to cap
+        if ((unsigned long long)num > (unsigned long long)cap * den) {
+            r.len = (int)cap + 1;
+        } else {
+            unsigned j = (unsigned)((float)num * rinv);
+            j += j * den < num;
+            j -= j > 1u && (j - 1u) * den >= num;
+            r.len = (int)j;
+        }
+    }
+    return r;
+}
+
 // ------------------------------------------------------------------------------------
 // lsum_kernel: lag products, sign codes and the T part (plus base 0 entirely)
 // ------------------------------------------------------------------------------------
@@ -301,38 +344,41 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 
         if (k0 + C < ke) win_store(nv);
 
-        // ---- T part: runs of constant twiddle signs within the chunk ----
+        // ---- T part: runs of constant twiddle sign within the chunk, per part ----
         // sum_runs S_r (P(e_r) - P(e_{r-1})) = S_last P(C) + sum_{inner ends} (S_r - S_{r+1}) P(e_r)
+        // (Re part into U, X; Im part into Y, V)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             if (__builtin_amdgcn_ballot_w64(own[j]) == 0) continue;
-            unsigned m = mc[j];
-            SignRun rr = sign_run(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
-            int o = rr.len;
-            while (o < C) { // run ends at o inside the chunk
-                const unsigned mn = m + (unsigned)rr.len * bb[j]; // < 2 N: the run ends in the next quarter
-                m = mn >= (unsigned)n ? mn - (unsigned)n : mn;
-                const SignRun nx = sign_run(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
-                const float dc = rr.sc - nx.sc, dt = rr.st - nx.st;
+            auto walk = [&](auto partc) {
+                constexpr int PART = decltype(partc)::value;
+                constexpr int IA = PART == 0 ? 0 : 3, IB = PART == 0 ? 2 : 1; // sums of P.x, P.y
+                unsigned m = mc[j];
+                PartRun rr = part_run<PART>(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
+                int o = rr.len;
+                while (o < C) { // run ends at o inside the chunk
+                    const unsigned mn = m + (unsigned)rr.len * bb[j]; // < 2 N
+                    m = mn >= (unsigned)n ? mn - (unsigned)n : mn;
+                    const PartRun nx = part_run<PART>(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
+                    const float ds = rr.s - nx.s;
+#pragma unroll
+                    for (int d = 0; d < DH; ++d) {
+                        const float2 p = pre[dh * DH + d][lpad(o)];
+                        acc[j][d][IA] = fmaf(ds, p.x, acc[j][d][IA]);
+                        acc[j][d][IB] = fmaf(ds, p.y, acc[j][d][IB]);
+                    }
+                    rr = nx;
+                    o += rr.len;
+                }
 #pragma unroll
                 for (int d = 0; d < DH; ++d) {
-                    const float2 p = pre[dh * DH + d][lpad(o)];
-                    acc[j][d][0] = fmaf(dc, p.x, acc[j][d][0]); // U
-                    acc[j][d][2] = fmaf(dc, p.y, acc[j][d][2]); // X
-                    acc[j][d][3] = fmaf(dt, p.x, acc[j][d][3]); // Y
-                    acc[j][d][1] = fmaf(dt, p.y, acc[j][d][1]); // V
+                    const float2 p = pre[dh * DH + d][lpad(C)];
+                    acc[j][d][IA] = fmaf(rr.s, p.x, acc[j][d][IA]);
+                    acc[j][d][IB] = fmaf(rr.s, p.y, acc[j][d][IB]);
                 }
-                rr = nx;
-                o += rr.len;
-            }
-#pragma unroll
-            for (int d = 0; d < DH; ++d) {
-                const float2 p = pre[dh * DH + d][lpad(C)];
-                acc[j][d][0] = fmaf(rr.sc, p.x, acc[j][d][0]);
-                acc[j][d][2] = fmaf(rr.sc, p.y, acc[j][d][2]);
-                acc[j][d][3] = fmaf(rr.st, p.x, acc[j][d][3]);
-                acc[j][d][1] = fmaf(rr.st, p.y, acc[j][d][1]);
-            }
+            };
+            walk(std::integral_constant<int, 0>());
+            walk(std::integral_constant<int, 1>());
             mc[j] = (unsigned)add_mod((int)mc[j], (int)dmc[j], n);
         }
         __syncthreads(); // next window stored, prefix sums read

@@ -87,3 +87,44 @@ def test_sign_split_halves_sum_to_surface(shape):
             got = T + D
             err = abs(got.real - A[t, q].real) + abs(got.imag - A[t, q].imag)
             assert err <= 1e-9 * max(sc[t, q], 1.0), (shape, t, q, got, A[t, q])
+
+
+def part_runs(b, k0, k1, n, part):
+    """Runs of one part of csgn(W^{b k}) alone: the real part changes only where b k mod N
+    crosses N/4 or 3N/4, the imaginary part only where it crosses 0 or N/2 (each exactly
+    zero on such a point)."""
+    out = []
+    k = k0
+    while k < k1:
+        m = (b * k) % n
+        q = int(4 * m >= n) + int(4 * m >= 2 * n) + int(4 * m >= 3 * n)
+        exact = 4 * m == q * n
+        if part == 0:
+            s = 1 if q in (0, 3) else -1
+            s = 0 if exact and q % 2 == 1 else s
+            target = n if q == 0 else (3 * n if q < 3 else 5 * n)
+        else:
+            s = -1 if q < 2 else 1
+            s = 0 if exact and q % 2 == 0 else s
+            target = 2 * n if q < 2 else 4 * n
+        if b == 0:
+            ln = k1 - k
+        elif s == 0:
+            ln = 1
+        else:
+            ln = -(-(target - 4 * m) // (4 * b))
+        ke = min(k1, k + ln)
+        out.append((k, ke, s))
+        k = ke
+    return out
+
+
+@pytest.mark.parametrize("n", [17, 30, 1000, 1002, 4096])
+def test_part_runs_match_quarter_rule(n):
+    for b in list(range(0, min(n, 40))) + list(range(n // 2 - 3, n // 2 + 1)):
+        for part in (0, 1):
+            got = np.zeros(n, int)
+            for ks, ke, s in part_runs(b, 0, n, n, part):
+                got[ks:ke] = s
+            want = np.array([quarter_signs((b * k) % n, n)[part] for k in range(n)])
+            assert np.array_equal(got, want), (n, b, part)

@@ -42,92 +42,50 @@ __device__ __forceinline__ uint32_t sign_field(float s)
 }
 
 // ------------------------------------------------------------------------------------
-// twiddle-sign runs
+// twiddle-sign crossings
 // ------------------------------------------------------------------------------------
-// csgn(W^m) for m = b k mod N from the quarter of m: q = floor(4m / N) and whether m is
-// exactly q N / 4 (then one of the parts is exactly 0):
-//   q = 0: (+1, -1), exact (+1,  0)      q = 2: (-1, +1), exact (-1,  0)
-//   q = 1: (-1, -1), exact ( 0, -1)      q = 3: (+1, +1), exact ( 0, +1)
-// Re from cos(2 pi m / N), Im from -sin(2 pi m / N).
-struct SignRun {
-    float sc, st;
-    int len; // samples until the quarter (or the exact point) changes, >= 1; capped at cap + 1
+// With u = 4 b k (the phase of W^{bk} in quarter turns times N), the real part of
+// csgn(W^{bk}) is the sign of cos(2 pi u / 4N) and the imaginary part that of
+// -sin(2 pi u / 4N). Each part is a square wave in u that changes only at its crossings
+// u = phi + 2 N i (phi = N for the real part, 0 for the imaginary part) and is exactly 0
+// where u hits one; the sign just before crossing i is (-1)^i for both parts. Crossing i
+// falls at sample k_i = ceil((phi + 2 N i) / 4b); it is exact (sample k_i has the zero)
+// when 4b k_i = phi + 2 N i. rem = 4b k_i - (phi + 2 N i) in [0, 4b) steps from one
+// crossing to the next with q0 = floor(2N / 4b), r0 = 2N mod 4b: the next crossing is
+// q0 + 1 samples on when rem < r0 (then rem += 4b - r0), q0 samples on otherwise
+// (rem -= r0). A walker that stands at sample kb keeps the next crossing at or after kb:
+// its offset nk >= 0 from the current chunk start, its rem, and the sign sg before it.
+struct Crossing {
+    int nk, rem;
+    float sg;
 };
 
-// rinv = 1 / (4 b) rounded; the quotient is only needed up to cap <= 2^12, where the
-// float estimate is within one of the exact ceiling and one check on each side fixes it.
-__device__ __forceinline__ SignRun sign_run(unsigned m, unsigned b, unsigned n, float rinv, unsigned cap)
+template <int PART> // 0: real part (phi = N), 1: imaginary part (phi = 0)
+__device__ __forceinline__ Crossing first_crossing(unsigned b, long long kb, int n)
 {
-    const unsigned m4 = 4u * m; // < 4 N <= 2^26
-    const unsigned q = (m4 >= n) + (m4 >= 2u * n) + (m4 >= 3u * n);
-    const bool exact = m4 == q * n;
-    SignRun r;
-    r.sc = (q == 0 || q == 3) ? 1.0f : -1.0f;
-    r.st = q < 2 ? -1.0f : 1.0f;
-    if (exact) {
-        if (q & 1) r.sc = 0.0f;
-        else r.st = 0.0f;
+    Crossing c;
+    if (b == 0) { // u stays 0: real part +1, imaginary part 0, no crossing ahead
+        c.nk = 0x3fffffff;
+        c.rem = 1;
+        c.sg = PART == 0 ? 1.0f : 0.0f;
+        return c;
     }
-    if (b == 0) {
-        r.len = (int)cap + 1; // m stays 0
-    } else if (exact) {
-        r.len = 1;
-    } else {
-        // first sample with 4 m >= (q + 1) N: ceil(num / den)
-        const unsigned num = (q + 1u) * n - m4, den = 4u * b;
-        if ((unsigned long long)num > (unsigned long long)cap * den) {
-            r.len = (int)cap + 1;
-        } else {
-            unsigned j = (unsigned)((float)num * rinv);
-            j += j * den < num;
-            j -= j > 1u && (j - 1u) * den >= num;
-            r.len = (int)j;
-        }
-    }
-    return r;
-}
-
-// One part of csgn(W^m) alone: the real part changes only where m crosses N/4 and 3N/4,
-// the imaginary part only where it crosses 0 and N/2 (each exactly 0 on such a point), so
-// each part has half the changes of the pair and a change updates two sums, not four.
-struct PartRun {
-    float s;
-    int len; // samples until this part changes, >= 1; capped at cap + 1
-};
-
-template <int PART> // 0: Re (cos), 1: Im (-sin)
-__device__ __forceinline__ PartRun part_run(unsigned m, unsigned b, unsigned n, float rinv, unsigned cap)
-{
-    const unsigned m4 = 4u * m; // < 4 N <= 2^26
-    const unsigned q = (m4 >= n) + (m4 >= 2u * n) + (m4 >= 3u * n);
-    const bool exact = m4 == q * n;
-    PartRun r;
-    unsigned target; // 4 x the next m (unwrapped) where this part changes
+    const int fb = 4 * (int)b;                               // <= 2N
+    int w = 4 * (int)(((long long)b * kb) % n) - fb;        // u of sample kb - 1, mod 4N
+    if (w < 0) w += 4 * n;
+    int cu; // next crossing value above w (mod 4N, possibly past 4N)
     if (PART == 0) {
-        r.s = (q == 0 || q == 3) ? 1.0f : -1.0f;
-        if (exact && (q & 1)) r.s = 0.0f; // N/4, 3N/4
-        target = q == 0 ? n : (q < 3 ? 3u * n : 5u * n);
+        cu = w < n ? n : (w < 3 * n ? 3 * n : 5 * n);
+        c.sg = cu == 3 * n ? -1.0f : 1.0f;
     } else {
-        r.s = q < 2 ? -1.0f : 1.0f;
-        if (exact && !(q & 1)) r.s = 0.0f; // 0, N/2
-        target = q < 2 ? 2u * n : 4u * n;
+        cu = w < 2 * n ? 2 * n : 4 * n;
+        c.sg = cu == 2 * n ? -1.0f : 1.0f;
     }
-    if (b == 0) {
-        r.len = (int)cap + 1; // m stays 0
-    } else if (r.s == 0.0f) {
-        r.len = 1;
-    } else {
-        const unsigned num = target - m4, den = 4u * b; // ceil(num / den), needed up to cap
-        if ((unsigned long long)num > (unsigned long long)cap * den) {
-            r.len = (int)cap + 1;
-        } else {
-            unsigned j = (unsigned)((float)num * rinv);
-            j += j * den < num;
-            j -= j > 1u && (j - 1u) * den >= num;
-            r.len = (int)j;
-        }
-    }
-    return r;
+    const int d = cu - w;                 // > 0: the crossing lies d past sample kb - 1
+    const int cq = (d + fb - 1) / fb;     // >= 1
+    c.nk = cq - 1;
+    c.rem = cq * fb - d;
+    return c;
 }
 
 // ------------------------------------------------------------------------------------
@@ -153,11 +111,45 @@ constexpr int kLsumBases = 256;   // base rows per block
 // lanes of a wave access entries 16 apart; the pad spreads them over the banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+// Prefix tables: row o holds the 16 delays of the block (float2 each) at a stride of 17
+// float2 plus 1 more after every 16 rows. The 16 writers of a delay store rows 16 apart,
+// which the per-16 shift puts on 16 different bank pairs; the walkers read rows at random,
+// which the odd stride spreads. A walker reads the 8 delays it owns as four 8-byte pairs.
+constexpr int kLsumRowF2 = kLsumDelays + 1;
+__device__ __forceinline__ int prow(int o) { return (int)__umul24((unsigned)o, kLsumRowF2) + (o >> 4); }
+constexpr int kLsumTabF2 = kLsumChunk * kLsumRowF2 + (kLsumChunk >> 4) + kLsumDelays;
+
+// inclusive scan over the 16 lanes of a DPP row (the 16 threads of one delay)
+__device__ __forceinline__ float row_scan16(float x)
+{
+#define NDFT_SHR_ADD(k)                                                                        \
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + (k), 0xf, 0xf, true))
+    NDFT_SHR_ADD(1);
+    NDFT_SHR_ADD(2);
+    NDFT_SHR_ADD(4);
+    NDFT_SHR_ADD(8);
+#undef NDFT_SHR_ADD
+    return x;
+}
+
+// sign bits of two floats at bits 15 (lo) and 31 (hi)
+__device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
+{
+    return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x070c030cu);
+}
+
 // Blocks: blockIdx.x = 16 delays, blockIdx.y = range of whole chunks, blockIdx.z = 256
-// base rows (after row 0 when base 0 is present: base 0 is summed apart from the chunk
-// totals by one thread per delay). For the run sums a thread takes 8 of the delays and two
-// base rows i and M - 1 - i of the group's M rows: the rows ascend in b and the runs per
-// chunk grow with b, so every thread walks about as many runs as any other.
+// base rows (after row 0 when base 0 is present: base 0 is summed apart from the thread
+// totals of z and the sign counts). Lag phase: thread (dl, grp) makes z for delay dl and
+// samples 16 grp .. 16 grp + 15 of the chunk. Crossing phase: a thread takes 8 of the
+// delays and two base rows i and M - 1 - i of the group's M rows: the rows ascend in b and
+// the crossings per chunk grow with b, so every thread walks about as many as any other.
+//
+// Per chunk and part, with P(o) the prefix sum of z over the chunk's first o samples,
+//   sum_k S(k) z_k = S_end P(C) + sum_{crossings k_i < C} S_i (P(k_i) + P(k_i + e_i))
+// (S_i the sign before crossing i, e_i = 1 when it is exact: the zero sample is then a
+// run of its own; S_end the sign after the last crossing). P(k) + P(k) = 2 P(k) and
+// R(k) = P(k) + P(k + 1) are both tables, so a crossing costs one row read either way.
 __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 {
     constexpr int DT = kLsumDelays, C = kLsumChunk;
@@ -168,7 +160,8 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     constexpr int WIT = (WIN + 255) / 256;        // window loads per thread
     __shared__ float4 sw[C + C / 16];             // s with signs (padded index)
     __shared__ float4 rw[RW + RW / 16 + 1];       // r with signs, the block's delays
-    __shared__ float2 pre[DT][C + 1 + (C + 1) / 16 + 1]; // prefix sums of z within the chunk
+    __shared__ float2 ptab[kLsumTabF2]; // P(o), o = 0 .. C
+    __shared__ float2 rtab[kLsumTabF2]; // R(o) = P(o) + P(o + 1), o < C
 
     const int tid = threadIdx.x;
     const int n = L.n;
@@ -181,7 +174,7 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     const int dl = tid >> 4, grp = tid & 15, o0 = grp * SPT;
     const int col = c0 + dl;
 
-    // base work: delays dh * 8 .. + 7, base rows i and M - 1 - i of the group
+    // crossing work: delays dh * 8 .. + 7, base rows i and M - 1 - i of the group
     constexpr int DH = DT / 2;
     const int has0 = L.bm.nseg > 0 && L.bm.start[0] == 0;
     const int row_base = has0 + blockIdx.z * kLsumBases;
@@ -189,8 +182,8 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     const int pi = tid & 127, dh = tid >> 7;
     int bi[2];
     bool own[2];
-    unsigned bb[2], mc[2], dmc[2];
-    float rinv[2];
+    int fb[2], q0[2], r0[2];
+    Crossing cr[2][2]; // [row][part]
     bi[0] = row_base + pi;
     bi[1] = row_base + M - 1 - pi;
     own[0] = pi < M && pi <= M - 1 - pi;
@@ -199,16 +192,20 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const unsigned b = (unsigned)base_of(L.bm, min(max(bi[j], 0), L.n_bases - 1));
-        bb[j] = b;
-        rinv[j] = b > 0 ? 1.0f / (float)(4 * b) : 0.0f;
-        mc[j] = (unsigned)(((long long)b * kb) % n);
-        dmc[j] = (unsigned)(((long long)b * C) % n);
+        fb[j] = 4 * (int)b;
+        q0[j] = b > 0 ? (2 * n) / fb[j] : 0; // >= 1: b <= N / 2
+        r0[j] = b > 0 ? 2 * n - q0[j] * fb[j] : 0;
+        cr[j][0] = first_crossing<0>(b, kb, n);
+        cr[j][1] = first_crossing<1>(b, kb, n);
 #pragma unroll
         for (int d = 0; d < DH; ++d)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[j][d][t] = 0.0f;
     }
-    float u0 = 0.0f, x0 = 0.0f; // base 0 of delay dl (grp = 0)
+    // base 0 of delay dl: sums of z and counts of negative and zero signs (this thread's
+    // samples; the 16 threads of the delay are added at the end)
+    float u0 = 0.0f, x0 = 0.0f;
+    int ngr = 0, ngi = 0, zcr = 0, zci = 0, nfield = 0;
 
     // windows of a chunk (zero outside [0, n)): s[k0 + i], then r[k0 - dmax + i]
     auto win_load = [&](long long k0, float2 (&v)[WIT]) {
@@ -249,7 +246,7 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         float zr[SPT], zi[SPT];
         uint32_t code[4];
         float mz = 3.0e38f; // smallest |component|
-        float pr = 0.0f, pi = 0.0f;
+        float pr = 0.0f, pim = 0.0f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             float vr[4], vi[4];
@@ -261,23 +258,17 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
                 vi[e] = fmaf(a.y, c.z, c.x * a.w) - fmaf(c.y, a.z, a.x * c.w);
                 mz = fminf(mz, fminf(fabsf(vr[e]), fabsf(vi[e])));
             }
-            // A normal FP32 value carries the exact sign and so does its BF16 rounding,
-            // whose (sign, non-zero) bits bf16_signs2 moves into the code positions of a pair.
-            uint32_t g[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float *z = t < 2 ? vr : vi;
-                const int e = 2 * (t & 1);
-                const bf16x2v hv = {(__bf16)z[e], (__bf16)z[e + 1]};
-                (void)bf16_signs2(__builtin_bit_cast(uint32_t, hv), g[t]);
-            }
-            code[w] = g[0] | (g[1] >> 2) | (g[2] >> 4) | (g[3] >> 6);
+            // a normal FP32 value carries the exact sign (see lag_product4): the sign bits
+            // go to the sign positions of the code word, every non-zero bit is set
+            code[w] = (sign_pair(vr[1], vr[0]) & 0x80008000u) | ((sign_pair(vr[3], vr[2]) >> 2) & 0x20002000u) |
+                      ((sign_pair(vi[1], vi[0]) >> 4) & 0x08000800u) |
+                      ((sign_pair(vi[3], vi[2]) >> 6) & 0x02000200u) | 0x55005500u;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 pr += vr[e];
-                pi += vi[e];
+                pim += vi[e];
                 zr[4 * w + e] = pr;
-                zi[4 * w + e] = pi;
+                zi[4 * w + e] = pim;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -293,19 +284,21 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
                     code[w] = (code[w] & ~((3u << pos_r) | (3u << (pos_r - 4)))) | (sign_field(e.sr) << pos_r) |
                               (sign_field(e.si) << (pos_r - 4));
                 }
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    zcr += 4 - __builtin_popcount(code[w] & 0x50005000u);
+                    zci += 4 - __builtin_popcount(code[w] & 0x05000500u);
+                }
             }
         }
-        // sums of the signs: non-zero fields minus twice the negative ones
-        int cnr = 0, cgr = 0, cni = 0, cgi = 0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const uint32_t neg = code[w] & (code[w] >> 1);
-            cnr += __builtin_popcount(code[w] & 0x50005000u);
-            cgr += __builtin_popcount(neg & 0x50005000u);
-            cni += __builtin_popcount(code[w] & 0x05000500u);
-            cgi += __builtin_popcount(neg & 0x05000500u);
+            ngr += __builtin_popcount(code[w] & 0xa000a000u);
+            ngi += __builtin_popcount(code[w] & 0x0a000a00u);
         }
-        float ssr = (float)(cnr - 2 * cgr), ssi = (float)(cni - 2 * cgi);
+        nfield += SPT;
+        u0 += pr;
+        x0 += pim;
         if (col < L.n_cols_pad) {
             const long long k = k0 + o0; // 16-aligned: the words (h, q) and (h, q + 1)
             const long long st = k >> 5;
@@ -314,79 +307,81 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             cw[0] = make_uint2(code[0], code[2]); // h = 0: steps q, q + 1
             cw[2] = make_uint2(code[1], code[3]); // h = 1
         }
-        // prefix sums across the 16 threads of the delay (within the thread: above)
-        float er = pr, ei = pi; // inclusive scan of the thread totals
+        // prefix tables: P(o0 + 1 + j) = (exclusive scan of the thread totals) + zr[j]
+        {
+            const float er = row_scan16(pr) - pr, ei = row_scan16(pim) - pim;
+            float lr = er, li = ei; // P(o0 + j)
+            if (grp == 0) ptab[dl] = make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const float ur = __shfl_up(er, off, 16), ui = __shfl_up(ei, off, 16);
-            if (grp >= off) {
-                er += ur;
-                ei += ui;
+            for (int j = 0; j < SPT; ++j) {
+                const float nr = er + zr[j], ni = ei + zi[j];
+                ptab[prow(o0 + j + 1) + dl] = make_float2(nr, ni);
+                rtab[prow(o0 + j) + dl] = make_float2(lr + nr, li + ni);
+                lr = nr;
+                li = ni;
             }
         }
-        const float tr = __shfl(er, 15, 16), ti = __shfl(ei, 15, 16); // chunk totals
-        er -= pr; // exclusive
-        ei -= pi;
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) pre[dl][lpad(o0 + j + 1)] = make_float2(er + zr[j], ei + zi[j]);
-        if (grp == 0) pre[dl][0] = make_float2(0.0f, 0.0f);
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            ssr += __shfl_xor(ssr, off, 16);
-            ssi += __shfl_xor(ssi, off, 16);
-        }
-        // base 0: W = 1, so the T part is the chunk total of z and the D part that of the signs
-        if (grp == 0) {
-            u0 += tr + ssr;
-            x0 += ti + ssi;
-        }
-        __syncthreads(); // prefix sums complete; the windows are free again
+        __syncthreads(); // prefix tables complete; the windows are free again
 
         if (k0 + C < ke) win_store(nv);
 
-        // ---- T part: runs of constant twiddle sign within the chunk, per part ----
-        // sum_runs S_r (P(e_r) - P(e_{r-1})) = S_last P(C) + sum_{inner ends} (S_r - S_{r+1}) P(e_r)
-        // (Re part into U, X; Im part into Y, V)
+        // ---- T part: crossings within the chunk, per row and part (Re part into U, X;
+        // Im part into Y, V) ----
+        float2 pend[DH]; // P(C) of the thread's delays
+#pragma unroll
+        for (int d = 0; d < DH; ++d) pend[d] = ptab[prow(C) + dh * DH + d];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            if (__builtin_amdgcn_ballot_w64(own[j]) == 0) continue;
+            if (__builtin_amdgcn_ballot_w64(own[j]) == 0) continue; // no row of the wave kept
             auto walk = [&](auto partc) {
                 constexpr int PART = decltype(partc)::value;
                 constexpr int IA = PART == 0 ? 0 : 3, IB = PART == 0 ? 2 : 1; // sums of P.x, P.y
-                unsigned m = mc[j];
-                PartRun rr = part_run<PART>(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
-                int o = rr.len;
-                while (o < C) { // run ends at o inside the chunk
-                    const unsigned mn = m + (unsigned)rr.len * bb[j]; // < 2 N
-                    m = mn >= (unsigned)n ? mn - (unsigned)n : mn;
-                    const PartRun nx = part_run<PART>(m, bb[j], (unsigned)n, rinv[j], (unsigned)C);
-                    const float ds = rr.s - nx.s;
+                Crossing c = cr[j][PART];
+                while (c.nk < C) {
+                    const bool ex = c.rem == 0;
+                    const float2 *t2 = (ex ? rtab : ptab) + prow(c.nk) + dh * DH;
+                    const float wgt = ex ? c.sg : 2.0f * c.sg;
 #pragma unroll
                     for (int d = 0; d < DH; ++d) {
-                        const float2 p = pre[dh * DH + d][lpad(o)];
-                        acc[j][d][IA] = fmaf(ds, p.x, acc[j][d][IA]);
-                        acc[j][d][IB] = fmaf(ds, p.y, acc[j][d][IB]);
+                        const float2 v = t2[d];
+                        acc[j][d][IA] = fmaf(wgt, v.x, acc[j][d][IA]);
+                        acc[j][d][IB] = fmaf(wgt, v.y, acc[j][d][IB]);
                     }
-                    rr = nx;
-                    o += rr.len;
+                    c.sg = -c.sg;
+                    const int t = c.rem - r0[j];
+                    c.nk += q0[j] + (t < 0 ? 1 : 0);
+                    c.rem = t < 0 ? t + fb[j] : t;
                 }
 #pragma unroll
                 for (int d = 0; d < DH; ++d) {
-                    const float2 p = pre[dh * DH + d][lpad(C)];
-                    acc[j][d][IA] = fmaf(rr.s, p.x, acc[j][d][IA]);
-                    acc[j][d][IB] = fmaf(rr.s, p.y, acc[j][d][IB]);
+                    acc[j][d][IA] = fmaf(c.sg, pend[d].x, acc[j][d][IA]);
+                    acc[j][d][IB] = fmaf(c.sg, pend[d].y, acc[j][d][IB]);
                 }
+                c.nk -= C;
+                cr[j][PART] = c;
             };
             walk(std::integral_constant<int, 0>());
             walk(std::integral_constant<int, 1>());
-            mc[j] = (unsigned)add_mod((int)mc[j], (int)dmc[j], n);
         }
-        __syncthreads(); // next window stored, prefix sums read
+        __syncthreads(); // next window stored, prefix tables read
     }
 
+    // base 0: W = 1, so the T part is the sum of z and the D part that of the signs
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        u0 += __shfl_xor(u0, off, 16);
+        x0 += __shfl_xor(x0, off, 16);
+        ngr += __shfl_xor(ngr, off, 16);
+        ngi += __shfl_xor(ngi, off, 16);
+        zcr += __shfl_xor(zcr, off, 16);
+        zci += __shfl_xor(zci, off, 16);
+    }
     float4 *out = L.part + (long long)blockIdx.y * L.n_cols_pad * L.n_bases_pad;
-    if (has0 && blockIdx.z == 0 && grp == 0 && col < L.n_cols)
-        out[(long long)col * L.n_bases_pad] = make_float4(u0, 0.0f, x0, 0.0f);
+    if (has0 && blockIdx.z == 0 && grp == 0 && col < L.n_cols) {
+        const int nf = 16 * nfield; // fields per part over the 16 threads
+        out[(long long)col * L.n_bases_pad] =
+            make_float4(u0 + (float)(nf - zcr - 2 * ngr), 0.0f, x0 + (float)(nf - zci - 2 * ngi), 0.0f);
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         if (!own[j]) continue;

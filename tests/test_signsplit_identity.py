@@ -8,8 +8,9 @@ The split-BF16 sign-split kernels evaluate T by runs of constant csgn(W^{pk}) (i
 changes where pk mod N crosses a multiple of N/4, with a single exact zero there) and D
 on the matrix cores. This test evaluates both halves from the oracle's lag rows and the
 exact twiddle signs (FP64 sums, run by run for T as the kernel walks them) and compares
-T + D with the oracle's surface; it also pins the run rule against the twiddle signs the
-oracle computes sample by sample.
+T + D with the oracle's surface; it also pins the crossing walk of the kernel (the next sign
+change from a remainder, the exact zeros, the P / R prefix tables) against the twiddle signs
+the oracle computes sample by sample.
 """
 import numpy as np
 import pytest
@@ -89,42 +90,87 @@ def test_sign_split_halves_sum_to_surface(shape):
             assert err <= 1e-9 * max(sc[t, q], 1.0), (shape, t, q, got, A[t, q])
 
 
-def part_runs(b, k0, k1, n, part):
-    """Runs of one part of csgn(W^{b k}) alone: the real part changes only where b k mod N
-    crosses N/4 or 3N/4, the imaginary part only where it crosses 0 or N/2 (each exactly
-    zero on such a point)."""
-    out = []
-    k = k0
-    while k < k1:
-        m = (b * k) % n
-        q = int(4 * m >= n) + int(4 * m >= 2 * n) + int(4 * m >= 3 * n)
-        exact = 4 * m == q * n
-        if part == 0:
-            s = 1 if q in (0, 3) else -1
-            s = 0 if exact and q % 2 == 1 else s
-            target = n if q == 0 else (3 * n if q < 3 else 5 * n)
-        else:
-            s = -1 if q < 2 else 1
-            s = 0 if exact and q % 2 == 0 else s
-            target = 2 * n if q < 2 else 4 * n
-        if b == 0:
-            ln = k1 - k
-        elif s == 0:
-            ln = 1
-        else:
-            ln = -(-(target - 4 * m) // (4 * b))
-        ke = min(k1, k + ln)
-        out.append((k, ke, s))
-        k = ke
+def first_crossing(b, kb, n, part):
+    """The walker state at sample kb: offset of the next crossing at or after kb, its rem
+    (4b k_i minus the crossing value; 0 when the crossing sample is the exact zero) and the
+    sign just before it. Crossings of the real part lie at u = N + 2N i, those of the
+    imaginary part at u = 2N i, with u = 4 b k."""
+    if b == 0:
+        return 1 << 30, 1, (1 if part == 0 else 0)
+    fb = 4 * b
+    w = (4 * ((b * kb) % n) - fb) % (4 * n)  # u of sample kb - 1, mod 4N
+    if part == 0:
+        cu = n if w < n else (3 * n if w < 3 * n else 5 * n)
+        sg = -1 if cu == 3 * n else 1
+    else:
+        cu = 2 * n if w < 2 * n else 4 * n
+        sg = -1 if cu == 2 * n else 1
+    d = cu - w
+    cq = -(-d // fb)
+    return cq - 1, cq * fb - d, sg
+
+
+def crossing_step(nk, rem, sg, b, n):
+    """The next crossing: 2N / 4b samples on, in whole samples by the remainder."""
+    fb = 4 * b
+    q0, r0 = (2 * n) // fb, (2 * n) % fb
+    t = rem - r0
+    return nk + q0 + (1 if t < 0 else 0), (t + fb if t < 0 else t), -sg
+
+
+def walk_signs(b, kb, k1, n, part):
+    """Per-sample signs of one part over kb .. k1 - 1 rebuilt from the crossings alone."""
+    out = np.zeros(k1 - kb, int)
+    nk, rem, sg = first_crossing(b, kb, n, part)
+    k = 0
+    while k < k1 - kb:
+        stop = min(nk, k1 - kb)
+        out[k:stop] = sg
+        k = stop
+        if k >= k1 - kb:
+            break
+        if rem == 0:  # exact: the crossing sample itself is zero
+            out[k] = 0
+            k += 1
+        nk, rem, sg = crossing_step(nk, rem, sg, b, n)
     return out
 
 
 @pytest.mark.parametrize("n", [17, 30, 1000, 1002, 4096])
-def test_part_runs_match_quarter_rule(n):
-    for b in list(range(0, min(n, 40))) + list(range(n // 2 - 3, n // 2 + 1)):
+def test_crossing_walk_matches_quarter_rule(n):
+    bases = sorted(set(list(range(0, min(n // 2 + 1, 40))) + list(range(n // 2 - 3, n // 2 + 1))))
+    for b in bases:
+        want = [np.array([quarter_signs((b * k) % n, n)[part] for k in range(2 * n)]) for part in (0, 1)]
+        for kb in (0, 1, 5, n // 4, n // 2 + 1, n - 1, n + 3):
+            for part in (0, 1):
+                got = walk_signs(b, kb, 2 * n, n, part)
+                assert np.array_equal(got, want[part][kb:]), (n, b, kb, part)
+
+
+@pytest.mark.parametrize("shape", [(4096, 7, 256), (1000, 3, 256), (65536, 0, 256), (1200, 11, 64)])
+def test_crossing_tables_give_twiddle_sign_sums(shape):
+    """The sum the kernel forms per chunk: sign after the last crossing times P(C), plus for
+    each crossing the sign before it times 2 P(k) (or R(k) = P(k) + P(k + 1) when exact),
+    equals sum_k csgn(W^{bk}) z_k over a block that starts at kb (FP64, random z)."""
+    n, kb, chunk = shape
+    rng = np.random.default_rng(n + kb)
+    nch = 3
+    z = rng.standard_normal(nch * chunk) + 1j * rng.standard_normal(nch * chunk)
+    k = kb + np.arange(nch * chunk)
+    for b in sorted(set([0, 1, 2, 3, 5, 64, 127, 128, 129, n // 256, n // 8 - 1, n // 2])):
+        sc = np.array([quarter_signs((b * int(kk)) % n, n) for kk in k])
+        want = np.sum(sc[:, 0] * z) + 1j * np.sum(sc[:, 1] * z)
+        got = [0j, 0j]
         for part in (0, 1):
-            got = np.zeros(n, int)
-            for ks, ke, s in part_runs(b, 0, n, n, part):
-                got[ks:ke] = s
-            want = np.array([quarter_signs((b * k) % n, n)[part] for k in range(n)])
-            assert np.array_equal(got, want), (n, b, part)
+            nk, rem, sg = first_crossing(b, kb, n, part)
+            for c in range(nch):
+                zc = z[c * chunk:(c + 1) * chunk]
+                P = np.concatenate([[0], np.cumsum(zc)])
+                R = P[:-1] + P[1:]
+                while nk < chunk:
+                    got[part] += sg * (R[nk] if rem == 0 else 2 * P[nk])
+                    nk, rem, sg = crossing_step(nk, rem, sg, b, n)
+                got[part] += sg * P[chunk]
+                nk -= chunk
+        total = got[0] + 1j * got[1]
+        assert abs(total - want) <= 1e-9 * (1 + np.sum(np.abs(z))), (shape, b, total, want)

@@ -107,9 +107,9 @@ constexpr int kLsumDelays = 16;   // delays per block
 constexpr int kLsumChunk = 256;   // samples per chunk (prefix sums in LDS)
 constexpr int kLsumBases = 256;   // base rows per block
 
-// LDS index with one pad entry per 16: a thread works on 16 consecutive samples, so the
-// lanes of a wave access entries 16 apart; the pad spreads them over the banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// Window index with one pad entry per 8: the lanes of a wave read entries 8 apart, which
+// the pad puts on different banks.
+__device__ __forceinline__ int wpad(int i) { return i + (i >> 3); }
 
 // Prefix tables: row o holds the 16 delays of the block (float2 each) at a stride of 17
 // float2 plus 1 more after every 16 rows. The 16 writers of a delay store rows 16 apart,
@@ -119,16 +119,18 @@ constexpr int kLsumRowF2 = kLsumDelays + 1;
 __device__ __forceinline__ int prow(int o) { return (int)__umul24((unsigned)o, kLsumRowF2) + (o >> 4); }
 constexpr int kLsumTabF2 = kLsumChunk * kLsumRowF2 + (kLsumChunk >> 4) + kLsumDelays;
 
-// inclusive scan over the 16 lanes of a DPP row (the 16 threads of one delay)
-__device__ __forceinline__ float row_scan16(float x)
+// inclusive scan over the 32 lanes of each half wave (the 32 threads of one delay pair):
+// within the DPP rows of 16 lanes, then row 1 (3) adds the last lane of row 0 (2)
+__device__ __forceinline__ float half_scan32(float x)
 {
-#define NDFT_SHR_ADD(k)                                                                        \
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + (k), 0xf, 0xf, true))
-    NDFT_SHR_ADD(1);
-    NDFT_SHR_ADD(2);
-    NDFT_SHR_ADD(4);
-    NDFT_SHR_ADD(8);
-#undef NDFT_SHR_ADD
+#define NDFT_DPP_ADD(ctrl, rows)                                                               \
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, rows, 0xf, true))
+    NDFT_DPP_ADD(0x111, 0xf); // row_shr:1
+    NDFT_DPP_ADD(0x112, 0xf); // row_shr:2
+    NDFT_DPP_ADD(0x114, 0xf); // row_shr:4
+    NDFT_DPP_ADD(0x118, 0xf); // row_shr:8
+    NDFT_DPP_ADD(0x142, 0xa); // row_bcast:15 into rows 1 and 3
+#undef NDFT_DPP_ADD
     return x;
 }
 
@@ -140,8 +142,9 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 
 // Blocks: blockIdx.x = 16 delays, blockIdx.y = range of whole chunks, blockIdx.z = 256
 // base rows (after row 0 when base 0 is present: base 0 is summed apart from the thread
-// totals of z and the sign counts). Lag phase: thread (dl, grp) makes z for delay dl and
-// samples 16 grp .. 16 grp + 15 of the chunk. Crossing phase: a thread takes 8 of the
+// totals of z and the sign counts). Lag phase: thread (dp, g) makes z for the delay pair
+// 2 dp, 2 dp + 1 and samples 8 g .. 8 g + 7 of the chunk (the pair shares the s values and
+// all but one r value). Crossing phase: a thread takes 8 of the
 // delays and two base rows i and M - 1 - i of the group's M rows: the rows ascend in b and
 // the crossings per chunk grow with b, so every thread walks about as many as any other.
 //
@@ -153,13 +156,13 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 {
     constexpr int DT = kLsumDelays, C = kLsumChunk;
-    constexpr int SPT = DT * C / 256; // samples per thread
-    static_assert(SPT == 16, "four code words per thread");
+    constexpr int SPT = DT * C / 512; // samples per thread and delay (two delays each)
+    static_assert(SPT == 8, "two code words per thread and delay");
     constexpr int RW = C + DT - 1;
     constexpr int WIN = C + RW;                   // window entries (s, then r)
     constexpr int WIT = (WIN + 255) / 256;        // window loads per thread
-    __shared__ float4 sw[C + C / 16];             // s with signs (padded index)
-    __shared__ float4 rw[RW + RW / 16 + 1];       // r with signs, the block's delays
+    __shared__ float4 sw[C + C / 8];              // s with signs (padded index)
+    __shared__ float4 rw[RW + RW / 8 + 1];        // r with signs, the block's delays
     __shared__ float2 ptab[kLsumTabF2]; // P(o), o = 0 .. C
     __shared__ float2 rtab[kLsumTabF2]; // R(o) = P(o) + P(o + 1), o < C
 
@@ -170,9 +173,9 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     const long long kb = (long long)blockIdx.y * L.kchunk;
     const long long ke = min(kb + L.kchunk, L.k_end);
 
-    // z work: delay dl, samples o0 .. o0 + 15 of the chunk
-    const int dl = tid >> 4, grp = tid & 15, o0 = grp * SPT;
-    const int col = c0 + dl;
+    // z work: delays dl0 = 2 dp and dl0 + 1, samples o0 .. o0 + 7 of the chunk
+    const int dp = tid >> 5, g = tid & 31, o0 = g * SPT, dl0 = 2 * dp;
+    const int col0 = c0 + dl0;
 
     // crossing work: delays dh * 8 .. + 7, base rows i and M - 1 - i of the group
     constexpr int DH = DT / 2;
@@ -202,10 +205,10 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[j][d][t] = 0.0f;
     }
-    // base 0 of delay dl: sums of z and counts of negative and zero signs (this thread's
-    // samples; the 16 threads of the delay are added at the end)
-    float u0 = 0.0f, x0 = 0.0f;
-    int ngr = 0, ngi = 0, zcr = 0, zci = 0, nfield = 0;
+    // base 0 of delays dl0 + h: sums of z and counts of negative and zero signs (this
+    // thread's samples; the 32 threads of the pair are added at the end)
+    float u0[2] = {0.0f, 0.0f}, x0[2] = {0.0f, 0.0f};
+    int ngr[2] = {0, 0}, ngi[2] = {0, 0}, zcr[2] = {0, 0}, zci[2] = {0, 0}, nfield = 0;
 
     // windows of a chunk (zero outside [0, n)): s[k0 + i], then r[k0 - dmax + i]
     auto win_load = [&](long long k0, float2 (&v)[WIT]) {
@@ -222,9 +225,9 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         for (int it = 0; it < WIT; ++it) {
             const int i = tid + it * 256;
             if (i < C)
-                sw[lpad(i)] = with_signs(v[it]);
+                sw[wpad(i)] = with_signs(v[it]);
             else if (i < WIN)
-                rw[lpad(i - C)] = with_signs(v[it]);
+                rw[wpad(i - C)] = with_signs(v[it]);
         }
     };
 
@@ -238,37 +241,49 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         float2 nv[WIT]; // next chunk's window, in flight during this chunk
         if (k0 + C < ke) win_load(k0 + C, nv);
 
-        // ---- lag products of (dl, o0 .. o0 + 15): FP32 values (the operations of
+        // ---- lag products of (dl0 + h, o0 .. o0 + 7): FP32 values (the operations of
         // lag_product4), their signs as codes ----
         // In groups of four samples (a scheduling barrier between groups keeps the loads
-        // of one group in registers at a time): the values, their code word, and the
-        // running prefix within the thread (zr, zi end up holding it).
-        float zr[SPT], zi[SPT];
-        uint32_t code[4];
+        // of one group in registers at a time): the values, the code word of each delay,
+        // and the running prefix within the thread (zr, zi end up holding it). Delay dl0 + h
+        // pairs sample o0 + j with r entry o0 + j + 15 - dl0 - h = rb + j + 1 - h.
+        const int rb = o0 + DT - 2 - dl0;
+        float zr[2][SPT], zi[2][SPT];
+        uint32_t code[2][2]; // [delay][half]
         float mz = 3.0e38f; // smallest |component|
-        float pr = 0.0f, pim = 0.0f;
+        float pr[2] = {0.0f, 0.0f}, pim[2] = {0.0f, 0.0f};
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            float vr[4], vi[4];
+        for (int w = 0; w < 2; ++w) {
+            // sample 4 w + e meets r entries cn (delay dl0) and cp (delay dl0 + 1)
+            float vr[2][4], vi[2][4];
+            float4 cp = rw[wpad(rb + 4 * w)];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int j = 4 * w + e;
-                const float4 a = sw[lpad(o0 + j)], c = rw[lpad(o0 + j + (DT - 1 - dl))];
-                vr[e] = fmaf(a.x, c.z, c.x * a.z) + fmaf(a.y, c.w, c.y * a.w);
-                vi[e] = fmaf(a.y, c.z, c.x * a.w) - fmaf(c.y, a.z, a.x * c.w);
-                mz = fminf(mz, fminf(fabsf(vr[e]), fabsf(vi[e])));
+                const float4 a = sw[wpad(o0 + 4 * w + e)], cn = rw[wpad(rb + 4 * w + e + 1)];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float4 cc = h == 0 ? cn : cp;
+                    vr[h][e] = fmaf(a.x, cc.z, cc.x * a.z) + fmaf(a.y, cc.w, cc.y * a.w);
+                    vi[h][e] = fmaf(a.y, cc.z, cc.x * a.w) - fmaf(cc.y, a.z, a.x * cc.w);
+                    mz = fminf(mz, fminf(fabsf(vr[h][e]), fabsf(vi[h][e])));
+                }
+                cp = cn;
             }
-            // a normal FP32 value carries the exact sign (see lag_product4): the sign bits
-            // go to the sign positions of the code word, every non-zero bit is set
-            code[w] = (sign_pair(vr[1], vr[0]) & 0x80008000u) | ((sign_pair(vr[3], vr[2]) >> 2) & 0x20002000u) |
-                      ((sign_pair(vi[1], vi[0]) >> 4) & 0x08000800u) |
-                      ((sign_pair(vi[3], vi[2]) >> 6) & 0x02000200u) | 0x55005500u;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                pr += vr[e];
-                pim += vi[e];
-                zr[4 * w + e] = pr;
-                zi[4 * w + e] = pim;
+            for (int h = 0; h < 2; ++h) {
+                // a normal FP32 value carries the exact sign (see lag_product4): the sign
+                // bits go to the sign positions of the code word, every non-zero bit is set
+                code[h][w] = (sign_pair(vr[h][1], vr[h][0]) & 0x80008000u) |
+                             ((sign_pair(vr[h][3], vr[h][2]) >> 2) & 0x20002000u) |
+                             ((sign_pair(vi[h][1], vi[h][0]) >> 4) & 0x08000800u) |
+                             ((sign_pair(vi[h][3], vi[h][2]) >> 6) & 0x02000200u) | 0x55005500u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    pr[h] += vr[h][e];
+                    pim[h] += vi[h][e];
+                    zr[h][4 * w + e] = pr[h];
+                    zi[h][4 * w + e] = pim[h];
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -277,48 +292,82 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         if (__builtin_amdgcn_ballot_w64(!(mz >= 1.17549435e-38f))) {
             if (!(mz >= 1.17549435e-38f)) {
 #pragma unroll
-                for (int j = 0; j < SPT; ++j) {
-                    const Lag e = lag_product4(sw[lpad(o0 + j)], rw[lpad(o0 + j + (DT - 1 - dl))]);
-                    const int w = j >> 2, q = j & 3;
-                    const int pos_r = (q & 1) ? 30 - 2 * (q >> 1) : 14 - 2 * (q >> 1); // k0:14 k1:30 k2:12 k3:28
-                    code[w] = (code[w] & ~((3u << pos_r) | (3u << (pos_r - 4)))) | (sign_field(e.sr) << pos_r) |
-                              (sign_field(e.si) << (pos_r - 4));
-                }
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
+                    for (int j = 0; j < SPT; ++j) { // rolled: the FP64 test is long and rare
+                        const Lag e = lag_product4(sw[wpad(o0 + j)], rw[wpad(rb + j + 1 - h)]);
+                        const int q = j & 3;
+                        const int pos_r = (q & 1) ? 30 - 2 * (q >> 1) : 14 - 2 * (q >> 1); // k0:14 k1:30 k2:12 k3:28
+                        const uint32_t keep = ~((3u << pos_r) | (3u << (pos_r - 4)));
+                        const uint32_t f = (sign_field(e.sr) << pos_r) | (sign_field(e.si) << (pos_r - 4));
+                        const bool w1 = j >= 4;
+                        const uint32_t cw = ((w1 ? code[h][1] : code[h][0]) & keep) | f;
+                        code[h][0] = w1 ? code[h][0] : cw;
+                        code[h][1] = w1 ? cw : code[h][1];
+                    }
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    zcr += 4 - __builtin_popcount(code[w] & 0x50005000u);
-                    zci += 4 - __builtin_popcount(code[w] & 0x05000500u);
+                    for (int w = 0; w < 2; ++w) {
+                        zcr[h] += 4 - __builtin_popcount(code[h][w] & 0x50005000u);
+                        zci[h] += 4 - __builtin_popcount(code[h][w] & 0x05000500u);
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            ngr += __builtin_popcount(code[w] & 0xa000a000u);
-            ngi += __builtin_popcount(code[w] & 0x0a000a00u);
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                ngr[h] += __builtin_popcount(code[h][w] & 0xa000a000u);
+                ngi[h] += __builtin_popcount(code[h][w] & 0x0a000a00u);
+            }
+            u0[h] += pr[h];
+            x0[h] += pim[h];
         }
         nfield += SPT;
-        u0 += pr;
-        x0 += pim;
-        if (col < L.n_cols_pad) {
-            const long long k = k0 + o0; // 16-aligned: the words (h, q) and (h, q + 1)
+        {
+            // the thread's 8 samples are one step q of a 32-sample stage: word (w, q) holds
+            // samples 8 q + 4 w .. + 3
+            const long long k = k0 + o0;
             const long long st = k >> 5;
             const int q = (int)((k >> 3) & 3);
-            uint2 *cw = reinterpret_cast<uint2 *>(L.codes + ((st * L.n_cols_pad + col) * 2) * 4 + q);
-            cw[0] = make_uint2(code[0], code[2]); // h = 0: steps q, q + 1
-            cw[2] = make_uint2(code[1], code[3]); // h = 1
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (col0 + h < L.n_cols_pad) {
+                    uint32_t *cw = L.codes + ((st * L.n_cols_pad + col0 + h) * 2) * 4 + q;
+                    cw[0] = code[h][0];
+                    cw[4] = code[h][1];
+                }
+            }
         }
         // prefix tables: P(o0 + 1 + j) = (exclusive scan of the thread totals) + zr[j]
         {
-            const float er = row_scan16(pr) - pr, ei = row_scan16(pim) - pim;
-            float lr = er, li = ei; // P(o0 + j)
-            if (grp == 0) ptab[dl] = make_float2(0.0f, 0.0f);
+            float er[2], ei[2], lr[2], li[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                er[h] = half_scan32(pr[h]) - pr[h];
+                ei[h] = half_scan32(pim[h]) - pim[h];
+                lr[h] = er[h]; // P(o0 + j)
+                li[h] = ei[h];
+            }
+            if (g == 0) ptab[dl0] = ptab[dl0 + 1] = make_float2(0.0f, 0.0f);
 #pragma unroll
             for (int j = 0; j < SPT; ++j) {
-                const float nr = er + zr[j], ni = ei + zi[j];
-                ptab[prow(o0 + j + 1) + dl] = make_float2(nr, ni);
-                rtab[prow(o0 + j) + dl] = make_float2(lr + nr, li + ni);
-                lr = nr;
-                li = ni;
+                float nr[2], ni[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    nr[h] = er[h] + zr[h][j];
+                    ni[h] = ei[h] + zi[h][j];
+                }
+                float2 *pp = ptab + prow(o0 + j + 1) + dl0, *rp = rtab + prow(o0 + j) + dl0;
+                pp[0] = make_float2(nr[0], ni[0]);
+                pp[1] = make_float2(nr[1], ni[1]);
+                rp[0] = make_float2(lr[0] + nr[0], li[0] + ni[0]);
+                rp[1] = make_float2(lr[1] + nr[1], li[1] + ni[1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    lr[h] = nr[h];
+                    li[h] = ni[h];
+                }
             }
         }
         __syncthreads(); // prefix tables complete; the windows are free again
@@ -367,20 +416,23 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     }
 
     // base 0: W = 1, so the T part is the sum of z and the D part that of the signs
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-        u0 += __shfl_xor(u0, off, 16);
-        x0 += __shfl_xor(x0, off, 16);
-        ngr += __shfl_xor(ngr, off, 16);
-        ngi += __shfl_xor(ngi, off, 16);
-        zcr += __shfl_xor(zcr, off, 16);
-        zci += __shfl_xor(zci, off, 16);
-    }
     float4 *out = L.part + (long long)blockIdx.y * L.n_cols_pad * L.n_bases_pad;
-    if (has0 && blockIdx.z == 0 && grp == 0 && col < L.n_cols) {
-        const int nf = 16 * nfield; // fields per part over the 16 threads
-        out[(long long)col * L.n_bases_pad] =
-            make_float4(u0 + (float)(nf - zcr - 2 * ngr), 0.0f, x0 + (float)(nf - zci - 2 * ngi), 0.0f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+            u0[h] += __shfl_xor(u0[h], off, 32);
+            x0[h] += __shfl_xor(x0[h], off, 32);
+            ngr[h] += __shfl_xor(ngr[h], off, 32);
+            ngi[h] += __shfl_xor(ngi[h], off, 32);
+            zcr[h] += __shfl_xor(zcr[h], off, 32);
+            zci[h] += __shfl_xor(zci[h], off, 32);
+        }
+        if (has0 && blockIdx.z == 0 && g == 0 && col0 + h < L.n_cols) {
+            const int nf = 32 * nfield; // fields per part over the 32 threads
+            out[(long long)(col0 + h) * L.n_bases_pad] = make_float4(u0[h] + (float)(nf - zcr[h] - 2 * ngr[h]), 0.0f,
+                                                                    x0[h] + (float)(nf - zci[h] - 2 * ngi[h]), 0.0f);
+        }
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {

@@ -187,6 +187,43 @@ def test_deterministic(nd, prec):
     assert torch.equal(a, b)
 
 
+def test_caf_split_graph_replay(nd):
+    """The sign-split form (twiddle planes, lsum_kernel, dsum_kernel, reduction) captured
+    into a graph: every replay (with unrelated eager work and a cleared workspace between)
+    must equal the eager call."""
+    names = [nd.plan_name(1, k) for k in range(nd.plan_count(1))]
+    plan = names.index("bf16x2s_b64_l128_w4_ks32")
+    n, tau0, n_tau, p0, n_dop = 8192, 3, 100, -32, 64
+    s, r = synth.random_pair(n, seed=21, zeros=0.02)
+    S, R = dev(s), dev(r)
+    nd.set_plan(1, plan, 0)
+    try:
+        ws = torch.empty(nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 1), dtype=torch.uint8, device="cuda")
+        eager = nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=1, ws=ws)
+        out = torch.zeros_like(eager)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=1, out=out, ws=ws)  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(stream)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=1, out=out, ws=ws)
+        for rep in range(3):
+            out.zero_()
+            ws.zero_()
+            junk = torch.randn(1 << 20, device="cuda") * 2  # unrelated eager work in between
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), rep
+            del junk
+    finally:
+        nd.set_plan(1, -1, 0)
+
+
 # ------------------------------------------------------------------------------------
 # Sign operands: bit-exact
 # ------------------------------------------------------------------------------------

@@ -470,7 +470,8 @@ struct DsumCfg {
     static constexpr int G = KS / 8;             // 8-sample steps per stage
     static constexpr int STAGE_A = G * 4 * BT;   // uint4 per stage (step, A1/A2, h, row)
     static constexpr int UNITS = G * 2 * BT;     // (step, h, row): four samples, both operands
-    static_assert(KS == 32, "one code stage per stage");
+    static constexpr int CW = KS / 32;           // code stages (32 samples) per stage
+    static_assert(KS % 32 == 0, "whole code stages per stage");
 };
 
 // Twiddle operands of one unit (base b, four consecutive samples from index m): W^m / 2
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
                                                          long long code_stages)
 {
     using Cfg = DsumCfg<NW, WB, KS>;
-    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, STAGE_A = Cfg::STAGE_A;
+    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, G = Cfg::G, STAGE_A = Cfg::STAGE_A, CW = Cfg::CW;
     constexpr int PLI = STAGE_A / NT;
     constexpr int UPT = (Cfg::UNITS + NT - 1) / NT; // generated units per thread
     static_assert(STAGE_A % NT == 0, "plane stages split evenly");
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
     };
 
     AFrag fa[2];
-    uint4 cw = make_uint4(0u, 0u, 0u, 0u);
+    uint4 cw[CW];
     auto stage = [&](auto cbc) {
         constexpr int CB = decltype(cbc)::value;
         // two LDS variables so the compiler tells the plane copy's target from the stage read
@@ -664,13 +665,15 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
                                                  (__attribute__((address_space(3))) void *)(dst + k * NT), 16, 0, 0);
             pl_src += STAGE_A;
         }
-        const uint4 cn = code_load(cst + 1);
+        uint4 cn[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) cn[c] = code_load(cst + CW + c);
         load_a(cur, 0, fa[0]);
-        const uint32_t cwv[4] = {cw.x, cw.y, cw.z, cw.w};
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             if (q + 1 < G) load_a(cur, q + 1, fa[(q + 1) & 1]);
-            mfma_step(fa[q & 1], cwv[q]);
+            const uint4 cq = cw[q >> 2];
+            mfma_step(fa[q & 1], (q & 3) == 0 ? cq.x : (q & 3) == 1 ? cq.y : (q & 3) == 2 ? cq.z : cq.w);
             // GEN: the next stage's units while this step's matrix instructions run
             if (GEN) {
 #pragma unroll
@@ -678,8 +681,9 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
                     if ((it * G) / UPT == q) gen_unit(nxt, it);
             }
         }
-        cw = cn;
-        ++cst;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) cw[c] = cn[c];
+        cst += CW;
         if (!GEN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); // plane block landed before the barrier
         __syncthreads();
     };
@@ -694,7 +698,8 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
             for (int k = 0; k < PLI; ++k) dst[k * NT] = src[k * NT];
             pl_src += STAGE_A;
         }
-        cw = code_load(cst);
+#pragma unroll
+        for (int c = 0; c < CW; ++c) cw[c] = code_load(cst + c);
         __syncthreads();
         for (int p = 0; p < npair; ++p) {
             stage(std::integral_constant<int, 0>());

@@ -238,6 +238,7 @@ const std::vector<Plan> &plans(int prec)
         make_split_plan<4, 2, 64, false>("bf16x2s_b64_l128_w4_ks64", 0.96),
         make_split_plan<8, 2, 64, false>("bf16x2s_b64_l256_w8_ks64", 0.97),
         make_split_plan<8, 2, 128, false>("bf16x2s_b64_l256_w8_ks128", 0.85),
+        make_split_plan<8, 2, 128, true>("bf16x2g_b64_l256_w8_ks128", 0.8),
     };
     return prec == NDFT_FP8 ? fp8 : (prec == NDFT_BF16X2 ? bf16 : f32);
 }

@@ -148,11 +148,13 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 // delays and two base rows i and M - 1 - i of the group's M rows: the rows ascend in b and
 // the crossings per chunk grow with b, so every thread walks about as many as any other.
 //
-// Per chunk and part, with P(o) the prefix sum of z over the chunk's first o samples,
-//   sum_k S(k) z_k = S_end P(C) + sum_{crossings k_i < C} S_i (P(k_i) + P(k_i + e_i))
+// Per part, with P(k) the prefix sum of z over the block's first k samples,
+//   sum_k S(k) z_k = S_end P(K) + sum_{crossings k_i < K} S_i (P(k_i) + P(k_i + e_i))
 // (S_i the sign before crossing i, e_i = 1 when it is exact: the zero sample is then a
-// run of its own; S_end the sign after the last crossing). P(k) + P(k) = 2 P(k) and
-// R(k) = P(k) + P(k + 1) are both tables, so a crossing costs one row read either way.
+// run of its own; S_end the sign after the last crossing, K the block's samples). Each
+// chunk's tables hold P at its C + 1 sample edges, the earlier chunks' sum included:
+// P(k) + P(k) = 2 P(k) and R(k) = P(k) + P(k + 1), so a crossing costs one row read
+// either way, and the end term comes once per block.
 __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 {
     constexpr int DT = kLsumDelays, C = kLsumChunk;
@@ -205,9 +207,10 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[j][d][t] = 0.0f;
     }
-    // base 0 of delays dl0 + h: sums of z and counts of negative and zero signs (this
+    // sum of z over the block's earlier chunks, delays dl0 + h (the prefix tables hold
+    // block prefix sums); base 0 of those delays: counts of negative and zero signs (this
     // thread's samples; the 32 threads of the pair are added at the end)
-    float u0[2] = {0.0f, 0.0f}, x0[2] = {0.0f, 0.0f};
+    float2 gq[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
     int ngr[2] = {0, 0}, ngi[2] = {0, 0}, zcr[2] = {0, 0}, zci[2] = {0, 0}, nfield = 0;
 
     // windows of a chunk (zero outside [0, n)): s[k0 + i], then r[k0 - dmax + i]
@@ -320,8 +323,6 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
                 ngr[h] += __builtin_popcount(code[h][w] & 0xa000a000u);
                 ngi[h] += __builtin_popcount(code[h][w] & 0x0a000a00u);
             }
-            u0[h] += pr[h];
-            x0[h] += pim[h];
         }
         nfield += SPT;
         {
@@ -339,17 +340,21 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
                 }
             }
         }
-        // prefix tables: P(o0 + 1 + j) = (exclusive scan of the thread totals) + zr[j]
+        // prefix tables: P(o0 + 1 + j) = (earlier chunks) + (exclusive scan of the thread
+        // totals) + zr[j]
         {
             float er[2], ei[2], lr[2], li[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                er[h] = half_scan32(pr[h]) - pr[h];
-                ei[h] = half_scan32(pim[h]) - pim[h];
+                er[h] = (half_scan32(pr[h]) - pr[h]) + gq[h].x;
+                ei[h] = (half_scan32(pim[h]) - pim[h]) + gq[h].y;
                 lr[h] = er[h]; // P(o0 + j)
                 li[h] = ei[h];
             }
-            if (g == 0) ptab[dl0] = ptab[dl0 + 1] = make_float2(0.0f, 0.0f);
+            if (g == 0) {
+                ptab[dl0] = gq[0];
+                ptab[dl0 + 1] = gq[1];
+            }
 #pragma unroll
             for (int j = 0; j < SPT; ++j) {
                 float nr[2], ni[2];
@@ -371,14 +376,13 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             }
         }
         __syncthreads(); // prefix tables complete; the windows are free again
+        gq[0] = ptab[prow(C) + dl0];
+        gq[1] = ptab[prow(C) + dl0 + 1];
 
         if (k0 + C < ke) win_store(nv);
 
         // ---- T part: crossings within the chunk, per row and part (Re part into U, X;
         // Im part into Y, V) ----
-        float2 pend[DH]; // P(C) of the thread's delays
-#pragma unroll
-        for (int d = 0; d < DH; ++d) pend[d] = ptab[prow(C) + dh * DH + d];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             if (__builtin_amdgcn_ballot_w64(own[j]) == 0) continue; // no row of the wave kept
@@ -401,11 +405,6 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
                     c.nk += q0[j] + (t < 0 ? 1 : 0);
                     c.rem = t < 0 ? t + fb[j] : t;
                 }
-#pragma unroll
-                for (int d = 0; d < DH; ++d) {
-                    acc[j][d][IA] = fmaf(c.sg, pend[d].x, acc[j][d][IA]);
-                    acc[j][d][IB] = fmaf(c.sg, pend[d].y, acc[j][d][IB]);
-                }
                 c.nk -= C;
                 cr[j][PART] = c;
             };
@@ -414,6 +413,20 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         }
         __syncthreads(); // next window stored, prefix tables read
     }
+    // the sign after the last crossing times the block total (the last table's row C)
+    if (ke > kb) {
+#pragma unroll
+        for (int d = 0; d < DH; ++d) {
+            const float2 q = ptab[prow(C) + dh * DH + d];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc[j][d][0] = fmaf(cr[j][0].sg, q.x, acc[j][d][0]);
+                acc[j][d][2] = fmaf(cr[j][0].sg, q.y, acc[j][d][2]);
+                acc[j][d][3] = fmaf(cr[j][1].sg, q.x, acc[j][d][3]);
+                acc[j][d][1] = fmaf(cr[j][1].sg, q.y, acc[j][d][1]);
+            }
+        }
+    }
 
     // base 0: W = 1, so the T part is the sum of z and the D part that of the signs
     float4 *out = L.part + (long long)blockIdx.y * L.n_cols_pad * L.n_bases_pad;
@@ -421,8 +434,6 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int off = 16; off > 0; off >>= 1) {
-            u0[h] += __shfl_xor(u0[h], off, 32);
-            x0[h] += __shfl_xor(x0[h], off, 32);
             ngr[h] += __shfl_xor(ngr[h], off, 32);
             ngi[h] += __shfl_xor(ngi[h], off, 32);
             zcr[h] += __shfl_xor(zcr[h], off, 32);
@@ -430,8 +441,8 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
         }
         if (has0 && blockIdx.z == 0 && g == 0 && col0 + h < L.n_cols) {
             const int nf = 32 * nfield; // fields per part over the 32 threads
-            out[(long long)(col0 + h) * L.n_bases_pad] = make_float4(u0[h] + (float)(nf - zcr[h] - 2 * ngr[h]), 0.0f,
-                                                                    x0[h] + (float)(nf - zci[h] - 2 * ngi[h]), 0.0f);
+            out[(long long)(col0 + h) * L.n_bases_pad] = make_float4(gq[h].x + (float)(nf - zcr[h] - 2 * ngr[h]), 0.0f,
+                                                                    gq[h].y + (float)(nf - zci[h] - 2 * ngi[h]), 0.0f);
         }
     }
 #pragma unroll

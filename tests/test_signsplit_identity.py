@@ -149,9 +149,11 @@ def test_crossing_walk_matches_quarter_rule(n):
 
 @pytest.mark.parametrize("shape", [(4096, 7, 256), (1000, 3, 256), (65536, 0, 256), (1200, 11, 64)])
 def test_crossing_tables_give_twiddle_sign_sums(shape):
-    """The sum the kernel forms per chunk: sign after the last crossing times P(C), plus for
-    each crossing the sign before it times 2 P(k) (or R(k) = P(k) + P(k + 1) when exact),
-    equals sum_k csgn(W^{bk}) z_k over a block that starts at kb (FP64, random z)."""
+    """The sum the kernel forms over a block that starts at kb, chunk by chunk: for each
+    crossing the sign before it times 2 P(k) (or R(k) = P(k) + P(k + 1) when exact), P the
+    prefix sum over the block (each chunk's table starts from the earlier chunks' total),
+    plus the sign after the last crossing times the block total, equals
+    sum_k csgn(W^{bk}) z_k (FP64, random z)."""
     n, kb, chunk = shape
     rng = np.random.default_rng(n + kb)
     nch = 3
@@ -163,14 +165,16 @@ def test_crossing_tables_give_twiddle_sign_sums(shape):
         got = [0j, 0j]
         for part in (0, 1):
             nk, rem, sg = first_crossing(b, kb, n, part)
+            g = 0j  # sum over the earlier chunks
             for c in range(nch):
                 zc = z[c * chunk:(c + 1) * chunk]
-                P = np.concatenate([[0], np.cumsum(zc)])
+                P = g + np.concatenate([[0], np.cumsum(zc)])
                 R = P[:-1] + P[1:]
                 while nk < chunk:
                     got[part] += sg * (R[nk] if rem == 0 else 2 * P[nk])
                     nk, rem, sg = crossing_step(nk, rem, sg, b, n)
-                got[part] += sg * P[chunk]
+                g = P[chunk]
                 nk -= chunk
+            got[part] += sg * g
         total = got[0] + 1j * got[1]
         assert abs(total - want) <= 1e-9 * (1 + np.sum(np.abs(z))), (shape, b, total, want)

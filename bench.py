@@ -149,7 +149,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=100)  # clocks settle after ~100 calls
     ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2", "fp8"])
     ap.add_argument("--forms", default="fp32,bf16x2,fp8", help="forms to time (comma list)")
     ap.add_argument("--autotune", action="store_true",

@@ -588,6 +588,9 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         GEN ? nullptr : P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
     // GEN: thread units (step q, half h, row) -> twiddle index m of the unit's first sample
     float2 *coarse = tables, *fine = tables + P.n_coarse;
+    // When the block's threads cover whole (h, row) sets, a thread's units share the row
+    // and h (only the step differs): one base, step and offset for all of them.
+    constexpr bool SAME_ROW = NT % (2 * BT) == 0 && Cfg::UNITS % NT == 0;
     int un_off[UPT], un_m[UPT], un_dm[UPT];
     float2 un_wb[UPT];
     if (GEN) {
@@ -611,10 +614,11 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
     auto gen_unit = [&](uint4 *buf, int it) { // unit it of the stage after the last generated one
         if (Cfg::UNITS % NT == 0 || tid + it * NT < Cfg::UNITS) {
             uint4 a1, a2;
-            dsum_unit(coarse, fine, P.tb, un_m[it], un_wb[it], a1, a2);
-            buf[un_off[it]] = a1;
-            buf[un_off[it] + 2 * BT] = a2;
-            un_m[it] = add_mod(un_m[it], un_dm[it], P.n);
+            const int off = SAME_ROW ? un_off[0] + it * 2 * NT : un_off[it]; // NT units = 2 NT uint4
+            dsum_unit(coarse, fine, P.tb, un_m[it], un_wb[SAME_ROW ? 0 : it], a1, a2);
+            buf[off] = a1;
+            buf[off + 2 * BT] = a2;
+            un_m[it] = add_mod(un_m[it], un_dm[SAME_ROW ? 0 : it], P.n);
         }
     };
     auto gen = [&](uint4 *buf) {
@@ -676,13 +680,14 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
                                                  (__attribute__((address_space(3))) void *)(dst + k * NT), 16, 0, 0);
             pl_src += STAGE_A;
         }
-        uint4 cn[CW];
-#pragma unroll
-        for (int c = 0; c < CW; ++c) cn[c] = code_load(cst + CW + c);
+        uint4 cn[CW]; // the next stage's code words, each loaded as its slot here frees
         load_a(cur, 0, fa[0]);
 #pragma unroll
         for (int q = 0; q < G; ++q) {
+            if ((q & 3) == 0) cn[q >> 2] = code_load(cst + CW + (q >> 2));
             if (q + 1 < G) load_a(cur, q + 1, fa[(q + 1) & 1]);
+            // the next step's operand reads stay ahead of this step's matrix instructions
+            __builtin_amdgcn_sched_barrier(0);
             const uint4 cq = cw[q >> 2];
             mfma_step(fa[q & 1], (q & 3) == 0 ? cq.x : (q & 3) == 1 ? cq.y : (q & 3) == 2 ? cq.z : cq.w);
             // GEN: the next stage's units while this step's matrix instructions run

@@ -651,21 +651,29 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
             for (int t = 0; t < 2; ++t)
                 f.a[i][t] = __builtin_bit_cast(bf16x8, buf[((q * 2 + t) * 2 + h) * BT + 32 * i + l32]);
     };
-    auto mfma_step = [&](const AFrag &f, uint32_t w) {
+    // sign operands of one step from its code word: B1 real signs, B2 imaginary signs
+    struct BFrag {
+        bf16x8 b1, b2;
+    };
+    auto make_b = [&](uint32_t w, BFrag &g) {
         constexpr uint32_t M = 0xC000C000u;
         const uint32_t r01 = w & M, r23 = (w << 2) & M, i01 = (w << 4) & M, i23 = (w << 6) & M;
-        const bf16x8 b1 = __builtin_bit_cast(bf16x8, make_uint4(r01, r23, r01, r23));
-        const bf16x8 b2 = __builtin_bit_cast(bf16x8, make_uint4(i01, i23, i01, i23));
+        g.b1 = __builtin_bit_cast(bf16x8, make_uint4(r01, r23, r01, r23));
+        g.b2 = __builtin_bit_cast(bf16x8, make_uint4(i01, i23, i01, i23));
+    };
+    auto mfma_step = [&](const AFrag &f, const BFrag &g) {
 #pragma unroll
         for (int i = 0; i < WB; ++i) {
-            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b1, acc[i][0], 0, 0, 0);
-            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], b2, acc[i][1], 0, 0, 0);
-            acc[i][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b1, acc[i][2], 0, 0, 0);
-            acc[i][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], b2, acc[i][3], 0, 0, 0);
+            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], g.b1, acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], g.b2, acc[i][1], 0, 0, 0);
+            acc[i][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], g.b1, acc[i][2], 0, 0, 0);
+            acc[i][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], g.b2, acc[i][3], 0, 0, 0);
         }
     };
+    auto word = [](const uint4 &c, int q) { return (q & 3) == 0 ? c.x : (q & 3) == 1 ? c.y : (q & 3) == 2 ? c.z : c.w; };
 
     AFrag fa[2];
+    BFrag fb[2];
     uint4 cw[CW];
     auto stage = [&](auto cbc) {
         constexpr int CB = decltype(cbc)::value;
@@ -682,14 +690,18 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         }
         uint4 cn[CW]; // the next stage's code words, each loaded as its slot here frees
         load_a(cur, 0, fa[0]);
+        make_b(cw[0].x, fb[0]);
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             if ((q & 3) == 0) cn[q >> 2] = code_load(cst + CW + (q >> 2));
-            if (q + 1 < G) load_a(cur, q + 1, fa[(q + 1) & 1]);
-            // the next step's operand reads stay ahead of this step's matrix instructions
+            if (q + 1 < G) {
+                load_a(cur, q + 1, fa[(q + 1) & 1]);
+                make_b(word(cw[(q + 1) >> 2], q + 1), fb[(q + 1) & 1]);
+            }
+            // the next step's operands stay ahead of this step's matrix instructions (and
+            // are made in registers those instructions do not read)
             __builtin_amdgcn_sched_barrier(0);
-            const uint4 cq = cw[q >> 2];
-            mfma_step(fa[q & 1], (q & 3) == 0 ? cq.x : (q & 3) == 1 ? cq.y : (q & 3) == 2 ? cq.z : cq.w);
+            mfma_step(fa[q & 1], fb[q & 1]);
             // GEN: the next stage's units while this step's matrix instructions run
             if (GEN) {
 #pragma unroll

@@ -1033,6 +1033,7 @@ ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t
     P.n = (int)n;
     P.n_tau = (int)n_tau;
     P.n_bases_pad = L.n_bases_pad;
+    P.inv_n = 1.0 / (double)n;
     P.dz = dz;
     dim3 grid((unsigned)(cdiv(n_tau, 64) * cdiv(n, 128)));
     {
@@ -1044,7 +1045,7 @@ ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t
         prof.stop();
     }
     if ((st = check_launch()) != NDFT_OK) return st;
-    hipLaunchKernelGGL(adj_band_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, dz,
+    hipLaunchKernelGGL(adj_band_kernel, dim3((unsigned)cdiv(n, kAdjBandOut)), dim3(kAdjBandOut * kAdjBandGroups), 0, s, dz,
                        reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), (int)n,
                        (int)tau0, (int)n_tau, reinterpret_cast<float2 *>(grad_ref),
                        reinterpret_cast<float2 *>(grad_surv));

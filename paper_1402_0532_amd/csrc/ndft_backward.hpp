@@ -52,7 +52,8 @@ struct AdjParams {
     const float4 *eo; // [n_bases_pad][n_tau]
     BaseMap bm;
     int n, n_tau, n_bases_pad;
-    float2 *dz; // [n_tau][n]
+    double inv_n; // 1 / n rounded
+    float2 *dz;   // [n_tau][n]
 };
 
 // dz tile: 64 delays x 128 samples per work-group (4 waves of 32 x 64), K = bases.
@@ -94,7 +95,12 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
             int k = u / IT, c = u % IT;
             int i = min(i0 + c, n - 1);
             int b = base_of(P.bm, kb0 + k);
-            int m = (int)(((unsigned long long)b * (unsigned long long)i) % (unsigned long long)n);
+            // m = b i mod n: the product (< 2^48) and the remainder are exact in FP64, the
+            // quotient from the rounded reciprocal is off by at most one either way
+            const double prod = (double)b * (double)i;
+            double rem = fma(-floor(prod * P.inv_n), (double)n, prod);
+            rem = rem < 0.0 ? rem + (double)n : (rem >= (double)n ? rem - (double)n : rem);
+            const int m = (int)rem;
             TwSign g = twiddle_sign(m, n);
             sB[k][c] = make_float2((float)g.c, (float)g.t);
         }
@@ -155,40 +161,55 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
 }
 
 // grad_r[m] = sum_l conj(dz[l][m + d_l]) csgn(s[m + d_l]); grad_s[i] = sum_l dz[l][i] csgn(r[i - d_l]).
-// One thread per output element, delays summed in ascending order.
-__global__ __launch_bounds__(256) void adj_band_kernel(const float2 *__restrict__ dz, const float2 *__restrict__ s,
-                                                       const float2 *__restrict__ r, int n, int tau0, int n_tau,
-                                                       float2 *__restrict__ grad_r, float2 *__restrict__ grad_s)
+// A block takes kAdjBandOut consecutive outputs; its kAdjBandGroups thread groups each sum
+// one range of delays (ascending), and the group sums are added in group order, so the
+// result does not depend on the launch. Lanes of a group read consecutive samples.
+constexpr int kAdjBandOut = 32, kAdjBandGroups = 16;
+
+__global__ __launch_bounds__(kAdjBandOut * kAdjBandGroups) void adj_band_kernel(
+    const float2 *__restrict__ dz, const float2 *__restrict__ s, const float2 *__restrict__ r, int n, int tau0,
+    int n_tau, float2 *__restrict__ grad_r, float2 *__restrict__ grad_s)
 {
-    int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    {
-        const int m = k;
-        float ar = 0.f, ai = 0.f;
-        for (int l = 0; l < n_tau; ++l) {
-            int i = m + tau0 + l;
-            if (i >= n) break;
-            float2 z = dz[(long long)l * n + i];
-            float2 sv = s[i];
-            float sr = sgnf(sv.x), si = sgnf(sv.y);
-            ar += z.x * sr + z.y * si;
-            ai += z.x * si - z.y * sr;
+    __shared__ float4 part[kAdjBandGroups][kAdjBandOut];
+    const int lane = threadIdx.x % kAdjBandOut, grp = threadIdx.x / kAdjBandOut;
+    const int k = blockIdx.x * kAdjBandOut + lane;
+    const int per = (n_tau + kAdjBandGroups - 1) / kAdjBandGroups;
+    const int l0 = min(n_tau, grp * per), l1 = min(n_tau, l0 + per);
+    float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f; // grad_r, grad_s partial sums
+    if (k < n) {
+        for (int l = l0; l < l1; ++l) {
+            const int i = k + tau0 + l; // grad_r: sample i = m + d_l
+            if (i < n) {
+                const float2 z = dz[(long long)l * n + i];
+                const float2 sv = s[i];
+                const float sr = sgnf(sv.x), si = sgnf(sv.y);
+                gr += z.x * sr + z.y * si;
+                gi += z.x * si - z.y * sr;
+            }
+            const int m = k - tau0 - l; // grad_s: reference index m = i - d_l
+            if (grad_s && m >= 0) {
+                const float2 z = dz[(long long)l * n + k];
+                const float2 rv = r[m];
+                const float rr = sgnf(rv.x), ri = sgnf(rv.y);
+                hr += z.x * rr - z.y * ri;
+                hi += z.x * ri + z.y * rr;
+            }
         }
-        grad_r[m] = make_float2(ar, ai);
     }
-    if (grad_s) {
-        const int i = k;
-        float ar = 0.f, ai = 0.f;
-        for (int l = 0; l < n_tau; ++l) {
-            int m = i - tau0 - l;
-            if (m < 0) break;
-            float2 z = dz[(long long)l * n + i];
-            float2 rv = r[m];
-            float rr = sgnf(rv.x), ri = sgnf(rv.y);
-            ar += z.x * rr - z.y * ri;
-            ai += z.x * ri + z.y * rr;
+    part[grp][lane] = make_float4(gr, gi, hr, hi);
+    __syncthreads();
+    if (grp == 0 && k < n) {
+        float4 t = part[0][lane];
+#pragma unroll
+        for (int g = 1; g < kAdjBandGroups; ++g) {
+            const float4 u = part[g][lane];
+            t.x += u.x;
+            t.y += u.y;
+            t.z += u.z;
+            t.w += u.w;
         }
-        grad_s[i] = make_float2(ar, ai);
+        grad_r[k] = make_float2(t.x, t.y);
+        if (grad_s) grad_s[k] = make_float2(t.z, t.w);
     }
 }
 

@@ -1035,7 +1035,7 @@ ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t
     P.n_bases_pad = L.n_bases_pad;
     P.inv_n = 1.0 / (double)n;
     P.dz = dz;
-    dim3 grid((unsigned)(cdiv(n_tau, 64) * cdiv(n, 128)));
+    dim3 grid((unsigned)(cdiv(n_tau, 64) * cdiv(n, 64)));
     {
         ProfScope prof(s);
         if (prec == NDFT_BF16X2)

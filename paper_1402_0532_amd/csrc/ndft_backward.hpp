@@ -56,7 +56,7 @@ struct AdjParams {
     float2 *dz;   // [n_tau][n]
 };
 
-// dz tile: 64 delays x 128 samples per work-group (4 waves of 32 x 64), K = bases.
+// dz tile: 64 delays x 64 samples per work-group (4 waves of 32 x 32), K = bases.
 //   PREC_FP32:   v_mfma_f32_32x32x2_f32, one base per step: k = (E term, O term).
 //   PREC_BF16X2: v_mfma_f32_32x32x16_bf16, lane k order for bases (b, b+1):
 //                [E_hi_b, E_hi_b+1, E_lo_b, E_lo_b+1, O_hi_b, O_hi_b+1, O_lo_b, O_lo_b+1]
@@ -64,37 +64,49 @@ struct AdjParams {
 template <int PREC>
 __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
 {
-    constexpr int LT = 64, IT = 128, KB = 8; // delays, samples, bases per stage
-    __shared__ float4 sA[KB][LT];            // E/O of the stage's bases
-    __shared__ float2 sB[KB][IT];            // (Sc, St) of the stage's bases
+    constexpr int LT = 64, IT = 64, KB = 16, JB = IT / 64; // delays, samples, bases per stage
+    constexpr int AIT = KB * LT / 256;        // E/O loads per thread and stage
+    __shared__ float4 sA[KB][LT];             // E/O of the stage's bases
+    __shared__ float2 sB[KB][IT];             // (Sc, St) of the stage's bases
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
-    const int wl = wave & 1, wi = wave >> 1; // wave tile: 32 delays x 64 samples
+    const int wl = wave & 1, wi = wave >> 1; // wave tile: 32 delays x 32 JB samples
     const int tiles_l = (P.n_tau + LT - 1) / LT;
     const int l0 = (blockIdx.x % tiles_l) * LT;
     const int i0 = (blockIdx.x / tiles_l) * IT;
     const int n = P.n;
 
-    f32x16 acc[2][2]; // [sample block][re, im]
+    f32x16 acc[JB][2]; // [sample block][re, im]
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[j][c][e] = 0.0f;
 
-    for (int kb0 = 0; kb0 < P.n_bases_pad; kb0 += KB) {
-        // stage: E/O rows (64 delays x 8 bases) and sign columns (8 bases x 128 samples)
-        for (int u = tid; u < KB * LT; u += 256) {
-            int k = u / LT, l = u % LT;
-            int lc = min(l0 + l, P.n_tau - 1);
-            float4 v = P.eo[(long long)(kb0 + k) * P.n_tau + lc];
-            sA[k][l] = l0 + l < P.n_tau ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    // E/O rows of a stage (64 delays x 16 bases, zero past the delays and padded bases),
+    // loaded into registers one stage ahead
+    auto load_eo = [&](int kb0, float4 (&v)[AIT]) {
+#pragma unroll
+        for (int t = 0; t < AIT; ++t) {
+            const int u = tid + 256 * t, k = u / LT, l = u % LT;
+            v[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (kb0 + k < P.n_bases_pad && l0 + l < P.n_tau) v[t] = P.eo[(long long)(kb0 + k) * P.n_tau + l0 + l];
         }
+    };
+    float4 pre[AIT];
+    load_eo(0, pre);
+    for (int kb0 = 0; kb0 < P.n_bases_pad; kb0 += KB) {
+#pragma unroll
+        for (int t = 0; t < AIT; ++t) {
+            const int u = tid + 256 * t;
+            sA[u / LT][u % LT] = pre[t];
+        }
+        // sign columns (16 bases x 128 samples); padding bases meet zero E/O rows
         for (int u = tid; u < KB * IT; u += 256) {
             int k = u / IT, c = u % IT;
             int i = min(i0 + c, n - 1);
-            int b = base_of(P.bm, kb0 + k);
+            int b = base_of(P.bm, min(kb0 + k, P.n_bases_pad - 1));
             // m = b i mod n: the product (< 2^48) and the remainder are exact in FP64, the
             // quotient from the rounded reciprocal is off by at most one either way
             const double prod = (double)b * (double)i;
@@ -105,6 +117,7 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
             sB[k][c] = make_float2((float)g.c, (float)g.t);
         }
         __syncthreads();
+        if (kb0 + KB < P.n_bases_pad) load_eo(kb0 + KB, pre); // in flight during the products
         if (PREC == PREC_FP32) {
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
@@ -112,8 +125,8 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
                 float ar = h ? e.z : e.x; // E_r or O_r
                 float ai = h ? e.w : e.y; // E_i or O_i
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    float2 sg = sB[k][wi * 64 + 32 * j + l32];
+                for (int j = 0; j < JB; ++j) {
+                    float2 sg = sB[k][wi * 32 * JB + 32 * j + l32];
                     float bv = h ? sg.y : sg.x; // Sc or St
                     acc[j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bv, acc[j][0], 0, 0, 0);
                     acc[j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bv, acc[j][1], 0, 0, 0);
@@ -132,9 +145,9 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
                 split_pair(e1.w, e2.w, ai.z, ai.w);
                 bf16x8 va = __builtin_bit_cast(bf16x8, ar), vi = __builtin_bit_cast(bf16x8, ai);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    float2 s1 = sB[k + 2 * h][wi * 64 + 32 * j + l32];
-                    float2 s2 = sB[k + 2 * h + 1][wi * 64 + 32 * j + l32];
+                for (int j = 0; j < JB; ++j) {
+                    float2 s1 = sB[k + 2 * h][wi * 32 * JB + 32 * j + l32];
+                    float2 s2 = sB[k + 2 * h + 1][wi * 32 * JB + 32 * j + l32];
                     uint4 bv;
                     bv.x = pack_bf16x2(s1.x, s2.x);
                     bv.y = bv.x;
@@ -150,8 +163,8 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
     }
     // rows = delays 8*(e/4) + 4*h + e%4, column = sample l32
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        int i = i0 + wi * 64 + 32 * j + l32;
+    for (int j = 0; j < JB; ++j) {
+        int i = i0 + wi * 32 * JB + 32 * j + l32;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             int l = l0 + wl * 32 + 8 * (e >> 2) + 4 * h + (e & 3);

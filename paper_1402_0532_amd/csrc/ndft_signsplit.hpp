@@ -112,9 +112,9 @@ constexpr int kLsumBases = 256;   // base rows per block
 __device__ __forceinline__ int wpad(int i) { return i + (i >> 3); }
 
 // Prefix tables: row o holds the 16 delays of the block (float2 each) at a stride of 17
-// float2 plus 1 more after every 16 rows. The 16 writers of a delay store rows 16 apart,
-// which the per-16 shift puts on 16 different bank pairs; the walkers read rows at random,
-// which the odd stride spreads. A walker reads the 8 delays it owns as four 8-byte pairs.
+// float2 plus 1 more after every 16 rows. The 32 writers of a delay pair store rows 8
+// apart, which the odd stride and the per-16 shift spread over the banks; the walkers read
+// rows at random. A walker reads the 8 delays it owns as four 8-byte pairs.
 constexpr int kLsumRowF2 = kLsumDelays + 1;
 __device__ __forceinline__ int prow(int o) { return (int)__umul24((unsigned)o, kLsumRowF2) + (o >> 4); }
 constexpr int kLsumTabF2 = kLsumChunk * kLsumRowF2 + (kLsumChunk >> 4) + kLsumDelays;
@@ -141,12 +141,12 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 }
 
 // Blocks: blockIdx.x = 16 delays, blockIdx.y = range of whole chunks, blockIdx.z = 256
-// base rows (after row 0 when base 0 is present: base 0 is summed apart from the thread
-// totals of z and the sign counts). Lag phase: thread (dp, g) makes z for the delay pair
+// base rows (after row 0 when base 0 is present: base 0 is summed apart, from the block
+// total of z and the sign counts). Lag phase: thread (dp, g) makes z for the delay pair
 // 2 dp, 2 dp + 1 and samples 8 g .. 8 g + 7 of the chunk (the pair shares the s values and
-// all but one r value). Crossing phase: a thread takes 8 of the
-// delays and two base rows i and M - 1 - i of the group's M rows: the rows ascend in b and
-// the crossings per chunk grow with b, so every thread walks about as many as any other.
+// all but one r value). Crossing phase: a thread takes 8 of the delays and two base rows
+// i and M - 1 - i of the group's M rows: the rows ascend in b and the crossings per chunk
+// grow with b, so every thread walks about as many as any other.
 //
 // Per part, with P(k) the prefix sum of z over the block's first k samples,
 //   sum_k S(k) z_k = S_end P(K) + sum_{crossings k_i < K} S_i (P(k_i) + P(k_i + e_i))

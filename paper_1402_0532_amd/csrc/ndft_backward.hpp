@@ -102,19 +102,29 @@ __global__ __launch_bounds__(256, 2) void adj_contract_kernel(AdjParams P)
             const int u = tid + 256 * t;
             sA[u / LT][u % LT] = pre[t];
         }
-        // sign columns (16 bases x 128 samples); padding bases meet zero E/O rows
-        for (int u = tid; u < KB * IT; u += 256) {
-            int k = u / IT, c = u % IT;
-            int i = min(i0 + c, n - 1);
-            int b = base_of(P.bm, min(kb0 + k, P.n_bases_pad - 1));
+        // sign columns (16 bases x 64 samples; a thread takes 4 consecutive samples of one
+        // base); padding bases meet zero E/O rows
+        static_assert(KB * IT == 4 * 256, "four signs per thread");
+        {
+            const int k = tid / (IT / 4), c = (tid % (IT / 4)) * 4;
+            const int b = base_of(P.bm, min(kb0 + k, P.n_bases_pad - 1));
+            const int i = min(i0 + c, n - 1);
             // m = b i mod n: the product (< 2^48) and the remainder are exact in FP64, the
             // quotient from the rounded reciprocal is off by at most one either way
             const double prod = (double)b * (double)i;
             double rem = fma(-floor(prod * P.inv_n), (double)n, prod);
             rem = rem < 0.0 ? rem + (double)n : (rem >= (double)n ? rem - (double)n : rem);
-            const int m = (int)rem;
-            TwSign g = twiddle_sign(m, n);
-            sB[k][c] = make_float2((float)g.c, (float)g.t);
+            int m = (int)rem;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                TwSign g = twiddle_sign(m, n);
+                sB[k][c + e] = make_float2((float)g.c, (float)g.t);
+                // next sample (clamped at the last one like i): m + b mod n
+                if (i0 + c + e + 1 < n) {
+                    m += b;
+                    m = m >= n ? m - n : m;
+                }
+            }
         }
         __syncthreads();
         if (kb0 + KB < P.n_bases_pad) load_eo(kb0 + KB, pre); // in flight during the products

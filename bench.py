@@ -31,7 +31,7 @@ KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_contract.hpp",
                   "paper_1402_0532_amd/csrc/ndft_surface_bf16.hpp",
                   "paper_1402_0532_amd/csrc/ndft_signsplit.hpp"]
 TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
-SPLIT_PLAN_PREFIXES = ("bf16x2s_", "bf16x2g_")
+SPLIT_PLAN_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_")
 
 
 def kernel_source_hash() -> str:

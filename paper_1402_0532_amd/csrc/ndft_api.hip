@@ -202,6 +202,17 @@ Plan make_split_plan(const char *name, double rel_cost)
     return p;
 }
 
+// FP8 form of the sign-split plans: the same lsum_kernel, dsum8_kernel with four-term e4m3
+// twiddle planes against exact e4m3 lag signs.
+template <int NW, int WB, int KS>
+Plan make_split8_plan(const char *name, double rel_cost)
+{
+    Plan p = make_split_plan<NW, WB, KS, false>(name, rel_cost);
+    p.kfn[0] = reinterpret_cast<const void *>(&dsum8_kernel<NW, WB, KS>);
+    p.planes_kfn = reinterpret_cast<const void *>(&dplane8_build_kernel<DsumCfg<NW, WB, KS>::BT, KS>);
+    return p;
+}
+
 const std::vector<Plan> &plans(int prec)
 {
     // name: bases x delays per work-group, waves, samples per stage
@@ -214,6 +225,7 @@ const std::vector<Plan> &plans(int prec)
     static const std::vector<Plan> fp8 = {
         make_plan<PREC_FP8, 2, 4, 2, 1, 16>("fp8_b128_l128_w8_ks16"),
         make_plan<PREC_FP8, 3, 4, 1, 1, 16>("fp8_b96_l128_w12_ks16"),
+        make_split8_plan<8, 2, 128>("fp8s_b64_l256_w8_ks128", 0.85),
     };
     static const std::vector<Plan> bf16 = {
         make_plan<PREC_BF16X2, 2, 4, 2, 1, 8>("bf16x2_b128_l128_w8_ks8"),

@@ -751,4 +751,252 @@ __global__ __launch_bounds__(64 * NW, 1) void dsum_kernel(ContractParams P, cons
         }
 }
 
+// ------------------------------------------------------------------------------------
+// FP8 form of the D part (dsum8_kernel)
+// ------------------------------------------------------------------------------------
+// v_mfma_scale_f32_32x32x64_f8f6f4 with e4m3 operands: lane half h of a 32-sample K group
+// holds 32 bytes per row, [term 2mm of samples 16h .. 16h+15, term 2mm+1 of the same
+// samples], scaled by 2^(-4 (2mm)) and 2^(-4 (2mm+1)) (the E8M0 scale of the lane in half
+// 0 applies to bytes 0-15 of every lane, that of half 1 to bytes 16-31). The twiddle W / 2
+// is carried as four e4m3 terms (each rounds the remaining residual, scaled by 16^j), the
+// lag signs as exact e4m3 +-2 / 0 (the code fields moved to bits 7:6 of a byte), so two
+// instructions (mm = 0, 1) cover 32 samples. Within a dword the samples are in the order
+// (2, 0, 3, 1) of their 4-sample code word, which the sign extraction gives for free.
+
+// e4m3 +-2 / 0 bytes of the real (IM = 0) or imaginary (IM = 1) signs of a code word, in
+// the byte order (k2, k0, k3, k1)
+template <int IM>
+__device__ __forceinline__ uint32_t f8_signs(uint32_t w)
+{
+    constexpr uint32_t M = 0xC000C000u;
+    const uint32_t x = IM ? w << 4 : w;
+    return (x & M) | (((x << 2) & M) >> 8);
+}
+
+// Four e4m3 terms of four values, each term a dword in the byte order (v2, v0, v3, v1):
+// v = t0 + t1 / 16 + t2 / 256 + t3 / 4096 + O(2^-16 |v|).
+__device__ __forceinline__ void f8_terms4(float v0, float v1, float v2, float v3, uint32_t t[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v2, v0, 0, false);
+        const int d = __builtin_amdgcn_cvt_pk_fp8_f32(v3, v1, lo, true);
+        t[j] = (uint32_t)d;
+        if (j < 3) {
+            v2 = (v2 - __builtin_amdgcn_cvt_f32_fp8(d, 0)) * 16.0f;
+            v0 = (v0 - __builtin_amdgcn_cvt_f32_fp8(d, 1)) * 16.0f;
+            v3 = (v3 - __builtin_amdgcn_cvt_f32_fp8(d, 2)) * 16.0f;
+            v1 = (v1 - __builtin_amdgcn_cvt_f32_fp8(d, 3)) * 16.0f;
+        }
+    }
+}
+
+// Twiddle operands of one unit: base row b, samples k0 .. k0 + 15 (m = b k0 mod n), W / 2
+// from the two-level table and the step W^b. o[tt][mm][half] is the uint4 half of the
+// lane's 32 bytes for the real (tt = 0) or imaginary (tt = 1) part.
+__device__ __forceinline__ void dsum8_unit(const float2 *coarse, const float2 *fine, int tb, int m, float2 wb,
+                                           uint4 (&o)[2][2][2])
+{
+    const int mask = (1 << tb) - 1;
+    float wr[16], wi[16];
+    {
+        const float2 a = coarse[m >> tb], c = fine[m & mask];
+        wr[0] = fmaf(a.x, c.x, -a.y * c.y);
+        wi[0] = fmaf(a.x, c.y, a.y * c.x);
+    }
+#pragma unroll
+    for (int j = 1; j < 16; ++j) {
+        wr[j] = fmaf(wr[j - 1], wb.x, -wi[j - 1] * wb.y);
+        wi[j] = fmaf(wr[j - 1], wb.y, wi[j - 1] * wb.x);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const float *v = tt ? wi : wr;
+        uint32_t t[4][4]; // [dword d][term j]
+#pragma unroll
+        for (int d = 0; d < 4; ++d) f8_terms4(v[4 * d], v[4 * d + 1], v[4 * d + 2], v[4 * d + 3], t[d]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[tt][j >> 1][j & 1] = make_uint4(t[0][j], t[1][j], t[2][j], t[3][j]);
+    }
+}
+
+// FP8 twiddle planes: [base tile][stage][32-sample group G][tt][mm][h][row][2] uint4.
+template <int BT, int KS>
+__global__ __launch_bounds__(256) void dplane8_build_kernel(DplaneParams Q)
+{
+    extern __shared__ float2 tables[];
+    constexpr int NG = KS / 32;
+    constexpr int STAGE_A = NG * 16 * BT; // uint4
+    constexpr int UNITS = NG * 2 * BT;    // (G, h, row): 16 samples, both parts, all terms
+    float2 *coarse = tables;
+    float2 *fine = tables + Q.n_coarse;
+    const int n = Q.n;
+    build_twiddle_tables(coarse, fine, n, Q.tb, Q.n_coarse, threadIdx.x, 256, 0.5f); // W / 2
+    __syncthreads();
+    const long long s0 = (long long)blockIdx.x * Q.stages_per_block;
+    const long long s1 = min(s0 + Q.stages_per_block, Q.plane_stages);
+    for (int u = threadIdx.x; u < UNITS; u += 256) {
+        const int row = u % BT, gh = u / BT, h = gh & 1, g = gh >> 1;
+        const int b = base_of(Q.bm, blockIdx.y * BT + row);
+        const float2 wb = twiddle_step(coarse, fine, Q.tb, b);
+        int m = (int)(((long long)b * (s0 * KS + 32 * g + 16 * h)) % n);
+        const int dm = (int)(((long long)b * KS) % n);
+        uint4 *dst = Q.planes + ((long long)blockIdx.y * Q.plane_stages + s0) * STAGE_A;
+        for (long long st = s0; st < s1; ++st) {
+            uint4 o[2][2][2];
+            dsum8_unit(coarse, fine, Q.tb, m, wb, o);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                    for (int hf = 0; hf < 2; ++hf)
+                        dst[(((((g * 2 + tt) * 2 + mm) * 2 + h) * BT) + row) * 2 + hf] = o[tt][mm][hf];
+            dst += STAGE_A;
+            m = add_mod(m, dm, n);
+        }
+    }
+}
+
+// D part in the FP8 form: the structure of dsum_kernel (same blocks, stages of KS samples,
+// twiddle planes copied to LDS by direct loads, code words of the next stage loaded as
+// their slots free), with the K groups of 32 samples above.
+template <int NW, int WB, int KS>
+__global__ __launch_bounds__(64 * NW, 1) void dsum8_kernel(ContractParams P, const uint32_t *codes,
+                                                          long long code_stages)
+{
+    using Cfg = DsumCfg<NW, WB, KS>;
+    constexpr int NT = Cfg::NT, BT = Cfg::BT, LT = Cfg::LT, CW = Cfg::CW;
+    constexpr int NG = KS / 32;
+    constexpr int STAGE_A = NG * 16 * BT;
+    constexpr int PLI = STAGE_A / NT;
+    static_assert(STAGE_A % NT == 0, "plane stages split evenly");
+    __shared__ uint4 bufA0[STAGE_A];
+    __shared__ uint4 bufA1[STAGE_A];
+
+    const int grp = blockIdx.x % P.grp_stride;
+    const int tile_l = blockIdx.x / P.grp_stride;
+    if (grp >= P.tiles_b * P.ksplit) return;
+    const int tile_b = grp / P.ksplit, kc = grp % P.ksplit;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int b0 = tile_b * BT, c0 = tile_l * LT;
+    const int k_begin = kc * P.kchunk;
+    const int k_end = min(P.n, k_begin + P.kchunk);
+    const int npair = k_end > k_begin ? (k_end - k_begin + 2 * KS - 1) / (2 * KS) : 0;
+    const int col = c0 + wave * 32 + l32;
+
+    const uint4 *pl_src = P.planes + ((long long)tile_b * P.plane_stages + k_begin / KS) * STAGE_A + tid;
+    // code words of (stage, col) that lane half h needs: (h' = 0, 1) x (q = 2h, 2h + 1)
+    const uint2 *cd = reinterpret_cast<const uint2 *>(codes);
+    long long cst = k_begin / 32;
+    auto code_load = [&](long long st, uint4 &w) { // w = words for dwords d = 0 .. 3
+        st = min(st, code_stages - 1); // prefetch past the last stage reads a valid, unused one
+        const long long base = (st * P.n_cols_pad + col) * 4 + h; // uint2 index of (h' = 0, q = 2h)
+        const uint2 w0 = cd[base], w1 = cd[base + 2];              // h' = 0, h' = 1
+        w = make_uint4(w0.x, w1.x, w0.y, w1.y);
+    };
+
+    f32x16 acc[WB][4];
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][t][e] = 0.0f;
+
+    auto load_a = [&](const uint4 *buf, int g, int mm, i32x8 (&a)[WB][2]) {
+#pragma unroll
+        for (int i = 0; i < WB; ++i)
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const int idx = ((((g * 2 + tt) * 2 + mm) * 2 + h) * BT + 32 * i + l32) * 2;
+                const uint4 lo = buf[idx], hi = buf[idx + 1];
+                a[i][tt] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+    };
+
+    uint4 cw[CW];
+    auto stage = [&](auto cbc) {
+        constexpr int CB = decltype(cbc)::value;
+        const uint4 *cur = CB ? bufA1 : bufA0;
+        uint4 *nxt = CB ? bufA0 : bufA1;
+        {
+            uint4 *dst = nxt + __builtin_amdgcn_readfirstlane(wave) * 64;
+#pragma unroll
+            for (int k = 0; k < PLI; ++k)
+                __builtin_amdgcn_global_load_lds(pl_src + k * NT,
+                                                 (__attribute__((address_space(3))) void *)(dst + k * NT), 16, 0, 0);
+            pl_src += STAGE_A;
+        }
+        uint4 cn[CW];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            code_load(cst + CW + g, cn[g]);
+            const uint4 w = cw[g];
+            const i32x8 b1 = i32x8{(int)f8_signs<0>(w.x), (int)f8_signs<0>(w.y), (int)f8_signs<0>(w.z),
+                                   (int)f8_signs<0>(w.w), (int)f8_signs<0>(w.x), (int)f8_signs<0>(w.y),
+                                   (int)f8_signs<0>(w.z), (int)f8_signs<0>(w.w)};
+            const i32x8 b2 = i32x8{(int)f8_signs<1>(w.x), (int)f8_signs<1>(w.y), (int)f8_signs<1>(w.z),
+                                   (int)f8_signs<1>(w.w), (int)f8_signs<1>(w.x), (int)f8_signs<1>(w.y),
+                                   (int)f8_signs<1>(w.z), (int)f8_signs<1>(w.w)};
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) {
+                i32x8 a[WB][2];
+                load_a(cur, g, mm, a);
+                const int scale_a = 127 - 4 * (2 * mm + h);
+#pragma unroll
+                for (int i = 0; i < WB; ++i) {
+                    acc[i][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i][0], b1, acc[i][0], 0, 0, 0,
+                                                                              scale_a, 0, 127);
+                    acc[i][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i][0], b2, acc[i][1], 0, 0, 0,
+                                                                              scale_a, 0, 127);
+                    acc[i][2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i][1], b1, acc[i][2], 0, 0, 0,
+                                                                              scale_a, 0, 127);
+                    acc[i][3] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i][1], b2, acc[i][3], 0, 0, 0,
+                                                                              scale_a, 0, 127);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CW; ++c) cw[c] = cn[c];
+        cst += CW;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); // plane block landed before the barrier
+        __syncthreads();
+    };
+
+    if (npair > 0) {
+        {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(pl_src);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(bufA0) + tid;
+#pragma unroll
+            for (int k = 0; k < PLI; ++k) dst[k * NT] = src[k * NT];
+            pl_src += STAGE_A;
+        }
+#pragma unroll
+        for (int c = 0; c < CW; ++c) code_load(cst + c, cw[c]);
+        __syncthreads();
+        for (int p = 0; p < npair; ++p) {
+            stage(std::integral_constant<int, 0>());
+            stage(std::integral_constant<int, 1>());
+        }
+    }
+
+    float4 *out = P.partial + (long long)kc * P.n_cols_pad * P.n_bases_pad;
+    if (P.row0 && tile_b == 0 && h == 0) out[(long long)col * P.n_bases_pad] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = P.row0 + b0 + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+            float4 v;
+            v.x = acc[i][0][e]; // U
+            v.y = acc[i][3][e]; // V
+            v.z = acc[i][1][e]; // X
+            v.w = acc[i][2][e]; // Y
+            out[(long long)col * P.n_bases_pad + row] = v;
+        }
+}
+
 } // namespace ndft

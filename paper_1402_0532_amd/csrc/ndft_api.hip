@@ -592,7 +592,9 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
         Q.tb = L.tb;
         Q.n_coarse = L.n_coarse;
         Q.tw_exact = L.tw_exact;
-        Q.stages_per_block = 16;
+        // about two work-groups per compute unit (each builds its own twiddle table)
+        Q.stages_per_block =
+            (int)std::max<int64_t>(1, cdiv((int64_t)L.plane_stages * L.tiles_b, 2LL * device_cu_count()));
         Q.bm = L.bm_tile;
         void *qargs[] = {&Q};
         dim3 qgrid((unsigned)cdiv(L.plane_stages, Q.stages_per_block), (unsigned)L.tiles_b);
@@ -627,7 +629,9 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         Q.n = (int)n;
         Q.tb = L.tb;
         Q.n_coarse = L.n_coarse;
-        Q.stages_per_block = 16;
+        // about two work-groups per compute unit (each builds its own twiddle table)
+        Q.stages_per_block =
+            (int)std::max<int64_t>(1, cdiv((int64_t)L.plane_stages * L.tiles_b, 2LL * device_cu_count()));
         Q.bm = L.bm_tile;
         void *qargs[] = {&Q};
         dim3 qgrid((unsigned)cdiv(L.plane_stages, Q.stages_per_block), (unsigned)L.tiles_b);

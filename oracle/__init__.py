@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package. It shares no code with the
 GPU path (``paper_1402_0532_amd``) and does not import it.
 
-The numerical work lives in ``ndft_oracle.c`` (plain C, FP64, literal Eqs. (1)-(7) and
-(12a)); this module only loads it with ctypes and marshals numpy arrays. Inputs are
+The numerical work lives in ``ndft_oracle.c`` (plain C, FP64, literal Eqs. (1)-(7),
+(12a) and (12c)); this module only loads it with ctypes and marshals numpy arrays. Inputs are
 complex arrays (normally complex64 upcast exactly to complex128).
 """
 from __future__ import annotations
@@ -52,11 +52,14 @@ def _load():
         lib.oracle_exact_sign_of_sum.argtypes = [P, P, ctypes.c_int]
         lib.oracle_exact_sign_of_sum.restype = ctypes.c_int
         lib.oracle_lag_row.argtypes = [P, P, I, I, P, P]
+        lib.oracle_lag_row_lin.argtypes = [P, P, I, I, P, P]
         lib.oracle_twiddle_signs.argtypes = [I, I, I, P]
         lib.oracle_ndft.argtypes = [P, I, I, I, I, P, P]
         lib.oracle_ndft.restype = ctypes.c_int
         lib.oracle_caf.argtypes = [P, P, I, I, I, I, I, P, I, P, P]
         lib.oracle_caf.restype = ctypes.c_int
+        lib.oracle_caf_lin.argtypes = [P, P, I, I, I, I, I, P, I, P, P]
+        lib.oracle_caf_lin.restype = ctypes.c_int
         lib.oracle_caf_grad.argtypes = [P, P, I, I, I, I, I, P, P, P]
         lib.oracle_caf_grad.restype = ctypes.c_int
         lib.oracle_caf_loss.argtypes = [P, P, I, I, I, I, I, P]
@@ -117,6 +120,18 @@ def lag_row(s, r, d: int):
     return z, sg
 
 
+def lag_row_lin(s, r, d: int):
+    """Eq. (12c) lag row: z[i] = s[i] conj(r[i-d]) (ordinary product) and its exact
+    component signs (int8 [n][2])."""
+    s = _c128(s)
+    r = _c128(r)
+    n = s.shape[0]
+    z = np.zeros(n, np.complex128)
+    sg = np.zeros((n, 2), np.int8)
+    _load().oracle_lag_row_lin(_ptr(s), _ptr(r), n, int(d), _ptr(z), _ptr(sg))
+    return z, sg
+
+
 def twiddle_signs(n: int, p0: int, n_dop: int) -> np.ndarray:
     """csgn(W^{(p0+q) i mod N}) as int8 [n_dop][n][2]."""
     out = np.zeros((n_dop, n, 2), np.int8)
@@ -158,6 +173,29 @@ def caf(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
     )
     if rc:
         raise ValueError("oracle_caf: invalid arguments")
+    return A, sc
+
+
+def caf12c(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
+    """Eq. (12c) surface (linear lag product, then the Eq. (6) operator with the
+    twiddle). Returns (A [rows][n_dop], scale [rows][n_dop])."""
+    s = _c128(s)
+    r = _c128(r)
+    n = s.shape[0]
+    if rows is None:
+        rows_arr = None
+        nr = n_tau
+    else:
+        rows_arr = np.ascontiguousarray(rows, dtype=np.int64)
+        nr = rows_arr.shape[0]
+    A = np.zeros((nr, n_dop), np.complex128)
+    sc = np.zeros((nr, n_dop), np.float64)
+    rc = _load().oracle_caf_lin(
+        _ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop),
+        None if rows_arr is None else _ptr(rows_arr), nr, _ptr(A), _ptr(sc),
+    )
+    if rc:
+        raise ValueError("oracle_caf_lin: invalid arguments")
     return A, sc
 
 

@@ -9,6 +9,7 @@ Every step is the paper's definition written out with Python scalars:
 * ``cop``  -- Eq. (6): a_r(x)b_r - a_i(x)b_i + j(a_i(x)b_r + b_i(x)a_r).
 * ``ndft`` -- Eq. (7): X[k] = sum_n W^{kn mod N} (x) x[n], W = e^{-j2pi/N}, no 1/N.
 * ``caf``  -- Eq. (12a) read as ((s[i] (x) conj(r[i-d])) (x) W^{ip}), r[m<0] = 0.
+* ``caf12c`` -- Eq. (12c): (s[i] conj(r[i-d])) (x) W^{ip}, the lag product ordinary.
 
 Lag products are evaluated in exact rational arithmetic (``fractions.Fraction``) so
 their signs are exact; twiddles are FP64 except at quadrant multiples, where they are
@@ -85,6 +86,33 @@ def caf(s: list, r: list, tau0: int, n_tau: int, p0: int, n_dop: int) -> list:
     for l in range(n_tau):
         d = tau0 + l
         z = [lag_product(s[i], r[i - d] if i - d >= 0 else 0j) for i in range(n)]
+        row = []
+        for q in range(n_dop):
+            p = (p0 + q) % n
+            re = im = 0.0
+            for i in range(n):
+                a, b = cop(z[i], twiddle(i * p, n))
+                re += float(a)
+                im += float(b)
+            row.append(complex(re, im))
+        rows.append(row)
+    return rows
+
+
+def linear_lag_product(s: complex, r: complex) -> tuple:
+    """s conj(r), the ordinary product of Eq. (11), in exact rational arithmetic."""
+    ar, ai = Fraction(float(s.real)), Fraction(float(s.imag))
+    br, bi = Fraction(float(r.real)), -Fraction(float(r.imag))
+    return (ar * br - ai * bi, ai * br + ar * bi)
+
+
+def caf12c(s: list, r: list, tau0: int, n_tau: int, p0: int, n_dop: int) -> list:
+    """Eq. (12c): the ordinary lag product, then Eq. (6) with W^{ip}; r[m < 0] = 0."""
+    n = len(s)
+    rows = []
+    for l in range(n_tau):
+        d = tau0 + l
+        z = [linear_lag_product(s[i], r[i - d] if i - d >= 0 else 0j) for i in range(n)]
         row = []
         for q in range(n_dop):
             p = (p0 + q) % n

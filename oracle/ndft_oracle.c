@@ -20,6 +20,8 @@
  *              the lag product of the surveillance sample and the conjugated reference
  *              sample (the conjugate is the one written in Eq. (11)), then one NDFT per
  *              range bin. Reference samples before the start of the record are zero.
+ *   CAF (12c)  Eq. (12c): the ordinary lag product s[i] conj(r[i-d]) (Eq. (11)), then
+ *              the operator of Eq. (6) with W^{ip}; signs of the lag product exact.
  *
  * Readings of the paper taken here (each also listed in the design notes):
  *   - sign(0) = 0 and -0.0 counts as zero (Eq. (2) "otherwise").
@@ -185,10 +187,45 @@ static void lag_product(double sr, double si, double rr, double ri, xreal *zr, x
     }
 }
 
+/* ------------------------------------------------------------------------------ */
+/* Linear lag product z = s conj(r) (the ordinary product of Eq. (11), used by the */
+/* Eq. (12c) surface), with the exact sign of each component: each real product is */
+/* split exactly into value + error (fma), and the sign of their sum is exact.     */
+/* ------------------------------------------------------------------------------ */
+static void two_product(double a, double b, double *p, double *e)
+{
+    *p = a * b;
+    *e = fma(a, b, -*p);
+}
+
+static void linear_lag_product(double sr, double si, double rr, double ri, xreal *zr, xreal *zi)
+{
+    double br = rr, bi = -ri; /* conj(r) */
+    double p[4], e[4];
+    /* z_r = s_r b_r - s_i b_i */
+    two_product(sr, br, &p[0], &e[0]);
+    two_product(si, bi, &p[1], &e[1]);
+    zr->v = p[0] - p[1];
+    {   /* exact_sign_of_sum weighs |v[k]| by c[k]: the signs of the terms go into c */
+        double v[4] = {p[0], e[0], p[1], e[1]};
+        int c[4] = {sgn(p[0]), sgn(e[0]), -sgn(p[1]), -sgn(e[1])};
+        zr->s = exact_sign_of_sum(v, c, 4);
+    }
+    /* z_i = s_i b_r + s_r b_i */
+    two_product(si, br, &p[2], &e[2]);
+    two_product(sr, bi, &p[3], &e[3]);
+    zi->v = p[2] + p[3];
+    {
+        double v[4] = {p[2], e[2], p[3], e[3]};
+        int c[4] = {sgn(p[2]), sgn(e[2]), sgn(p[3]), sgn(e[3])};
+        zi->s = exact_sign_of_sum(v, c, 4);
+    }
+}
+
 /* One lag-product row: z[i] = s[i] (x) conj(r[i-d]), i in [0, n); r[m<0] = 0.
  * z is interleaved complex FP64 [n][2]; zsign (optional) is int8 [n][2]. */
-void oracle_lag_row(const double *s, const double *r, int64_t n, int64_t d, double *z,
-                    int8_t *zsign)
+static void lag_row_impl(const double *s, const double *r, int64_t n, int64_t d, double *z, int8_t *zsign,
+                         int linear)
 {
     for (int64_t i = 0; i < n; ++i) {
         double rr = 0.0, ri = 0.0;
@@ -197,7 +234,10 @@ void oracle_lag_row(const double *s, const double *r, int64_t n, int64_t d, doub
             ri = r[2 * (i - d) + 1];
         }
         xreal zr, zi;
-        lag_product(s[2 * i], s[2 * i + 1], rr, ri, &zr, &zi);
+        if (linear)
+            linear_lag_product(s[2 * i], s[2 * i + 1], rr, ri, &zr, &zi);
+        else
+            lag_product(s[2 * i], s[2 * i + 1], rr, ri, &zr, &zi);
         z[2 * i] = zr.v;
         z[2 * i + 1] = zi.v;
         if (zsign) {
@@ -205,6 +245,19 @@ void oracle_lag_row(const double *s, const double *r, int64_t n, int64_t d, doub
             zsign[2 * i + 1] = (int8_t)zi.s;
         }
     }
+}
+
+void oracle_lag_row(const double *s, const double *r, int64_t n, int64_t d, double *z,
+                    int8_t *zsign)
+{
+    lag_row_impl(s, r, n, d, z, zsign, 0);
+}
+
+/* The linear lag-product row of Eq. (12c): z[i] = s[i] conj(r[i-d]). */
+void oracle_lag_row_lin(const double *s, const double *r, int64_t n, int64_t d, double *z,
+                        int8_t *zsign)
+{
+    lag_row_impl(s, r, n, d, z, zsign, 1);
 }
 
 /* Signs of the twiddle operand, csgn(W^{(p0+q) i mod N}) as int8 [n_dop][n][2]. */
@@ -261,9 +314,9 @@ int oracle_ndft(const double *x, int64_t batch, int64_t n, int64_t k0, int64_t k
 /*   d = tau0 + rows[l] (or tau0 + l when rows == NULL), p = p0 + q mod N.          */
 /* Output A[n_rows][n_dop] interleaved complex; scale[n_rows][n_dop] (optional).    */
 /* ------------------------------------------------------------------------------ */
-int oracle_caf(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
-               int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
-               double *scale)
+static int caf_impl(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
+                    int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
+                    double *scale, int linear)
 {
     if (n < 1 || tau0 < 0 || n_tau < 0 || tau0 + n_tau > n || n_dop < 0) return 1;
     if (!rows) n_rows = n_tau;
@@ -275,7 +328,7 @@ int oracle_caf(const double *s, const double *r, int64_t n, int64_t tau0, int64_
         for (int64_t li = 0; li < n_rows; ++li) {
             int64_t l = rows ? rows[li] : li;
             int64_t d = tau0 + l;
-            oracle_lag_row(s, r, n, d, zrow, zsg);
+            lag_row_impl(s, r, n, d, zrow, zsg, linear);
             for (int64_t q = 0; q < n_dop; ++q) {
                 int64_t p = mod_n(p0 + q, n);
                 double re = 0.0, im = 0.0, sc = 0.0;
@@ -302,6 +355,23 @@ int oracle_caf(const double *s, const double *r, int64_t n, int64_t tau0, int64_
         free(zsg);
     }
     return 0;
+}
+
+/* Eq. (12a): A[l][q] = sum_i cop(cop(s[i], conj(r[i-l])), W^{i p}) (see above). */
+int oracle_caf(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
+               int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
+               double *scale)
+{
+    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 0);
+}
+
+/* Eq. (12c): the linear lag product s[i] conj(r[i-l]), then the operator of Eq. (6)
+ * with the twiddle: A[l][q] = sum_i cop(s[i] conj(r[i-l]), W^{i p}); scale as above. */
+int oracle_caf_lin(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
+                   int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
+                   double *scale)
+{
+    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 1);
 }
 
 /* ------------------------------------------------------------------------------ */

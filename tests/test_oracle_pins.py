@@ -346,3 +346,86 @@ def test_oracle_grad_s_matches_fd_by_symmetry(orc):
             fd = (Lp - Lm) / (2 * h)
             ana = gs[m].real if part == 0 else gs[m].imag
             assert ana == pytest.approx(fd, rel=1e-5, abs=1e-6)
+
+
+# ---------------------------------------------------------------------------------
+# P-10: the Eq. (12c) surface (ordinary lag product, then the Eq. (6) operator).
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 16])
+@pytest.mark.parametrize("kind", ["gauss", "int_zeros"])
+def test_brute_force_caf12c(orc, n, kind):
+    if kind == "gauss":
+        s, r = synth.random_pair(n, seed=n + 300, zeros=0.0)
+    else:
+        s, r = synth.random_pair(n, seed=350 + n, zeros=0.2, integer=True)
+    A, sc = orc.caf12c(s, r, 0, n, 0, n)
+    B = np.array(brute.caf12c(list(s), list(r), 0, n, 0, n))
+    scale = np.maximum(sc, 1e-300)
+    err = (np.abs(A.real - B.real) + np.abs(A.imag - B.imag)) / scale
+    assert np.all(err <= 1e-12)
+    assert np.all((sc > 0) | (A == 0))
+
+
+def test_caf12c_zero_delay_zero_bin_closed_form(orc):
+    # s = r: every lag product at delay 0 is |s_i|^2 (imaginary part exactly 0), and
+    # W^0 = 1, so each term is |s_i|^2 (x) 1 = |s_i|^2 + 1 for s_i != 0 and 0 otherwise.
+    s, _ = synth.random_pair(200, seed=31, zeros=0.1)
+    A, _ = orc.caf12c(s, s, 0, 1, 0, 1)
+    s64 = s.astype(np.complex128)
+    nz = s64 != 0
+    want = np.sum(np.abs(s64[nz]) ** 2 + 1.0)
+    assert A[0, 0].imag == 0.0
+    assert A[0, 0].real == pytest.approx(want, rel=1e-13)
+
+
+def test_caf12c_row_is_ndft_of_linear_lag_products(orc):
+    # Each row of Eq. (12c) is Eq. (7) applied to the ordinary lag-product sequence,
+    # formed here with numpy (integer data: products and sums exact in FP64).
+    n = 64
+    s, r = synth.random_pair(n, seed=41, zeros=0.15, integer=True)
+    s64, r64 = s.astype(np.complex128), r.astype(np.complex128)
+    A, _ = orc.caf12c(s, r, 2, 6, -9, 20)
+    for l in range(6):
+        d = 2 + l
+        rs = np.concatenate([np.zeros(d), r64[:n - d]])
+        z = s64 * np.conj(rs)
+        X, _ = orc.ndft(z[None], k0=-9 % n, k_count=20)
+        np.testing.assert_allclose(A[l], X[0], rtol=0, atol=1e-12)
+
+
+def test_caf12c_invariants(orc):
+    s, r = synth.random_pair(48, seed=6)
+    s64 = s.astype(np.complex128)
+    A, _ = orc.caf12c(s, r, 0, 6, -8, 16)
+    An, _ = orc.caf12c(-s64, r, 0, 6, -8, 16)
+    Aj, _ = orc.caf12c(1j * s64, r, 0, 6, -8, 16)
+    A0, _ = orc.caf12c(np.zeros(48, np.complex64), r, 0, 6, -8, 16)
+    np.testing.assert_array_equal(An, -A)
+    np.testing.assert_allclose(Aj, 1j * A, rtol=0, atol=1e-12)
+    assert np.all(A0 == 0)
+    A2, _ = orc.caf12c(s, r, 0, 6, 40, 16)
+    np.testing.assert_array_equal(A, A2)
+    # the last delay keeps one lag product, s[N-1] conj(r[0]): every bin is that term
+    Al, _ = orc.caf12c(s, r, 47, 1, 0, 4)
+    Xl, _ = orc.ndft(np.concatenate([np.zeros(47), [s64[47] * np.conj(complex(r[0]))]])[None], 0, 4)
+    np.testing.assert_allclose(Al[0], Xl[0], rtol=0, atol=1e-12)
+
+
+def test_brute_force_linear_lag_signs_near_cancellation(orc):
+    # Ordinary lag products whose parts cancel exactly or nearly: the oracle's signs
+    # equal the exact rational signs (FP64 inputs, products not exact in FP64).
+    cases = [
+        (1.0 + 2.0 ** -30, 1.0, 1.0, 1.0 + 2.0 ** -30),
+        (3.0, 2.0 ** -40, 1.0 / 3.0, 2.0 ** -40),
+        (0.1, 0.3, 0.3, 0.1),
+        (1e-160, 1e-160, 1e-160, 1e-160),
+        (1.0 + 2.0 ** -52, 1.0 - 2.0 ** -53, 1.0 - 2.0 ** -53, 1.0 + 2.0 ** -52),
+    ]
+    for sr, si, rr, ri in cases:
+        for sg in [(1, 1, 1, 1), (1, -1, 1, 1), (-1, 1, 1, -1), (1, 1, -1, -1)]:
+            s = complex(sg[0] * sr, sg[1] * si)
+            r = complex(sg[2] * rr, sg[3] * ri)
+            _, z = orc.lag_row_lin(np.array([s]), np.array([r]), 0)
+            zb = brute.linear_lag_product(s, r)
+            assert z[0, 0] == (zb[0] > 0) - (zb[0] < 0), (s, r)
+            assert z[0, 1] == (zb[1] > 0) - (zb[1] < 0), (s, r)

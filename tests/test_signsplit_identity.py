@@ -63,15 +63,19 @@ def runs(b, k0, k1, n):
     return out
 
 
+@pytest.mark.parametrize("form", ["12a", "12c"])
 @pytest.mark.parametrize("shape", [(1002, 3, 4, 0, 1002, True), (999, 0, 3, -50, 101, False),
                                    (4096, 5, 3, -256, 512, False), (1200, 0, 3, -96, 192, True)])
-def test_sign_split_halves_sum_to_surface(shape):
+def test_sign_split_halves_sum_to_surface(shape, form):
+    """Both surfaces: Eq. (12a) (lag product by Eq. (6)) and Eq. (12c) (ordinary lag
+    product); the split only needs the lag values and their exact signs."""
     n, tau0, n_tau, p0, n_dop, integer = shape
     s, r = synth.random_pair(n, seed=n + 11, zeros=0.1, integer=integer)
-    A, sc = oracle.caf(s, r, tau0, n_tau, p0, n_dop)
+    surface, row = (oracle.caf, oracle.lag_row) if form == "12a" else (oracle.caf12c, oracle.lag_row_lin)
+    A, sc = surface(s, r, tau0, n_tau, p0, n_dop)
     chunk = 256
     for t in range(n_tau):
-        z, zs = oracle.lag_row(s, r, tau0 + t)
+        z, zs = row(s, r, tau0 + t)
         csz = zs[:, 0] + 1j * zs[:, 1]
         for q in range(0, n_dop, max(1, n_dop // 12)):  # a spread of bins, both signs
             p = (p0 + q) % n

@@ -145,6 +145,49 @@ def bench_adjoint(nd, synth, torch, args):
     return res
 
 
+def bench_caf12c(nd, synth, torch, args):
+    """The Eq. (12c) surface (ordinary lag product, then the Eq. (6) operator) on the same
+    N=65536 workload, through the sign-split kernels."""
+    import numpy as np
+
+    c = synth.config3()
+    a = (c["tau0"], c["n_tau"], c["p0"], c["n_dop"])
+    s = torch.from_numpy(c["s"]).cuda()
+    r = torch.from_numpy(c["r"]).cuda()
+    cells = c["n_tau"] * c["n_dop"]
+    res = {"workload": "caf12c_n65536_tau1024_dop512"}
+    rows = np.array([0, 37, 511, 1023])
+    ref = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ref = oracle.caf12c(c["s"], c["r"], *a, rows=rows)
+    for form in ("bf16x2", "fp8"):
+        prec = nd.PRECISIONS[form]
+        ws = torch.empty(nd.caf12c_workspace_bytes(c["n"], *a, prec), dtype=torch.uint8, device="cuda")
+        out = torch.empty((c["n_tau"], c["n_dop"]), dtype=torch.complex64, device="cuda")
+        for _ in range(args.warmup):
+            nd.caf12c(s, r, *a, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        reps = max(5, args.steps)
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            nd.caf12c(s, r, *a, prec, out=out, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[form] = {"ms_per_surface": ms, "cells_per_s": cells / (ms * 1e-3)}
+        if ref is not None:
+            g = out.cpu().numpy()[rows].astype(np.complex128)
+            Ao, sc = ref
+            err = (np.abs(g.real - Ao.real) + np.abs(g.imag - Ao.imag)) / np.where(sc > 0, sc, 1)
+            res[form]["max_l1_rel_err_vs_oracle"] = float(err.max())
+            res[form]["err_rows_checked"] = int(len(rows))
+        del ws
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +346,7 @@ def main():
     if not args.no_extras:
         extras["batched"] = bench_batched(nd, tune, synth, torch, args)
         extras["adjoint"] = bench_adjoint(nd, synth, torch, args)
+        extras["caf12c"] = bench_caf12c(nd, synth, torch, args)
 
     main_res = results[args.form]
     line = {

@@ -95,6 +95,24 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
+ * The Eq. (12c) surface of Section 4: the ordinary lag product of Eq. (11), then the
+ * operator of Eq. (6) with the twiddle,
+ *   A[l][q] = sum_{i=0}^{N-1} ( s[i] conj(r[i - d]) ) (x) W^{i p mod N},
+ * with d, p, the zero reference before the record, the layout and the limits of
+ * ndft_caf. The lag product's component signs are exact (FP64 from the complex64
+ * inputs); its value enters in FP32.
+ * Only the sign-split forms compute it: prec NDFT_BF16X2 or NDFT_FP8 (their plans are
+ * the only candidates, for any Doppler window); NDFT_FP32 returns NDFT_E_UNSUPPORTED
+ * and ndft_caf12c_workspace then returns 0. ndft_set_plan overrides apply when they
+ * name a sign-split plan. Errors, workspace and stream as for ndft_caf.
+ * ------------------------------------------------------------------------------- */
+size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
+                             ndft_prec prec);
+ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                        int64_t n_tau, int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
  * Batched surfaces: many CPIs of uneven length in one persistent launch.
  * CPI c computes the ndft_caf surface of
  *   surv_pool[surv_off .. surv_off + n), ref_pool[ref_off .. ref_off + n)

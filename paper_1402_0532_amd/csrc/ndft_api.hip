@@ -109,6 +109,7 @@ struct Plan {
     const void *planes_kfn;  // twiddle plane builder (nullptr: twiddles made in the kernel)
     bool raw_inputs;         // reads complex64 inputs itself (no sign-prep launches)
     const void *lag_kfn;     // sign-split plans: the lag / twiddle-sign kernel (lsum_kernel)
+    const void *lag_kfn_lin; // the same for the Eq. (12c) surface (ordinary lag product)
     int stage_a;             // plane uint4 per stage (plane plans)
 };
 
@@ -134,6 +135,7 @@ Plan make_plan(const char *name)
     p.planes_kfn = nullptr;
     p.raw_inputs = false;
     p.lag_kfn = nullptr;
+    p.lag_kfn_lin = nullptr;
     p.stage_a = 0;
     return p;
 }
@@ -165,6 +167,7 @@ Plan make_surface_plan(const char *name)
     p.planes_kfn = PLANES ? reinterpret_cast<const void *>(&plane_build_kernel<Cfg::BT, KS>) : nullptr;
     p.raw_inputs = true;
     p.lag_kfn = nullptr;
+    p.lag_kfn_lin = nullptr;
     p.stage_a = Cfg::STAGE_A;
     return p;
 }
@@ -197,7 +200,8 @@ Plan make_split_plan(const char *name, double rel_cost)
     p.sign_scale = 0.5f;
     p.planes_kfn = GEN ? nullptr : reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
     p.raw_inputs = true;
-    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel);
+    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel<false>);
+    p.lag_kfn_lin = reinterpret_cast<const void *>(&lsum_kernel<true>);
     p.stage_a = Cfg::STAGE_A;
     return p;
 }
@@ -302,6 +306,7 @@ struct Launch {
     size_t plane_bytes;
     size_t plane_off;       // offset of the planes in the workspace
     int grp_stride;
+    int lin;           // sign-split: the Eq. (12c) lag product (lag_kfn_lin)
 };
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -408,12 +413,15 @@ int64_t lsum_groups(const Launch &L)
     return std::max<int64_t>(1, cdiv(L.n_bases - has0, kLsumBases));
 }
 
+// lin: the Eq. (12c) surface, which only the sign-split plans compute; L.plan is nullptr
+// when the precision has none.
 Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
-                   int64_t signed_elems)
+                   int64_t signed_elems, bool lin = false)
 {
     Launch L;
     std::memset(&L, 0, sizeof(L));
     L.prec = prec;
+    L.lin = lin ? 1 : 0;
     L.bm = make_base_map(n, p0, n_bins, &L.n_bases);
     int pi, ko;
     {
@@ -422,16 +430,18 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         ko = g_ksplit_override[prec];
     }
     const std::vector<Plan> &ps = plans(prec);
-    if (pi < 0 || pi >= (int)ps.size() || !ps[pi].kfn[prod]) {
+    auto usable = [&](int k) { return lin ? ps[k].lag_kfn_lin != nullptr : ps[k].kfn[prod] != nullptr; };
+    if (pi < 0 || pi >= (int)ps.size() || !usable(pi)) {
         // built-in choice: padded matrix-core work times the plan's operand-generation
         // overhead, then the earlier plan
         double best = -1.0;
-        pi = 0;
+        pi = lin ? -1 : 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
-            if (!ps[k].kfn[prod]) continue;
+            if (!usable(k)) continue;
             // sign-split: the twiddle-sign part walks ~4 b C / N sign runs per base b and
-            // chunk of C samples; taken only while that stays about one per chunk
-            if (ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
+            // chunk of C samples; taken only while that stays about one per chunk (the
+            // Eq. (12c) surface has no other form: the walk is exact for any base)
+            if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
             const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
             double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
@@ -442,6 +452,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
             }
         }
     }
+    if (pi < 0) return L; // L.plan stays nullptr
     L.plan = &ps[pi];
     L.row0 = zero_row(*L.plan, prod, L.bm, L.n_bases);
     L.bm_tile = L.row0 ? drop_first_base(L.bm) : L.bm;
@@ -656,7 +667,8 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         T.part = partial + (size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad;
         void *targs[] = {&T};
         dim3 tgrid((unsigned)cdiv(n_cols, kLsumDelays), (unsigned)L.ksT, (unsigned)lsum_groups(L));
-        if (hipLaunchKernel(L.plan->lag_kfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
+        const void *tfn = L.lin ? L.plan->lag_kfn_lin : L.plan->lag_kfn;
+        if (hipLaunchKernel(tfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
     }
     ndft_status st = check_launch();
     if (st != NDFT_OK || L.tiles_b == 0) return st;
@@ -994,6 +1006,32 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
         st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes,
                              reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref));
     }
+    if (st != NDFT_OK) return st;
+    return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+}
+
+size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
+{
+    if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
+    Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 0, true);
+    return L.plan ? L.ws_bytes : 0;
+}
+
+ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
+                        int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
+    if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
+    if (!prec_ok(prec)) return NDFT_E_INVAL;
+    Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 0, true);
+    if (!L.plan) return NDFT_E_UNSUPPORTED;
+    ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
+    if (st != NDFT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float4 *part = reinterpret_cast<float4 *>(ws);
+    st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
+                      tau0, part, ws, s);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }

@@ -14,6 +14,11 @@
 // combined form, and no lag arithmetic in the matrix loop. Base 0 (twiddle 1) is done
 // entirely in lsum_kernel: its D part is the plain sum of the signs.
 //
+// The split needs only the lag values and their exact signs, so the Eq. (12c) surface
+// (the ordinary lag product s conj(r), then the Eq. (6) operator with the twiddle) runs on
+// the same kernels: lsum_kernel<true> forms that product instead (FP64 from the FP32
+// inputs, where both products are exact and one rounding of their sum keeps the sign).
+//
 // Both kernels write float4 (U, V, X, Y) partial planes of the same layout, so one
 // reduction adds them: A[+b] = (U - V, X + Y), A[-b] = (U + V, X - Y) with
 //   U = sum Re(c) Re(v), V = sum Im(c) Im(v), X = sum Re(c) Im(v), Y = sum Im(c) Re(v)
@@ -39,6 +44,21 @@ namespace ndft {
 __device__ __forceinline__ uint32_t sign_field(float s)
 {
     return s == 0.0f ? 0u : (s < 0.0f ? 3u : 1u);
+}
+
+__device__ __forceinline__ uint32_t sign_field(double s)
+{
+    return s == 0.0 ? 0u : (s < 0.0 ? 3u : 1u);
+}
+
+// The ordinary lag product s conj(r) of Eq. (11) from complex64 samples, in FP64: each
+// product of two FP32 values is exact there, so the single rounding of the fused sum gives
+// each component with its exact sign (and 0 only for an exact 0).
+__device__ __forceinline__ void linear_lag64(float4 s, float4 r, double &zr, double &zi)
+{
+    const double sx = s.x, sy = s.y, rx = r.x, ry = r.y;
+    zr = fma(sx, rx, sy * ry);
+    zi = fma(sy, rx, -(sx * ry));
 }
 
 // ------------------------------------------------------------------------------------
@@ -155,6 +175,9 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 // chunk's tables hold P at its C + 1 sample edges, the earlier chunks' sum included:
 // P(k) + P(k) = 2 P(k) and R(k) = P(k) + P(k + 1), so a crossing costs one row read
 // either way, and the end term comes once per block.
+//
+// LIN: the lag product of the Eq. (12c) surface (linear_lag64) instead of Eq. (6).
+template <bool LIN>
 __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 {
     constexpr int DT = kLsumDelays, C = kLsumChunk;
@@ -266,15 +289,23 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const float4 cc = h == 0 ? cn : cp;
-                    vr[h][e] = fmaf(a.x, cc.z, cc.x * a.z) + fmaf(a.y, cc.w, cc.y * a.w);
-                    vi[h][e] = fmaf(a.y, cc.z, cc.x * a.w) - fmaf(cc.y, a.z, a.x * cc.w);
+                    if constexpr (LIN) {
+                        double zr64, zi64;
+                        linear_lag64(a, cc, zr64, zi64);
+                        vr[h][e] = (float)zr64;
+                        vi[h][e] = (float)zi64;
+                    } else {
+                        vr[h][e] = fmaf(a.x, cc.z, cc.x * a.z) + fmaf(a.y, cc.w, cc.y * a.w);
+                        vi[h][e] = fmaf(a.y, cc.z, cc.x * a.w) - fmaf(cc.y, a.z, a.x * cc.w);
+                    }
                     mz = fminf(mz, fminf(fabsf(vr[h][e]), fabsf(vi[h][e])));
                 }
                 cp = cn;
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                // a normal FP32 value carries the exact sign (see lag_product4): the sign
+                // a normal FP32 value carries the exact sign (see lag_product4, and
+                // linear_lag64 rounded once more, which keeps a sign): the sign
                 // bits go to the sign positions of the code word, every non-zero bit is set
                 code[h][w] = (sign_pair(vr[h][1], vr[h][0]) & 0x80008000u) |
                              ((sign_pair(vr[h][3], vr[h][2]) >> 2) & 0x20002000u) |
@@ -291,18 +322,28 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             __builtin_amdgcn_sched_barrier(0);
         }
         // zero or subnormal components (zero padding, integer or cancelling inputs): the
-        // exact signs of lag_product4 for this thread's samples
+        // exact signs of lag_product4 (linear_lag64) for this thread's samples
         if (__builtin_amdgcn_ballot_w64(!(mz >= 1.17549435e-38f))) {
             if (!(mz >= 1.17549435e-38f)) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
 #pragma unroll 1
                     for (int j = 0; j < SPT; ++j) { // rolled: the FP64 test is long and rare
-                        const Lag e = lag_product4(sw[wpad(o0 + j)], rw[wpad(rb + j + 1 - h)]);
+                        uint32_t fr, fi;
+                        if constexpr (LIN) {
+                            double zr64, zi64;
+                            linear_lag64(sw[wpad(o0 + j)], rw[wpad(rb + j + 1 - h)], zr64, zi64);
+                            fr = sign_field(zr64);
+                            fi = sign_field(zi64);
+                        } else {
+                            const Lag e = lag_product4(sw[wpad(o0 + j)], rw[wpad(rb + j + 1 - h)]);
+                            fr = sign_field(e.sr);
+                            fi = sign_field(e.si);
+                        }
                         const int q = j & 3;
                         const int pos_r = (q & 1) ? 30 - 2 * (q >> 1) : 14 - 2 * (q >> 1); // k0:14 k1:30 k2:12 k3:28
                         const uint32_t keep = ~((3u << pos_r) | (3u << (pos_r - 4)));
-                        const uint32_t f = (sign_field(e.sr) << pos_r) | (sign_field(e.si) << (pos_r - 4));
+                        const uint32_t f = (fr << pos_r) | (fi << (pos_r - 4));
                         const bool w1 = j >= 4;
                         const uint32_t cw = ((w1 ? code[h][1] : code[h][0]) & keep) | f;
                         code[h][0] = w1 ? code[h][0] : cw;

@@ -118,3 +118,33 @@ def test_plan_table():
         assert lib.ndft_set_plan(prec, 0, 3) == 0
         assert lib.ndft_set_plan(prec, -1, 0) == 0
     assert lib.ndft_plan_count(5) == 0
+
+
+@pytest.mark.parametrize(
+    "n,tau0,n_tau,p0,n_dop",
+    [(0, 0, 1, 0, 1), (8, -1, 1, 0, 1), (8, 0, 0, 0, 1), (8, 4, 5, 0, 1), (8, 0, 1, 0, 0),
+     (8, 0, 1, 0, 9), ((1 << 24) + 1, 0, 1, 0, 1)],
+)
+def test_caf12c_rejects_bad_shapes(n, tau0, n_tau, p0, n_dop):
+    lib = _lib.load()
+    keep, p = _host_buf()
+    assert lib.ndft_caf12c(p, p, n, tau0, n_tau, p0, n_dop, p, 1, p, 4096, None) == INVAL
+    assert lib.ndft_caf12c_workspace(n, tau0, n_tau, p0, n_dop, 1) == 0
+
+
+def test_caf12c_precisions_and_workspace():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    odd = ctypes.c_void_p(p.value + 4)
+    assert lib.ndft_caf12c(None, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == INVAL
+    assert lib.ndft_caf12c(odd, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == INVAL
+    assert lib.ndft_caf12c(p, p, 16, 0, 4, 0, 4, p, 7, p, 4096, None) == INVAL
+    # only the sign-split forms compute Eq. (12c): FP32 has none
+    assert lib.ndft_caf12c(p, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == UNSUPPORTED
+    assert lib.ndft_caf12c_workspace(16, 0, 4, 0, 4, 0) == 0
+    for prec in (1, 2):
+        need = lib.ndft_caf12c_workspace(65536, 0, 1024, -256, 512, prec)
+        assert need > 0
+        assert lib.ndft_caf12c(p, p, 65536, 0, 1024, -256, 512, p, prec, None, 0, None) == WORKSPACE
+        # every Doppler window, also one whose bases reach N / 2
+        assert lib.ndft_caf12c_workspace(1002, 0, 8, 0, 1002, prec) > 0

@@ -1,0 +1,165 @@
+"""GPU parity of the Eq. (12c) surface (ndft_caf12c) against the FP64 oracle.
+
+Eq. (12c): the ordinary lag product s[i] conj(r[i - d]) (Eq. (11)), then the Eq. (6)
+operator with the twiddle W^{ip}. Only the sign-split forms compute it, so every
+sign-split plan of both precisions is forced here (ndft_set_plan) over shapes that reach
+their code paths, plus the built-in choice at the N = 65536 surface on sampled rows.
+Data include lag products whose real part is a tiny exact value (+-2^-46) that FP32
+arithmetic would round to 0: the exact lag sign then decides a whole twiddle term.
+Tolerance and metric as in test_gpu_parity (l1-relative per output, exact zeros exact).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 1e-4, 2: 1e-4}
+SPLIT_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_")
+
+
+@pytest.fixture(scope="module")
+def nd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1402_0532_amd as m
+
+    yield m
+    for p in (1, 2):
+        m.set_plan(p, -1, 0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def rel_err(got, ref, scale):
+    got = np.asarray(got, np.complex128)
+    err = np.abs(got.real - ref.real) + np.abs(got.imag - ref.imag)
+    zero = scale == 0
+    assert not np.any(zero & (err != 0)), "non-zero output where the exact result is 0"
+    return float(np.max(np.where(zero, 0.0, err / np.where(zero, 1.0, scale)), initial=0.0))
+
+
+def near_cancel_pair(n, seed):
+    """About 40% of the pairs (s, r) = +-(a, 1), +-(a, -fl(a^2)) with a = 1 + 2^-23: their
+    lag products have real part +-(a^2 - fl(a^2)) = +-2^-46 exactly (FP32 products give
+    0); the rest small integers with zeros (exact zero lag products)."""
+    rng = np.random.default_rng(seed)
+    s = (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(np.complex64)
+    r = (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(np.complex64)
+    a = np.float32(1.0 + 2.0 ** -23)
+    a2 = np.float32(a * a)
+    ms = rng.uniform(size=n) < 0.4
+    mr = rng.uniform(size=n) < 0.4
+    s[ms] = (np.complex64(a + 1j) * rng.choice([1, -1], ms.sum())).astype(np.complex64)
+    r[mr] = (np.complex64(complex(a, -a2)) * rng.choice([1, -1], mr.sum())).astype(np.complex64)
+    return s, r
+
+
+# n, tau0, n_tau, p0, n_dop, ksplit, data
+SHAPES = [
+    (4096, 3, 300, -200, 400, 0, "gauss"),      # power of two, ragged tiles
+    (999, 0, 130, -50, 101, 3, "gauss"),        # odd length, three chunks
+    (1002, 7, 64, 0, 1002, 0, "int_zeros"),     # N = 2 mod 4, every bin (bases up to N / 2)
+    (65540, 0, 3, -2, 5, 2, "gauss"),           # quadrant points off the table grid
+    (1200, 0, 40, -96, 192, 5, "near_cancel"),  # tiny exact lag values, zeros
+    (17, 0, 17, 0, 17, 0, "int_zeros"),         # shorter than one stage
+    (2048, 0, 50, 10, 90, 0, "gauss"),          # no base 0 in the window
+    (8192, 2, 70, -33, 66, 3, "near_cancel"),   # sign runs crossing chunk edges
+]
+
+_ORACLE = {}
+
+
+def case(orc, shape):
+    if shape not in _ORACLE:
+        n, tau0, n_tau, p0, n_dop, _, kind = shape
+        if kind == "gauss":
+            s, r = synth.random_pair(n, seed=n + 5, zeros=0.02)
+        elif kind == "int_zeros":
+            s, r = synth.random_pair(n, seed=n + 6, zeros=0.2, integer=True)
+        else:
+            s, r = near_cancel_pair(n, n)
+        Ao, sc = orc.caf12c(s, r, tau0, n_tau, p0, n_dop)
+        _ORACLE[shape] = (s, r, Ao, sc)
+    return _ORACLE[shape]
+
+
+def split_plans():
+    import paper_1402_0532_amd as m
+
+    try:
+        return [(p, k) for p in (1, 2) for k in range(m.plan_count(p))
+                if m.plan_name(p, k).startswith(SPLIT_PREFIXES)]
+    except Exception:  # no library: the module fixture skips
+        return [(1, 0)]
+
+
+@pytest.mark.parametrize("prec,plan", split_plans())
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"n{s[0]}_{s[6]}" for s in SHAPES])
+def test_caf12c_plan_vs_oracle(nd, orc, prec, plan, shape):
+    n, tau0, n_tau, p0, n_dop, ks, kind = shape
+    s, r, Ao, sc = case(orc, shape)
+    nd.set_plan(prec, plan, ks)
+    log("caf12c plan", nd.plan_name(prec, plan), "shape", shape)
+    try:
+        A = nd.caf12c(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=prec).cpu().numpy()
+    finally:
+        nd.set_plan(prec, -1, 0)
+    assert rel_err(A, Ao, sc) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("shape", SHAPES[:5], ids=[f"n{s[0]}_{s[6]}" for s in SHAPES[:5]])
+def test_caf12c_builtin_choice(nd, orc, prec, shape):
+    n, tau0, n_tau, p0, n_dop, _, kind = shape
+    s, r, Ao, sc = case(orc, shape)
+    log("caf12c built-in", prec, shape)
+    A = nd.caf12c(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=prec).cpu().numpy()
+    assert rel_err(A, Ao, sc) <= TOL[prec]
+
+
+def test_caf12c_needs_a_split_precision(nd):
+    s, r = synth.random_pair(256, seed=3)
+    with pytest.raises(RuntimeError, match="UNSUPPORTED"):
+        nd.caf12c(dev(s), dev(r), 0, 8, -4, 8, prec=0)
+    assert nd._lib.load().ndft_caf12c_workspace(256, 0, 8, -4, 8, 0) == 0
+
+
+def test_caf12c_differs_from_caf12a(nd, orc):
+    # the two surfaces share the kernels after the lag product: a mix-up of the lag
+    # kernel would pass neither oracle
+    s, r = synth.random_pair(2048, seed=12, zeros=0.02)
+    A12c = nd.caf12c(dev(s), dev(r), 0, 40, -32, 64, prec=1).cpu().numpy()
+    A12a = nd.caf(dev(s), dev(r), 0, 40, -32, 64, prec=1).cpu().numpy()
+    Ao, sc = orc.caf12c(s, r, 0, 40, -32, 64)
+    assert rel_err(A12c, Ao, sc) <= TOL[1]
+    assert rel_err(A12a, Ao, sc) > 1e-2
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_caf12c_n65536_sampled_rows(nd, orc, prec):
+    c = synth.config3()
+    rng = np.random.default_rng(34)
+    rows = np.unique(np.concatenate([[0, 5, 37, 1023], rng.integers(0, c["n_tau"], 4)]))
+    log("caf12c N = 65536 prec", prec, "rows", rows.tolist())
+    A = nd.caf12c(dev(c["s"]), dev(c["r"]), c["tau0"], c["n_tau"], c["p0"], c["n_dop"], prec=prec)
+    A = A.cpu().numpy()
+    Ao, sc = orc.caf12c(c["s"], c["r"], c["tau0"], c["n_tau"], c["p0"], c["n_dop"], rows=rows)
+    e = rel_err(A[rows], Ao, sc)
+    log("caf12c N = 65536 sampled max l1-relative error", prec, e)
+    assert e <= TOL[prec]
+
+
+def test_caf12c_deterministic(nd):
+    s, r = synth.random_pair(4096, seed=9)
+    a = nd.caf12c(dev(s), dev(r), 0, 200, -300, 600, prec=1)
+    b = nd.caf12c(dev(s), dev(r), 0, 200, -300, 600, prec=1)
+    assert torch.equal(a, b)

@@ -5,7 +5,7 @@ CPU-baseline leg of ``bench.py`` may import this package. It shares no code with
 GPU path (``paper_1402_0532_amd``) and does not import it.
 
 The numerical work lives in ``ndft_oracle.c`` (plain C, FP64, literal Eqs. (1)-(7),
-(12a) and (12c)); this module only loads it with ctypes and marshals numpy arrays. Inputs are
+(12a), (12b) and (12c)); this module only loads it with ctypes and marshals numpy arrays. Inputs are
 complex arrays (normally complex64 upcast exactly to complex128).
 """
 from __future__ import annotations
@@ -60,6 +60,8 @@ def _load():
         lib.oracle_caf.restype = ctypes.c_int
         lib.oracle_caf_lin.argtypes = [P, P, I, I, I, I, I, P, I, P, P]
         lib.oracle_caf_lin.restype = ctypes.c_int
+        lib.oracle_caf_dft.argtypes = [P, P, I, I, I, I, I, P, I, P, P]
+        lib.oracle_caf_dft.restype = ctypes.c_int
         lib.oracle_caf_grad.argtypes = [P, P, I, I, I, I, I, P, P, P]
         lib.oracle_caf_grad.restype = ctypes.c_int
         lib.oracle_caf_loss.argtypes = [P, P, I, I, I, I, I, P]
@@ -174,6 +176,31 @@ def caf(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
     if rc:
         raise ValueError("oracle_caf: invalid arguments")
     return A, sc
+
+
+def _surface(fn, s, r, tau0, n_tau, p0, n_dop, rows):
+    s = _c128(s)
+    r = _c128(r)
+    n = s.shape[0]
+    if rows is None:
+        rows_arr = None
+        nr = n_tau
+    else:
+        rows_arr = np.ascontiguousarray(rows, dtype=np.int64)
+        nr = rows_arr.shape[0]
+    A = np.zeros((nr, n_dop), np.complex128)
+    sc = np.zeros((nr, n_dop), np.float64)
+    rc = fn(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop),
+            None if rows_arr is None else _ptr(rows_arr), nr, _ptr(A), _ptr(sc))
+    if rc:
+        raise ValueError("oracle surface: invalid arguments")
+    return A, sc
+
+
+def caf12b(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
+    """Eq. (12b) surface (lag product of Eq. (6), then the ordinary DFT). Returns
+    (A [rows][n_dop], scale [rows][n_dop]), scale the l1 mass of the real products."""
+    return _surface(_load().oracle_caf_dft, s, r, tau0, n_tau, p0, n_dop, rows)
 
 
 def caf12c(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):

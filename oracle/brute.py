@@ -9,6 +9,7 @@ Every step is the paper's definition written out with Python scalars:
 * ``cop``  -- Eq. (6): a_r(x)b_r - a_i(x)b_i + j(a_i(x)b_r + b_i(x)a_r).
 * ``ndft`` -- Eq. (7): X[k] = sum_n W^{kn mod N} (x) x[n], W = e^{-j2pi/N}, no 1/N.
 * ``caf``  -- Eq. (12a) read as ((s[i] (x) conj(r[i-d])) (x) W^{ip}), r[m<0] = 0.
+* ``caf12b`` -- Eq. (12b): (s[i] (x) conj(r[i-d])) W^{ip}, the DFT ordinary.
 * ``caf12c`` -- Eq. (12c): (s[i] conj(r[i-d])) (x) W^{ip}, the lag product ordinary.
 
 Lag products are evaluated in exact rational arithmetic (``fractions.Fraction``) so
@@ -122,5 +123,24 @@ def caf12c(s: list, r: list, tau0: int, n_tau: int, p0: int, n_dop: int) -> list
                 re += float(a)
                 im += float(b)
             row.append(complex(re, im))
+        rows.append(row)
+    return rows
+
+
+def caf12b(s: list, r: list, tau0: int, n_tau: int, p0: int, n_dop: int) -> list:
+    """Eq. (12b): the Eq. (6) lag product (exact), then the ordinary DFT with W^{ip}."""
+    n = len(s)
+    rows = []
+    for l in range(n_tau):
+        d = tau0 + l
+        z = [lag_product(s[i], r[i - d] if i - d >= 0 else 0j) for i in range(n)]
+        row = []
+        for q in range(n_dop):
+            p = (p0 + q) % n
+            acc = 0j
+            for i in range(n):
+                wr, wi = twiddle(i * p, n)
+                acc += complex(float(z[i][0]), float(z[i][1])) * complex(wr, wi)
+            row.append(acc)
         rows.append(row)
     return rows

@@ -20,6 +20,8 @@
  *              the lag product of the surveillance sample and the conjugated reference
  *              sample (the conjugate is the one written in Eq. (11)), then one NDFT per
  *              range bin. Reference samples before the start of the record are zero.
+ *   CAF (12b)  Eq. (12b): the lag product of Eq. (6), then the ordinary DFT (complex
+ *              products with W^{ip}).
  *   CAF (12c)  Eq. (12c): the ordinary lag product s[i] conj(r[i-d]) (Eq. (11)), then
  *              the operator of Eq. (6) with W^{ip}; signs of the lag product exact.
  *
@@ -316,7 +318,7 @@ int oracle_ndft(const double *x, int64_t batch, int64_t n, int64_t k0, int64_t k
 /* ------------------------------------------------------------------------------ */
 static int caf_impl(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
                     int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
-                    double *scale, int linear)
+                    double *scale, int linear, int linear_outer)
 {
     if (n < 1 || tau0 < 0 || n_tau < 0 || tau0 + n_tau > n || n_dop < 0) return 1;
     if (!rows) n_rows = n_tau;
@@ -329,6 +331,25 @@ static int caf_impl(const double *s, const double *r, int64_t n, int64_t tau0, i
             int64_t l = rows ? rows[li] : li;
             int64_t d = tau0 + l;
             lag_row_impl(s, r, n, d, zrow, zsg, linear);
+            if (linear_outer) { /* Eq. (12b): the ordinary DFT of the lag-product row */
+                for (int64_t q = 0; q < n_dop; ++q) {
+                    int64_t p = mod_n(p0 + q, n);
+                    double re = 0.0, im = 0.0, sc = 0.0;
+                    for (int64_t i = 0; i < n; ++i) {
+                        double w[2];
+                        oracle_twiddle(mod_n(i * p, n), n, w);
+                        const double a = zrow[2 * i] * w[0], b = zrow[2 * i + 1] * w[1];
+                        const double c = zrow[2 * i + 1] * w[0], e = zrow[2 * i] * w[1];
+                        re += a - b;
+                        im += c + e;
+                        sc += fabs(a) + fabs(b) + fabs(c) + fabs(e);
+                    }
+                    A[2 * (li * n_dop + q)] = re;
+                    A[2 * (li * n_dop + q) + 1] = im;
+                    if (scale) scale[li * n_dop + q] = sc;
+                }
+                continue;
+            }
             for (int64_t q = 0; q < n_dop; ++q) {
                 int64_t p = mod_n(p0 + q, n);
                 double re = 0.0, im = 0.0, sc = 0.0;
@@ -362,7 +383,7 @@ int oracle_caf(const double *s, const double *r, int64_t n, int64_t tau0, int64_
                int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
                double *scale)
 {
-    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 0);
+    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 0, 0);
 }
 
 /* Eq. (12c): the linear lag product s[i] conj(r[i-l]), then the operator of Eq. (6)
@@ -371,7 +392,17 @@ int oracle_caf_lin(const double *s, const double *r, int64_t n, int64_t tau0, in
                    int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
                    double *scale)
 {
-    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 1);
+    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 1, 0);
+}
+
+/* Eq. (12b): the lag product of Eq. (6), s[i] (x) conj(r[i-l]), then the ordinary DFT:
+ * A[l][q] = sum_i z_i W^{i p} (complex products), scale = sum_i of the four |real
+ * products| of z_i W^{i p}. */
+int oracle_caf_dft(const double *s, const double *r, int64_t n, int64_t tau0, int64_t n_tau,
+                   int64_t p0, int64_t n_dop, const int64_t *rows, int64_t n_rows, double *A,
+                   double *scale)
+{
+    return caf_impl(s, r, n, tau0, n_tau, p0, n_dop, rows, n_rows, A, scale, 0, 1);
 }
 
 /* ------------------------------------------------------------------------------ */

@@ -429,3 +429,58 @@ def test_brute_force_linear_lag_signs_near_cancellation(orc):
             zb = brute.linear_lag_product(s, r)
             assert z[0, 0] == (zb[0] > 0) - (zb[0] < 0), (s, r)
             assert z[0, 1] == (zb[1] > 0) - (zb[1] < 0), (s, r)
+
+
+# ---------------------------------------------------------------------------------
+# P-11: the Eq. (12b) surface (Eq. (6) lag product, then the ordinary DFT).
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 16])
+@pytest.mark.parametrize("kind", ["gauss", "int_zeros"])
+def test_brute_force_caf12b(orc, n, kind):
+    if kind == "gauss":
+        s, r = synth.random_pair(n, seed=n + 500, zeros=0.0)
+    else:
+        s, r = synth.random_pair(n, seed=550 + n, zeros=0.2, integer=True)
+    A, sc = orc.caf12b(s, r, 0, n, 0, n)
+    B = np.array(brute.caf12b(list(s), list(r), 0, n, 0, n))
+    scale = np.maximum(sc, 1e-300)
+    err = (np.abs(A.real - B.real) + np.abs(A.imag - B.imag)) / scale
+    assert np.all(err <= 1e-12)
+    assert np.all((sc > 0) | (A == 0))
+
+
+@pytest.mark.parametrize("n,tau0,n_tau,p0,n_dop", [(96, 2, 5, -40, 80), (1000, 0, 3, 7, 11),
+                                                   (257, 10, 4, -128, 257)])
+def test_caf12b_rows_are_library_fft_of_lag_rows(orc, n, tau0, n_tau, p0, n_dop):
+    # Each row of Eq. (12b) is the ordinary DFT of the Eq. (6) lag-product row (pinned by
+    # the brute-force tests above), i.e. numpy's FFT at the requested bins.
+    s, r = synth.random_pair(n, seed=n + 7, zeros=0.05)
+    A, sc = orc.caf12b(s, r, tau0, n_tau, p0, n_dop)
+    bins = (p0 + np.arange(n_dop)) % n
+    for l in range(n_tau):
+        z, _ = orc.lag_row(s, r, tau0 + l)
+        F = np.fft.fft(z)[bins]
+        assert np.max(np.abs(F - A[l]) / np.maximum(sc[l], 1e-300)) <= 1e-12
+        # the scale is the l1 mass of the four real products of each term
+        W = np.exp(-2j * np.pi * np.outer(bins, np.arange(n)) / n)
+        want = (np.abs(z.real * W.real) + np.abs(z.imag * W.imag) + np.abs(z.imag * W.real)
+                + np.abs(z.real * W.imag)).sum(axis=1)
+        np.testing.assert_allclose(sc[l], want, rtol=1e-12)
+
+
+def test_caf12b_invariants(orc):
+    s, r = synth.random_pair(64, seed=8)
+    s64 = s.astype(np.complex128)
+    A, _ = orc.caf12b(s, r, 0, 6, -8, 16)
+    An, _ = orc.caf12b(-s64, r, 0, 6, -8, 16)
+    A0, _ = orc.caf12b(np.zeros(64, np.complex64), r, 0, 6, -8, 16)
+    np.testing.assert_array_equal(An, -A)
+    assert np.all(A0 == 0)
+    A2, _ = orc.caf12b(s, r, 0, 6, 56, 16)
+    np.testing.assert_array_equal(A, A2)
+    # the l1 identity of Eq. (5) at delay 0, bin 0 with s = r: z_i = 2(|s_r| + |s_i|),
+    # real, so A[0][0] = 2 ||s||_1 (components) with a zero imaginary part
+    Ad, _ = orc.caf12b(s, s, 0, 1, 0, 1)
+    assert Ad[0, 0].imag == 0.0
+    want = 2.0 * np.sum(np.abs(s64.real) + np.abs(s64.imag))
+    assert Ad[0, 0].real == pytest.approx(want, rel=1e-13)

@@ -95,6 +95,23 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
+ * The Eq. (12b) surface of Section 4: the lag product of Eq. (6), then the ordinary DFT,
+ *   A[l][q] = sum_{i=0}^{N-1} ( s[i] (x) conj(r[i - d]) ) W^{i p mod N},
+ * with d, p, the zero reference before the record, the layout and the limits of
+ * ndft_caf. The outer transform is linear and is computed as a decimated DFT (length-L
+ * FFTs, L the largest power of two dividing n up to 512, then n / L terms per requested
+ * bin), in FP32: prec must be NDFT_FP32 (NDFT_BF16X2 / NDFT_FP8 return
+ * NDFT_E_UNSUPPORTED). ndft_caf12b_workspace returns the bytes of partial surfaces
+ * (0 when none are needed, and for invalid arguments); ws may be NULL when it is 0.
+ * Errors and stream as for ndft_caf.
+ * ------------------------------------------------------------------------------- */
+size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
+                             ndft_prec prec);
+ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                        int64_t n_tau, int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
  * The Eq. (12c) surface of Section 4: the ordinary lag product of Eq. (11), then the
  * operator of Eq. (6) with the twiddle,
  *   A[l][q] = sum_{i=0}^{N-1} ( s[i] conj(r[i - d]) ) (x) W^{i p mod N},

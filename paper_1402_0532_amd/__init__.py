@@ -19,7 +19,7 @@ FP8 = 2
 PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
 
 __all__ = [
-    "FP32", "BF16X2", "FP8", "forward", "caf", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
+    "FP32", "BF16X2", "FP8", "forward", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
     "pack_batch",
     "NDFTCaf", "dbg_signs", "plan_count", "plan_name", "set_plan", "get_plan",
     "prof_enable", "prof_read", "version",
@@ -98,6 +98,32 @@ def caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop:
                       p, _ptr(ws), nbytes, _stream_handle())
     _lib.check(st, "ndft_caf")
     return out
+
+
+def caf12b(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
+           prec=FP32, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. (12b) surface A[n_tau, n_dop] (lag product of Eq. (6), then the ordinary DFT);
+    FP32 only."""
+    lib = _lib.load()
+    _check_c64(s, "surv", 1)
+    _check_c64(r, "ref", 1)
+    n = s.shape[0]
+    if r.shape[0] != n:
+        raise ValueError("surv and ref must have the same length")
+    p = _prec(prec)
+    if out is None:
+        out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device)
+    nbytes = lib.ndft_caf12b_workspace(n, tau0, n_tau, p0, n_dop, p)
+    if nbytes and (ws is None or ws.numel() < nbytes):
+        ws = _workspace(nbytes, s.device)
+    st = lib.ndft_caf12b(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
+                         p, _ptr(ws) if nbytes else None, nbytes, _stream_handle())
+    _lib.check(st, "ndft_caf12b")
+    return out
+
+
+def caf12b_workspace_bytes(n: int, tau0: int, n_tau: int, p0: int, n_dop: int, prec=FP32) -> int:
+    return int(_lib.load().ndft_caf12b_workspace(n, tau0, n_tau, p0, n_dop, _prec(prec)))
 
 
 def caf12c(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,

@@ -18,6 +18,7 @@
 #include "ndft_backward.hpp"
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
+#include "ndft_dft12b.hpp"
 #include "ndft_signsplit.hpp"
 #include "ndft_surface_bf16.hpp"
 
@@ -748,6 +749,45 @@ ndft_status ws_ok(void *ws, size_t ws_bytes, size_t need)
     return NDFT_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// the Eq. (12b) surface: decimated DFT of the lag-product rows
+// ------------------------------------------------------------------------------------
+struct Dft12bLaunch {
+    int lb, M, MB, n_mg, tb, n_coarse;
+    size_t dyn_bytes; // the twiddle table (dynamic LDS)
+    size_t ws_bytes;  // partial surfaces when a delay takes more than one work-group
+};
+
+Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop)
+{
+    Dft12bLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    while (L.lb < kDftMaxLog && n % (2LL << L.lb) == 0) ++L.lb; // L = 2^lb, the largest power of two dividing n
+    L.M = (int)(n >> L.lb);
+    L.MB = std::min(kDftTile >> L.lb, L.M);
+    L.n_mg = (int)cdiv(L.M, L.MB);
+    int exact = 0;
+    choose_table(n, 65536, &L.tb, &L.n_coarse, &exact);
+    L.dyn_bytes = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
+    L.ws_bytes = L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0;
+    return L;
+}
+
+const void *dft12b_fn(int lb)
+{
+    static const void *fns[kDftMaxLog + 1] = {
+        reinterpret_cast<const void *>(&dft12b_kernel<0>), reinterpret_cast<const void *>(&dft12b_kernel<1>),
+        reinterpret_cast<const void *>(&dft12b_kernel<2>), reinterpret_cast<const void *>(&dft12b_kernel<3>),
+        reinterpret_cast<const void *>(&dft12b_kernel<4>), reinterpret_cast<const void *>(&dft12b_kernel<5>),
+        reinterpret_cast<const void *>(&dft12b_kernel<6>), reinterpret_cast<const void *>(&dft12b_kernel<7>),
+        reinterpret_cast<const void *>(&dft12b_kernel<8>), reinterpret_cast<const void *>(&dft12b_kernel<9>)};
+    static_assert(kDftMaxLog == 9, "one instance per transform length");
+    return fns[lb];
+}
+
+std::once_flag g_dft_attr_once;
+hipError_t g_dft_attr_err = hipSuccess;
+
 struct AdjLaunch {
     BaseMap bm;
     int n_bases, n_bases_pad;
@@ -1034,6 +1074,60 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
                       tau0, part, ws, s);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+}
+
+size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
+{
+    if (prec != NDFT_FP32 || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
+    return plan_dft12b(n, n_tau, n_dop).ws_bytes;
+}
+
+ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
+                        int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
+    if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
+    if (!prec_ok(prec)) return NDFT_E_INVAL;
+    if (prec != NDFT_FP32) return NDFT_E_UNSUPPORTED;
+    const Dft12bLaunch L = plan_dft12b(n, n_tau, n_dop);
+    ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
+    if (st != NDFT_OK) return st;
+    std::call_once(g_dft_attr_once, [] {
+        for (int lb = 0; lb <= kDftMaxLog; ++lb) {
+            hipError_t e = hipFuncSetAttribute(dft12b_fn(lb), hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
+        }
+    });
+    if (g_dft_attr_err != hipSuccess) return NDFT_E_HIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Dft12bParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.s = reinterpret_cast<const float2 *>(surv);
+    P.r = reinterpret_cast<const float2 *>(ref);
+    P.n = (int)n;
+    P.tau0 = (int)tau0;
+    P.n_tau = (int)n_tau;
+    P.p0n = (int)mod_n(p0, n);
+    P.n_dop = (int)n_dop;
+    P.M = L.M;
+    P.MB = L.MB;
+    P.n_mg = L.n_mg;
+    P.tb = L.tb;
+    P.n_coarse = L.n_coarse;
+    P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : reinterpret_cast<float2 *>(A);
+    void *args[] = {&P};
+    const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(n_tau, 65535));
+    ProfScope prof(s);
+    hipError_t e = hipLaunchKernel(dft12b_fn(L.lb), grid, dim3(kDftThreads), args, L.dyn_bytes, s);
+    prof.stop();
+    if (e != hipSuccess) return NDFT_E_HIP;
+    if (L.n_mg > 1) {
+        const long long cells = (long long)n_tau * n_dop;
+        hipLaunchKernelGGL(dft12b_reduce_kernel, dim3((unsigned)cdiv(cells, 256)), dim3(256), 0, s,
+                           static_cast<const float2 *>(ws), L.n_mg, cells, reinterpret_cast<float2 *>(A));
+    }
+    return check_launch();
 }
 
 ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,

@@ -1,0 +1,218 @@
+// The Eq. (12b) surface: the lag product of Eq. (6), then the ordinary DFT,
+//   A[l][q] = sum_i z_l[i] W^{i p},  z_l[i] = s[i] (x) conj(r[i - d]),  p = p0 + q mod N.
+// The outer transform is linear, so it needs no matrix-core contraction: each range row is
+// a DFT restricted to the requested bins, computed by decimation in time. With N = M L
+// (L the largest power of two dividing N, at most 512) and i = m + M t,
+//   A[l][p] = sum_{m < M} W^{m p} Y_m[p mod L],   Y_m[k] = sum_{t < L} z[m + M t] W_L^{t k},
+// so one range row costs M length-L FFTs plus M terms per requested bin, instead of N
+// terms per bin. A work-group takes one delay and MB consecutive phases m (MB L = 8192
+// samples, 64 KB of LDS): it forms their lag products (consecutive lanes read consecutive
+// samples), runs the MB FFTs in LDS with radix-8/4/2 Stockham passes (each lane holds its
+// butterflies' inputs in registers between the two barriers of a pass), and adds its
+// phases' share of every requested bin. Shares of the work-groups of a delay are partial
+// surfaces, added in a fixed order by dft12b_reduce_kernel (deterministic).
+//
+// FP32 throughout; twiddles come from the two-level table (exact 0 / +-1 at quadrant
+// points, a few ulp elsewhere), the FFT's inner twiddles as powers of one table entry.
+#pragma once
+
+#include "ndft_device.hpp"
+
+namespace ndft {
+
+constexpr int kDftTile = 8192;    // complex samples per work-group
+constexpr int kDftThreads = 256;
+constexpr int kDftMaxLog = 9;     // L <= 512
+
+struct Dft12bParams {
+    const float2 *s, *r;  // complex64 inputs, n samples each
+    int n, tau0, n_tau;
+    int p0n, n_dop;       // first bin (reduced mod n) and bin count
+    int M, MB, n_mg;      // phases, phases per work-group, work-groups per delay
+    int tb, n_coarse;     // two-level twiddle table of W^v, v in [0, n)
+    float2 *out;          // n_mg == 1: the surface [n_tau][n_dop]; else partials [n_mg][n_tau][n_dop]
+};
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ float2 caddf(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csubf(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a times -j
+__device__ __forceinline__ float2 cmulnj(float2 a) { return make_float2(a.y, -a.x); }
+
+__device__ __forceinline__ float2 table_twiddle(const float2 *coarse, const float2 *fine, int v, int tb)
+{
+    return cmulf(coarse[v >> tb], fine[v & ((1 << tb) - 1)]);
+}
+
+// In-register forward DFTs of size 2, 4, 8: U_s = sum_r u_r e^{-2 pi j r s / R}.
+__device__ __forceinline__ void dft2(float2 &a, float2 &b)
+{
+    const float2 t = a;
+    a = caddf(t, b);
+    b = csubf(t, b);
+}
+
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3)
+{
+    const float2 t0 = caddf(a0, a2), t1 = csubf(a0, a2);
+    const float2 t2 = caddf(a1, a3), t3 = cmulnj(csubf(a1, a3));
+    a0 = caddf(t0, t2);
+    a2 = csubf(t0, t2);
+    a1 = caddf(t1, t3);
+    a3 = csubf(t1, t3);
+}
+
+template <int R>
+__device__ __forceinline__ void small_dft(float2 (&u)[R])
+{
+    if constexpr (R == 2) {
+        dft2(u[0], u[1]);
+    } else if constexpr (R == 4) {
+        dft4(u[0], u[1], u[2], u[3]);
+    } else {
+        static_assert(R == 8, "radix 2, 4 or 8");
+        // even and odd samples, then U_s = E_s + W8^s O_s, U_{s+4} = E_s - W8^s O_s
+        dft4(u[0], u[2], u[4], u[6]);
+        dft4(u[1], u[3], u[5], u[7]);
+        const float c = 0.70710678118654752f;
+        const float2 o1 = make_float2(c * (u[3].x + u[3].y), c * (u[3].y - u[3].x)); // W8 O_1
+        const float2 o2 = cmulnj(u[5]);                                              // W8^2 O_2
+        const float2 o3 = make_float2(c * (u[7].y - u[7].x), -c * (u[7].x + u[7].y)); // W8^3 O_3
+        const float2 e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6], o0 = u[1];
+        u[0] = caddf(e0, o0);
+        u[4] = csubf(e0, o0);
+        u[1] = caddf(e1, o1);
+        u[5] = csubf(e1, o1);
+        u[2] = caddf(e2, o2);
+        u[6] = csubf(e2, o2);
+        u[3] = caddf(e3, o3);
+        u[7] = csubf(e3, o3);
+    }
+}
+
+// One radix-R Stockham pass over mb transforms of length L = 2^LB held in X[b][t]: the
+// butterfly (b, i), i < L / R, with k = i mod p (p the length of the sub-transforms done
+// so far) takes x[b][i + r L / R], turns input r by e^{-2 pi j r k / (R p)}, and writes
+// its R-point DFT to x[b][(i - k) R + k + r p]. All reads happen before the first write.
+template <int R, int LB>
+__device__ __forceinline__ void stockham_pass(float2 *X, int mb, int p, int n, const float2 *coarse,
+                                              const float2 *fine, int tb, int tid)
+{
+    constexpr int L = 1 << LB, Q = L / R;
+    constexpr int CNT = (kDftTile / R + kDftThreads - 1) / kDftThreads;
+    float2 u[CNT][R];
+    int dst[CNT];
+    const int nb = mb * Q;
+    const int vstep = n / (R * p); // W_N^{k n / (R p)} = e^{-2 pi j k / (R p)}
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        const int w = tid + c * kDftThreads;
+        dst[c] = -1;
+        if (w < nb) {
+            const int b = w / Q, i = w % Q;
+            const int k = i & (p - 1);
+            const float2 *src = X + b * L + i;
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[c][r] = src[r * Q];
+            if (p > 1) {
+                const float2 w1 = table_twiddle(coarse, fine, k * vstep, tb);
+                float2 wr = w1;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    u[c][r] = cmulf(u[c][r], wr);
+                    if (r + 1 < R) wr = cmulf(wr, w1);
+                }
+            }
+            small_dft<R>(u[c]);
+            dst[c] = b * L + (i - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CNT; ++c)
+        if (dst[c] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) X[dst[c] + r * p] = u[c][r];
+        }
+    __syncthreads();
+}
+
+// Radix 8 while three or more bits remain, then one radix-4 or radix-2 pass.
+template <int LB, int REM>
+__device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, const float2 *coarse,
+                                           const float2 *fine, int tb, int tid)
+{
+    if constexpr (REM >= 3) {
+        stockham_pass<8, LB>(X, mb, p, n, coarse, fine, tb, tid);
+        fft_passes<LB, REM - 3>(X, mb, p * 8, n, coarse, fine, tb, tid);
+    } else if constexpr (REM == 2) {
+        stockham_pass<4, LB>(X, mb, p, n, coarse, fine, tb, tid);
+    } else if constexpr (REM == 1) {
+        stockham_pass<2, LB>(X, mb, p, n, coarse, fine, tb, tid);
+    }
+}
+
+// Grid: x = phase group (MB phases), y strides over the delays. Dynamic LDS: the table.
+template <int LB>
+__global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
+{
+    constexpr int L = 1 << LB;
+    __shared__ float2 X[kDftTile];
+    extern __shared__ float2 tab[];
+    float2 *coarse = tab, *fine = tab + P.n_coarse;
+    const int tid = threadIdx.x;
+    const int n = P.n, M = P.M, mg = blockIdx.x;
+    const int m0 = mg * P.MB;
+    const int mb = min(P.MB, M - m0);
+    build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, kDftThreads);
+    for (int l = blockIdx.y; l < P.n_tau; l += gridDim.y) {
+        const int d = P.tau0 + l;
+        // lag products of samples m0 + j + M t (j < mb, t < L) into X[j][t]
+        for (int e = tid; e < mb * L; e += kDftThreads) {
+            const int j = e % mb, t = e / mb;
+            const int i = m0 + j + M * t;
+            const float2 sv = P.s[i];
+            const float2 rv = i >= d ? P.r[i - d] : make_float2(0.0f, 0.0f);
+            const Lag z = lag_product(sv, rv);
+            X[j * L + t] = make_float2(z.zr, z.zi);
+        }
+        __syncthreads(); // also orders the table build before its first use
+        fft_passes<LB, LB>(X, mb, 1, n, coarse, fine, P.tb, tid);
+        // this group's phases' share of every requested bin: sum_j W^{(m0 + j) p} Y_j[p mod L]
+        float2 *dst = P.out + ((size_t)mg * P.n_tau + l) * P.n_dop;
+        for (int q = tid; q < P.n_dop; q += kDftThreads) {
+            int p = P.p0n + q;
+            p = p >= n ? p - n : p;
+            const int kk = p & (L - 1);
+            int v = (int)(((unsigned long long)(unsigned)m0 * (unsigned)p) % (unsigned)n);
+            float2 acc = make_float2(0.0f, 0.0f);
+            for (int j = 0; j < mb; ++j) {
+                const float2 w = table_twiddle(coarse, fine, v, P.tb);
+                const float2 y = X[j * L + kk];
+                acc.x = fmaf(w.x, y.x, fmaf(-w.y, y.y, acc.x));
+                acc.y = fmaf(w.x, y.y, fmaf(w.y, y.x, acc.y));
+                v += p;
+                v = v >= n ? v - n : v;
+            }
+            dst[q] = acc;
+        }
+        __syncthreads(); // X is refilled for the next delay
+    }
+}
+
+// A[e] = sum over the phase groups g = 0 .. n_mg - 1 of part[g][e], in that order.
+__global__ __launch_bounds__(256) void dft12b_reduce_kernel(const float2 *part, int n_mg, long long cells,
+                                                            float2 *A)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= cells) return;
+    float2 acc = part[e];
+    for (int g = 1; g < n_mg; ++g) acc = caddf(acc, part[(long long)g * cells + e]);
+    A[e] = acc;
+}
+
+} // namespace ndft

@@ -148,3 +148,20 @@ def test_caf12c_precisions_and_workspace():
         assert lib.ndft_caf12c(p, p, 65536, 0, 1024, -256, 512, p, prec, None, 0, None) == WORKSPACE
         # every Doppler window, also one whose bases reach N / 2
         assert lib.ndft_caf12c_workspace(1002, 0, 8, 0, 1002, prec) > 0
+
+
+def test_caf12b_arguments_and_workspace():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    assert lib.ndft_caf12b(None, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == INVAL
+    assert lib.ndft_caf12b(p, p, 8, 4, 5, 0, 1, p, 0, p, 4096, None) == INVAL
+    assert lib.ndft_caf12b(p, p, 16, 0, 4, 0, 4, p, 7, p, 4096, None) == INVAL
+    # the outer transform is an FP32 decimated DFT: no split-BF16 / FP8 form
+    assert lib.ndft_caf12b(p, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == UNSUPPORTED
+    assert lib.ndft_caf12b(p, p, 16, 0, 4, 0, 4, p, 2, p, 4096, None) == UNSUPPORTED
+    assert lib.ndft_caf12b_workspace(16, 0, 4, 0, 4, 1) == 0
+    # one work-group per delay (8192 samples or fewer): no partial surfaces
+    assert lib.ndft_caf12b_workspace(4096, 0, 300, -200, 400, 0) == 0
+    # N = 65536: 128 phases in groups of 16, eight partial surfaces of 1024 x 512
+    assert lib.ndft_caf12b_workspace(65536, 0, 1024, -256, 512, 0) == 8 * 1024 * 512 * 8
+    assert lib.ndft_caf12b(p, p, 65536, 0, 1024, -256, 512, p, 0, None, 0, None) == WORKSPACE

@@ -6,11 +6,15 @@
 //   A[l][p] = sum_{m < M} W^{m p} Y_m[p mod L],   Y_m[k] = sum_{t < L} z[m + M t] W_L^{t k},
 // so one range row costs M length-L FFTs plus M terms per requested bin, instead of N
 // terms per bin. A work-group takes one delay and MB consecutive phases m (MB L = 8192
-// samples, 64 KB of LDS): it forms their lag products (consecutive lanes read consecutive
-// samples), runs the MB FFTs in LDS with radix-8/4/2 Stockham passes (each lane holds its
+// samples): it forms their lag products (consecutive lanes read consecutive samples),
+// runs the MB FFTs in LDS with radix-8/4/2 Stockham passes (each lane holds its
 // butterflies' inputs in registers between the two barriers of a pass), and adds its
 // phases' share of every requested bin. Shares of the work-groups of a delay are partial
 // surfaces, added in a fixed order by dft12b_reduce_kernel (deterministic).
+//
+// LDS layout: transform j, entry x at j S + x + x / 8 with the row stride S = L + L / 8 + 1
+// (L >= 8). The pad after every 8 entries spreads the strided writes of the first passes
+// over the banks; the odd row stride spreads the fill, whose lanes run across transforms.
 //
 // FP32 throughout; twiddles come from the two-level table (exact 0 / +-1 at quadrant
 // points, a few ulp elsewhere), the FFT's inner twiddles as powers of one table entry.
@@ -21,7 +25,7 @@
 namespace ndft {
 
 constexpr int kDftTile = 8192;    // complex samples per work-group
-constexpr int kDftThreads = 256;
+constexpr int kDftThreads = 512;
 constexpr int kDftMaxLog = 9;     // L <= 512
 
 struct Dft12bParams {
@@ -42,6 +46,19 @@ __device__ __forceinline__ float2 caddf(float2 a, float2 b) { return make_float2
 __device__ __forceinline__ float2 csubf(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 // a times -j
 __device__ __forceinline__ float2 cmulnj(float2 a) { return make_float2(a.y, -a.x); }
+
+// padded LDS row stride and entry offset (see above)
+template <int LB>
+constexpr int dft_row_stride()
+{
+    return (1 << LB) + ((1 << LB) >> 3) + (LB >= 3 ? 1 : 0);
+}
+template <int LB>
+constexpr int dft_lds_entries()
+{
+    return (kDftTile >> LB) * dft_row_stride<LB>();
+}
+__device__ __forceinline__ int dft_pad(int x) { return x + (x >> 3); }
 
 __device__ __forceinline__ float2 table_twiddle(const float2 *coarse, const float2 *fine, int v, int tb)
 {
@@ -102,22 +119,23 @@ template <int R, int LB>
 __device__ __forceinline__ void stockham_pass(float2 *X, int mb, int p, int n, const float2 *coarse,
                                               const float2 *fine, int tb, int tid)
 {
-    constexpr int L = 1 << LB, Q = L / R;
+    constexpr int L = 1 << LB, Q = L / R, S = dft_row_stride<LB>();
     constexpr int CNT = (kDftTile / R + kDftThreads - 1) / kDftThreads;
     float2 u[CNT][R];
-    int dst[CNT];
+    int drow[CNT], dx[CNT]; // destination row start and entry (before the pad)
     const int nb = mb * Q;
     const int vstep = n / (R * p); // W_N^{k n / (R p)} = e^{-2 pi j k / (R p)}
 #pragma unroll
     for (int c = 0; c < CNT; ++c) {
         const int w = tid + c * kDftThreads;
-        dst[c] = -1;
+        drow[c] = -1;
+        dx[c] = 0;
         if (w < nb) {
             const int b = w / Q, i = w % Q;
             const int k = i & (p - 1);
-            const float2 *src = X + b * L + i;
+            const float2 *src = X + b * S;
 #pragma unroll
-            for (int r = 0; r < R; ++r) u[c][r] = src[r * Q];
+            for (int r = 0; r < R; ++r) u[c][r] = src[dft_pad(i + r * Q)];
             if (p > 1) {
                 const float2 w1 = table_twiddle(coarse, fine, k * vstep, tb);
                 float2 wr = w1;
@@ -128,15 +146,16 @@ __device__ __forceinline__ void stockham_pass(float2 *X, int mb, int p, int n, c
                 }
             }
             small_dft<R>(u[c]);
-            dst[c] = b * L + (i - k) * R + k;
+            drow[c] = b * S;
+            dx[c] = (i - k) * R + k;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CNT; ++c)
-        if (dst[c] >= 0) {
+        if (drow[c] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) X[dst[c] + r * p] = u[c][r];
+            for (int r = 0; r < R; ++r) X[drow[c] + dft_pad(dx[c] + r * p)] = u[c][r];
         }
     __syncthreads();
 }
@@ -160,8 +179,8 @@ __device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, cons
 template <int LB>
 __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
 {
-    constexpr int L = 1 << LB;
-    __shared__ float2 X[kDftTile];
+    constexpr int L = 1 << LB, S = dft_row_stride<LB>();
+    __shared__ float2 X[dft_lds_entries<LB>()];
     extern __shared__ float2 tab[];
     float2 *coarse = tab, *fine = tab + P.n_coarse;
     const int tid = threadIdx.x;
@@ -178,25 +197,31 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
             const float2 sv = P.s[i];
             const float2 rv = i >= d ? P.r[i - d] : make_float2(0.0f, 0.0f);
             const Lag z = lag_product(sv, rv);
-            X[j * L + t] = make_float2(z.zr, z.zi);
+            X[j * S + dft_pad(t)] = make_float2(z.zr, z.zi);
         }
         __syncthreads(); // also orders the table build before its first use
         fft_passes<LB, LB>(X, mb, 1, n, coarse, fine, P.tb, tid);
-        // this group's phases' share of every requested bin: sum_j W^{(m0 + j) p} Y_j[p mod L]
+        // this group's phases' share of every requested bin: sum_j W^{(m0 + j) p} Y_j[p mod L],
+        // the twiddle turned by W^p from one phase to the next and taken afresh from the
+        // table every 16 phases (the rounding of the turns stays a few ulp)
         float2 *dst = P.out + ((size_t)mg * P.n_tau + l) * P.n_dop;
         for (int q = tid; q < P.n_dop; q += kDftThreads) {
             int p = P.p0n + q;
             p = p >= n ? p - n : p;
-            const int kk = p & (L - 1);
+            const int kk = dft_pad(p & (L - 1));
             int v = (int)(((unsigned long long)(unsigned)m0 * (unsigned)p) % (unsigned)n);
+            const float2 step = table_twiddle(coarse, fine, p, P.tb);
             float2 acc = make_float2(0.0f, 0.0f);
+            float2 w = make_float2(1.0f, 0.0f);
             for (int j = 0; j < mb; ++j) {
-                const float2 w = table_twiddle(coarse, fine, v, P.tb);
-                const float2 y = X[j * L + kk];
+                if ((j & 15) == 0) {
+                    w = table_twiddle(coarse, fine, v, P.tb);
+                    v = (int)(((long long)v + 16LL * p) % n);
+                }
+                const float2 y = X[j * S + kk];
                 acc.x = fmaf(w.x, y.x, fmaf(-w.y, y.y, acc.x));
                 acc.y = fmaf(w.x, y.y, fmaf(w.y, y.x, acc.y));
-                v += p;
-                v = v >= n ? v - n : v;
+                w = cmulf(w, step);
             }
             dst[q] = acc;
         }

@@ -145,9 +145,10 @@ def bench_adjoint(nd, synth, torch, args):
     return res
 
 
-def bench_caf12c(nd, synth, torch, args):
-    """The Eq. (12c) surface (ordinary lag product, then the Eq. (6) operator) on the same
-    N=65536 workload, through the sign-split kernels."""
+def bench_other_surfaces(nd, synth, torch, args):
+    """The Eq. (12b) surface (Eq. (6) lag product, then the ordinary DFT: decimated FFTs,
+    FP32) and the Eq. (12c) surface (ordinary lag product, then the Eq. (6) operator:
+    the sign-split kernels) on the same N=65536 workload."""
     import numpy as np
 
     c = synth.config3()
@@ -155,37 +156,41 @@ def bench_caf12c(nd, synth, torch, args):
     s = torch.from_numpy(c["s"]).cuda()
     r = torch.from_numpy(c["r"]).cuda()
     cells = c["n_tau"] * c["n_dop"]
-    res = {"workload": "caf12c_n65536_tau1024_dop512"}
     rows = np.array([0, 37, 511, 1023])
-    ref = None
-    if not args.no_cpu_baseline:
-        import oracle
+    out_all = {}
+    for eq, fn, wsfn, forms in (("caf12b", nd.caf12b, nd.caf12b_workspace_bytes, ("fp32",)),
+                                ("caf12c", nd.caf12c, nd.caf12c_workspace_bytes, ("bf16x2", "fp8"))):
+        res = {"workload": "%s_n65536_tau1024_dop512" % eq}
+        ref = None
+        if not args.no_cpu_baseline:
+            import oracle
 
-        ref = oracle.caf12c(c["s"], c["r"], *a, rows=rows)
-    for form in ("bf16x2", "fp8"):
-        prec = nd.PRECISIONS[form]
-        ws = torch.empty(nd.caf12c_workspace_bytes(c["n"], *a, prec), dtype=torch.uint8, device="cuda")
-        out = torch.empty((c["n_tau"], c["n_dop"]), dtype=torch.complex64, device="cuda")
-        for _ in range(args.warmup):
-            nd.caf12c(s, r, *a, prec, out=out, ws=ws)
-        torch.cuda.synchronize()
-        reps = max(5, args.steps)
-        e0, e1 = _events(torch)
-        e0.record()
-        for _ in range(reps):
-            nd.caf12c(s, r, *a, prec, out=out, ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        res[form] = {"ms_per_surface": ms, "cells_per_s": cells / (ms * 1e-3)}
-        if ref is not None:
-            g = out.cpu().numpy()[rows].astype(np.complex128)
-            Ao, sc = ref
-            err = (np.abs(g.real - Ao.real) + np.abs(g.imag - Ao.imag)) / np.where(sc > 0, sc, 1)
-            res[form]["max_l1_rel_err_vs_oracle"] = float(err.max())
-            res[form]["err_rows_checked"] = int(len(rows))
-        del ws
-    return res
+            ref = getattr(oracle, eq)(c["s"], c["r"], *a, rows=rows)
+        for form in forms:
+            prec = nd.PRECISIONS[form]
+            ws = torch.empty(max(1, wsfn(c["n"], *a, prec)), dtype=torch.uint8, device="cuda")
+            out = torch.empty((c["n_tau"], c["n_dop"]), dtype=torch.complex64, device="cuda")
+            for _ in range(args.warmup):
+                fn(s, r, *a, prec, out=out, ws=ws)
+            torch.cuda.synchronize()
+            reps = max(5, args.steps)
+            e0, e1 = _events(torch)
+            e0.record()
+            for _ in range(reps):
+                fn(s, r, *a, prec, out=out, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[form] = {"ms_per_surface": ms, "cells_per_s": cells / (ms * 1e-3)}
+            if ref is not None:
+                g = out.cpu().numpy()[rows].astype(np.complex128)
+                Ao, sc = ref
+                err = (np.abs(g.real - Ao.real) + np.abs(g.imag - Ao.imag)) / np.where(sc > 0, sc, 1)
+                res[form]["max_l1_rel_err_vs_oracle"] = float(err.max())
+                res[form]["err_rows_checked"] = int(len(rows))
+            del ws
+        out_all[eq] = res
+    return out_all
 
 
 def main():
@@ -346,7 +351,7 @@ def main():
     if not args.no_extras:
         extras["batched"] = bench_batched(nd, tune, synth, torch, args)
         extras["adjoint"] = bench_adjoint(nd, synth, torch, args)
-        extras["caf12c"] = bench_caf12c(nd, synth, torch, args)
+        extras.update(bench_other_surfaces(nd, synth, torch, args))
 
     main_res = results[args.form]
     line = {

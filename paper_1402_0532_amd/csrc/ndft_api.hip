@@ -1117,7 +1117,10 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     P.n_coarse = L.n_coarse;
     P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : reinterpret_cast<float2 *>(A);
     void *args[] = {&P};
-    const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(n_tau, 65535));
+    // about eight work-groups per compute unit, each looping over its delays (the table
+    // is built once per work-group)
+    const int64_t ydim = std::max<int64_t>(1, cdiv(8LL * device_cu_count(), L.n_mg));
+    const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(std::min<int64_t>(n_tau, ydim), 65535));
     ProfScope prof(s);
     hipError_t e = hipLaunchKernel(dft12b_fn(L.lb), grid, dim3(kDftThreads), args, L.dyn_bytes, s);
     prof.stop();

@@ -175,6 +175,56 @@ __device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, cons
     }
 }
 
+// The lag products and the first Stockham pass (p = 1: no inner twiddles) in one step:
+// butterfly (b, i) loads its R samples t = i + r L / R of transform b straight from the
+// inputs, forms their lag products and writes the R-point DFT to x[b][i R + r]. Lanes run
+// over b first, so a wave's loads are runs of consecutive samples.
+template <int LB>
+__device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P, int m0, int mb, int d, int tid)
+{
+    constexpr int L = 1 << LB, S = dft_row_stride<LB>();
+    constexpr int R = LB >= 3 ? 8 : (LB == 2 ? 4 : (LB == 1 ? 2 : 1));
+    constexpr int Q = L / R;
+    constexpr int CNT = kDftTile / R / kDftThreads;
+    static_assert(CNT * R * kDftThreads == kDftTile, "whole butterflies per thread");
+    float2 sv[CNT][R], rv[CNT][R];
+    int bi[CNT], ii[CNT];
+    const int nb = mb * Q;
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        const int w = tid + c * kDftThreads;
+        bi[c] = -1;
+        ii[c] = 0;
+        if (w < nb) {
+            bi[c] = w % mb;
+            ii[c] = w / mb;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sv[c][r] = make_float2(0.0f, 0.0f);
+            rv[c][r] = make_float2(0.0f, 0.0f);
+            if (bi[c] >= 0) {
+                const int idx = m0 + bi[c] + P.M * (ii[c] + r * Q);
+                sv[c][r] = P.s[idx];
+                if (idx >= d) rv[c][r] = P.r[idx - d];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        if (bi[c] < 0) continue;
+        float2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const Lag z = lag_product(sv[c][r], rv[c][r]);
+            u[r] = make_float2(z.zr, z.zi);
+        }
+        if constexpr (R > 1) small_dft<R>(u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) X[bi[c] * S + dft_pad(ii[c] * R + r)] = u[r];
+    }
+}
+
 // Grid: x = phase group (MB phases), y strides over the delays. Dynamic LDS: the table.
 template <int LB>
 __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
@@ -190,17 +240,11 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
     build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, kDftThreads);
     for (int l = blockIdx.y; l < P.n_tau; l += gridDim.y) {
         const int d = P.tau0 + l;
-        // lag products of samples m0 + j + M t (j < mb, t < L) into X[j][t]
-        for (int e = tid; e < mb * L; e += kDftThreads) {
-            const int j = e % mb, t = e / mb;
-            const int i = m0 + j + M * t;
-            const float2 sv = P.s[i];
-            const float2 rv = i >= d ? P.r[i - d] : make_float2(0.0f, 0.0f);
-            const Lag z = lag_product(sv, rv);
-            X[j * S + dft_pad(t)] = make_float2(z.zr, z.zi);
-        }
+        // lag products of samples m0 + j + M t (j < mb, t < L), transformed into X[j]
+        fill_first_pass<LB>(X, P, m0, mb, d, tid);
         __syncthreads(); // also orders the table build before its first use
-        fft_passes<LB, LB>(X, mb, 1, n, coarse, fine, P.tb, tid);
+        constexpr int LB0 = LB >= 3 ? 3 : LB; // bits of the first pass
+        fft_passes<LB, LB - LB0>(X, mb, 1 << LB0, n, coarse, fine, P.tb, tid);
         // this group's phases' share of every requested bin: sum_j W^{(m0 + j) p} Y_j[p mod L],
         // the twiddle turned by W^p from one phase to the next and taken afresh from the
         // table every 16 phases (the rounding of the turns stays a few ulp)

@@ -31,7 +31,7 @@ KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_contract.hpp",
                   "paper_1402_0532_amd/csrc/ndft_surface_bf16.hpp",
                   "paper_1402_0532_amd/csrc/ndft_signsplit.hpp"]
 TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
-SPLIT_PLAN_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_")
+SPLIT_PLAN_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_", "fp32s_")
 
 
 def kernel_source_hash() -> str:
@@ -302,7 +302,9 @@ def main():
             "frac_of_peak": achieved / PEAK_TFLOPS[form],
             "plan": pname,
             "ksplit": ks,
-            "timed_kernel": "dsum_kernel (8 N flops per cell)" if split else "contraction (16 N flops per cell)",
+            "timed_kernel": ("dft12b_kernel<., true> (twiddle half by decimated FFT; 8 N dense-equivalent flops "
+                             "per cell)" if pname.startswith("fp32s_") else "dsum_kernel (8 N flops per cell)")
+            if split else "contraction (16 N flops per cell)",
         }
         if form in tuned:
             results[form]["autotune"] = {k: tuned[form][k] for k in ("name", "ksplit", "ms", "tried")}

@@ -204,7 +204,8 @@ int32_t ndft_plan_count(ndft_prec prec);
 const char *ndft_plan_name(ndft_prec prec, int32_t plan);
 ndft_status ndft_set_plan(ndft_prec prec, int32_t plan, int32_t ksplit);
 /* The plan and ksplit ndft_caf / ndft_forward would use for (n, n_cols = delays or
- * rows, bins p0 .. p0 + n_bins - 1). */
+ * rows, bins p0 .. p0 + n_bins - 1). ksplit counts the matrix-core sample chunks: 0 for
+ * a plan with no matrix part (the FP32 sign-split plan, whose twiddle half is an FFT). */
 ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
                           int32_t *plan, int32_t *ksplit);
 

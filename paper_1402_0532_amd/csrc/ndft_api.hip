@@ -112,6 +112,7 @@ struct Plan {
     const void *lag_kfn;     // sign-split plans: the lag / twiddle-sign kernel (lsum_kernel)
     const void *lag_kfn_lin; // the same for the Eq. (12c) surface (ordinary lag product)
     int stage_a;             // plane uint4 per stage (plane plans)
+    bool fft_d;              // sign-split with the twiddle half as a decimated FFT (no matrix kernel)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -137,6 +138,7 @@ Plan make_plan(const char *name)
     p.raw_inputs = false;
     p.lag_kfn = nullptr;
     p.lag_kfn_lin = nullptr;
+    p.fft_d = false;
     p.stage_a = 0;
     return p;
 }
@@ -169,6 +171,7 @@ Plan make_surface_plan(const char *name)
     p.raw_inputs = true;
     p.lag_kfn = nullptr;
     p.lag_kfn_lin = nullptr;
+    p.fft_d = false;
     p.stage_a = Cfg::STAGE_A;
     return p;
 }
@@ -203,7 +206,21 @@ Plan make_split_plan(const char *name, double rel_cost)
     p.raw_inputs = true;
     p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel<false>);
     p.lag_kfn_lin = reinterpret_cast<const void *>(&lsum_kernel<true>);
+    p.fft_d = false;
     p.stage_a = Cfg::STAGE_A;
+    return p;
+}
+
+// FP32 form of the sign-split plans: lsum_kernel for the twiddle-sign half (and base 0), and
+// the twiddle half D = sum_k W^{pk} csgn(z_k), an ordinary DFT of the exact lag signs, by the
+// decimated FFT kernel of the Eq. (12b) surface (dft12b_kernel<., true>), in FP32.
+Plan make_fftd_plan(const char *name)
+{
+    Plan p = make_split_plan<8, 2, 128, true>(name, 1.0);
+    p.kfn[0] = nullptr;
+    p.lag_kfn_lin = nullptr;
+    p.fft_d = true;
+    p.cost_scale = 0.05; // far below the FP32 contraction wherever it is eligible
     return p;
 }
 
@@ -226,6 +243,7 @@ const std::vector<Plan> &plans(int prec)
         make_plan<PREC_FP32, 1, 8, 2, 1, 8>("fp32_b64_l256_w8_ks8"),
         make_plan<PREC_FP32, 4, 2, 2, 1, 8>("fp32_b256_l64_w8_ks8"),
         make_plan<PREC_FP32, 3, 4, 1, 1, 8>("fp32_b96_l128_w12_ks8"),
+        make_fftd_plan("fp32s_fftd_b64_l256"),
     };
     static const std::vector<Plan> fp8 = {
         make_plan<PREC_FP8, 2, 4, 2, 1, 16>("fp8_b128_l128_w8_ks16"),
@@ -287,6 +305,12 @@ void set_kernel_attributes()
             }
 }
 
+struct Dft12bLaunch {
+    int lb, M, MB, n_mg, tb, n_coarse;
+    size_t dyn_bytes; // the twiddle table (dynamic LDS)
+    size_t ws_bytes;  // partial surfaces when a delay takes more than one work-group
+};
+
 struct Launch {
     const Plan *plan;
     int prec;
@@ -308,6 +332,8 @@ struct Launch {
     size_t plane_off;       // offset of the planes in the workspace
     int grp_stride;
     int lin;           // sign-split: the Eq. (12c) lag product (lag_kfn_lin)
+    Dft12bLaunch dft;  // fft_d plans: the twiddle half's decimated FFT
+    size_t dft_off;    // fft_d plans: offset of its partial surfaces in the workspace
 };
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -414,6 +440,25 @@ int64_t lsum_groups(const Launch &L)
     return std::max<int64_t>(1, cdiv(L.n_bases - has0, kLsumBases));
 }
 
+// ------------------------------------------------------------------------------------
+// the Eq. (12b) surface: decimated DFT of the lag-product rows
+// ------------------------------------------------------------------------------------
+
+Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop)
+{
+    Dft12bLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    while (L.lb < kDftMaxLog && n % (2LL << L.lb) == 0) ++L.lb; // L = 2^lb, the largest power of two dividing n
+    L.M = (int)(n >> L.lb);
+    L.MB = std::min(kDftTile >> L.lb, L.M);
+    L.n_mg = (int)cdiv(L.M, L.MB);
+    int exact = 0;
+    choose_table(n, 65536, &L.tb, &L.n_coarse, &exact);
+    L.dyn_bytes = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
+    L.ws_bytes = L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0;
+    return L;
+}
+
 // lin: the Eq. (12c) surface, which only the sign-split plans compute; L.plan is nullptr
 // when the precision has none.
 Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, int64_t n_bins,
@@ -431,7 +476,10 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         ko = g_ksplit_override[prec];
     }
     const std::vector<Plan> &ps = plans(prec);
-    auto usable = [&](int k) { return lin ? ps[k].lag_kfn_lin != nullptr : ps[k].kfn[prod] != nullptr; };
+    auto usable = [&](int k) {
+        if (lin) return ps[k].lag_kfn_lin != nullptr;
+        return ps[k].kfn[prod] != nullptr || (prod == PROD_LAG && ps[k].fft_d);
+    };
     if (pi < 0 || pi >= (int)ps.size() || !usable(pi)) {
         // built-in choice: padded matrix-core work times the plan's operand-generation
         // overhead, then the earlier plan
@@ -443,6 +491,8 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
             // chunk of C samples; taken only while that stays about one per chunk (the
             // Eq. (12c) surface has no other form: the walk is exact for any base)
             if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
+            // the FFT of the twiddle half wants a power-of-two factor of at least 64 in n
+            if (ps[k].fft_d && n % 64 != 0) continue;
             const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
             double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
@@ -472,6 +522,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     L.kchunk = (int)(cdiv(cdiv(n, L.ksplit), gran) * gran);
     L.ksplit = (int)cdiv(n, L.kchunk); // no empty chunks
     if (L.tiles_b == 0) L.ksplit = 0;  // sign-split with base 0 only: no matrix part
+    if (L.plan->fft_d) L.ksplit = 0;   // the twiddle half is not a matrix contraction
     if (L.plan->lag_kfn) {
         // lsum_kernel: blocks of kLsumDelays delays x kLsumBases bases x a sample range of
         // whole chunks; about two blocks per compute unit
@@ -496,6 +547,11 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
         L.code_off = L.ws_bytes;
         L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
+    }
+    if (L.plan->fft_d) {
+        L.dft = plan_dft12b(n, n_cols, n_bins);
+        L.dft_off = L.ws_bytes;
+        L.ws_bytes += L.dft.ws_bytes;
     }
     return L;
 }
@@ -672,7 +728,7 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         if (hipLaunchKernel(tfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
     }
     ndft_status st = check_launch();
-    if (st != NDFT_OK || L.tiles_b == 0) return st;
+    if (st != NDFT_OK || L.tiles_b == 0 || L.plan->fft_d) return st; // fft_d: the FFT runs after the reduction
     ContractParams P;
     std::memset(&P, 0, sizeof(P));
     P.n = (int)n;
@@ -749,44 +805,70 @@ ndft_status ws_ok(void *ws, size_t ws_bytes, size_t need)
     return NDFT_OK;
 }
 
-// ------------------------------------------------------------------------------------
-// the Eq. (12b) surface: decimated DFT of the lag-product rows
-// ------------------------------------------------------------------------------------
-struct Dft12bLaunch {
-    int lb, M, MB, n_mg, tb, n_coarse;
-    size_t dyn_bytes; // the twiddle table (dynamic LDS)
-    size_t ws_bytes;  // partial surfaces when a delay takes more than one work-group
-};
-
-Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop)
-{
-    Dft12bLaunch L;
-    std::memset(&L, 0, sizeof(L));
-    while (L.lb < kDftMaxLog && n % (2LL << L.lb) == 0) ++L.lb; // L = 2^lb, the largest power of two dividing n
-    L.M = (int)(n >> L.lb);
-    L.MB = std::min(kDftTile >> L.lb, L.M);
-    L.n_mg = (int)cdiv(L.M, L.MB);
-    int exact = 0;
-    choose_table(n, 65536, &L.tb, &L.n_coarse, &exact);
-    L.dyn_bytes = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
-    L.ws_bytes = L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0;
-    return L;
-}
-
+template <bool SIGNS>
 const void *dft12b_fn(int lb)
 {
     static const void *fns[kDftMaxLog + 1] = {
-        reinterpret_cast<const void *>(&dft12b_kernel<0>), reinterpret_cast<const void *>(&dft12b_kernel<1>),
-        reinterpret_cast<const void *>(&dft12b_kernel<2>), reinterpret_cast<const void *>(&dft12b_kernel<3>),
-        reinterpret_cast<const void *>(&dft12b_kernel<4>), reinterpret_cast<const void *>(&dft12b_kernel<5>),
-        reinterpret_cast<const void *>(&dft12b_kernel<6>), reinterpret_cast<const void *>(&dft12b_kernel<7>),
-        reinterpret_cast<const void *>(&dft12b_kernel<8>), reinterpret_cast<const void *>(&dft12b_kernel<9>)};
+        reinterpret_cast<const void *>(&dft12b_kernel<0, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<1, SIGNS>),
+        reinterpret_cast<const void *>(&dft12b_kernel<2, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<3, SIGNS>),
+        reinterpret_cast<const void *>(&dft12b_kernel<4, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<5, SIGNS>),
+        reinterpret_cast<const void *>(&dft12b_kernel<6, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<7, SIGNS>),
+        reinterpret_cast<const void *>(&dft12b_kernel<8, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<9, SIGNS>)};
     static_assert(kDftMaxLog == 9, "one instance per transform length");
     return fns[lb];
 }
 
 std::once_flag g_dft_attr_once;
 hipError_t g_dft_attr_err = hipSuccess;
+
+// The decimated DFT of the lag products (signs = false: the Eq. (12b) surface) or of their
+// exact signs (signs = true: the twiddle half of the Eq. (12a) sign-split form, bin 0 left
+// out), written to A or, with accumulate, added to it. ws holds the partial surfaces.
+ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t tau0,
+                       int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, bool signs, bool accumulate,
+                       hipStream_t s)
+{
+    std::call_once(g_dft_attr_once, [] {
+        for (int lb = 0; lb <= kDftMaxLog; ++lb)
+            for (const void *fn : {dft12b_fn<false>(lb), dft12b_fn<true>(lb)}) {
+                hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+                if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
+            }
+    });
+    if (g_dft_attr_err != hipSuccess) return NDFT_E_HIP;
+    Dft12bParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.s = surv;
+    P.r = ref;
+    P.n = (int)n;
+    P.tau0 = (int)tau0;
+    P.n_tau = (int)n_tau;
+    P.p0n = (int)mod_n(p0, n);
+    P.n_dop = (int)n_dop;
+    P.M = L.M;
+    P.MB = L.MB;
+    P.n_mg = L.n_mg;
+    P.tb = L.tb;
+    P.n_coarse = L.n_coarse;
+    P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : A;
+    P.accumulate = L.n_mg > 1 ? 0 : (accumulate ? 1 : 0);
+    void *args[] = {&P};
+    // about eight work-groups per compute unit, each looping over its delays (the table
+    // is built once per work-group)
+    const int64_t ydim = std::max<int64_t>(1, cdiv(8LL * device_cu_count(), L.n_mg));
+    const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(std::min<int64_t>(n_tau, ydim), 65535));
+    const void *fn = signs ? dft12b_fn<true>(L.lb) : dft12b_fn<false>(L.lb);
+    ProfScope prof(s);
+    hipError_t e = hipLaunchKernel(fn, grid, dim3(kDftThreads), args, L.dyn_bytes, s);
+    prof.stop();
+    if (e != hipSuccess) return NDFT_E_HIP;
+    if (L.n_mg > 1) {
+        const long long cells = (long long)n_tau * n_dop;
+        hipLaunchKernelGGL(dft12b_reduce_kernel, dim3((unsigned)cdiv(cells, 256)), dim3(256), 0, s,
+                           static_cast<const float2 *>(ws), L.n_mg, cells, A, accumulate ? 1 : 0);
+    }
+    return check_launch();
+}
 
 struct AdjLaunch {
     BaseMap bm;
@@ -1040,6 +1122,14 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     if (L.plan->lag_kfn) {
         st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
                           tau0, part, ws, s);
+        if (st == NDFT_OK && L.plan->fft_d) {
+            // the twiddle-sign half (and base 0) into A, then the twiddle half added by FFT
+            st = launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+            if (st != NDFT_OK) return st;
+            return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n,
+                              tau0, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A),
+                              static_cast<char *>(ws) + L.dft_off, true, true, s);
+        }
     } else {
         uint4 *planes =
             L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
@@ -1093,44 +1183,9 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     const Dft12bLaunch L = plan_dft12b(n, n_tau, n_dop);
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
-    std::call_once(g_dft_attr_once, [] {
-        for (int lb = 0; lb <= kDftMaxLog; ++lb) {
-            hipError_t e = hipFuncSetAttribute(dft12b_fn(lb), hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-            if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
-        }
-    });
-    if (g_dft_attr_err != hipSuccess) return NDFT_E_HIP;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    Dft12bParams P;
-    std::memset(&P, 0, sizeof(P));
-    P.s = reinterpret_cast<const float2 *>(surv);
-    P.r = reinterpret_cast<const float2 *>(ref);
-    P.n = (int)n;
-    P.tau0 = (int)tau0;
-    P.n_tau = (int)n_tau;
-    P.p0n = (int)mod_n(p0, n);
-    P.n_dop = (int)n_dop;
-    P.M = L.M;
-    P.MB = L.MB;
-    P.n_mg = L.n_mg;
-    P.tb = L.tb;
-    P.n_coarse = L.n_coarse;
-    P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : reinterpret_cast<float2 *>(A);
-    void *args[] = {&P};
-    // about eight work-groups per compute unit, each looping over its delays (the table
-    // is built once per work-group)
-    const int64_t ydim = std::max<int64_t>(1, cdiv(8LL * device_cu_count(), L.n_mg));
-    const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(std::min<int64_t>(n_tau, ydim), 65535));
-    ProfScope prof(s);
-    hipError_t e = hipLaunchKernel(dft12b_fn(L.lb), grid, dim3(kDftThreads), args, L.dyn_bytes, s);
-    prof.stop();
-    if (e != hipSuccess) return NDFT_E_HIP;
-    if (L.n_mg > 1) {
-        const long long cells = (long long)n_tau * n_dop;
-        hipLaunchKernelGGL(dft12b_reduce_kernel, dim3((unsigned)cdiv(cells, 256)), dim3(256), 0, s,
-                           static_cast<const float2 *>(ws), L.n_mg, cells, reinterpret_cast<float2 *>(A));
-    }
-    return check_launch();
+    return launch_dft(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
+                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), ws, false, false,
+                      reinterpret_cast<hipStream_t>(stream));
 }
 
 ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,

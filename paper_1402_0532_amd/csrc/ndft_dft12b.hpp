@@ -16,6 +16,12 @@
 // (L >= 8). The pad after every 8 entries spreads the strided writes of the first passes
 // over the banks; the odd row stride spreads the fill, whose lanes run across transforms.
 //
+// SIGNS: the same DFT of the exact lag signs, D(l, p) = sum_i W^{ip} csgn(z_l[i]), which is
+// the twiddle half of the Eq. (12a) sign-split form (see ndft_signsplit.hpp): the FP32
+// form of that surface takes it from here instead of the matrix cores. Bin p = 0 is left
+// out there (the twiddle-sign kernel sums base 0 whole), and the result is added to the
+// surface the reduction of the other half wrote.
+//
 // FP32 throughout; twiddles come from the two-level table (exact 0 / +-1 at quadrant
 // points, a few ulp elsewhere), the FFT's inner twiddles as powers of one table entry.
 #pragma once
@@ -35,6 +41,7 @@ struct Dft12bParams {
     int M, MB, n_mg;      // phases, phases per work-group, work-groups per delay
     int tb, n_coarse;     // two-level twiddle table of W^v, v in [0, n)
     float2 *out;          // n_mg == 1: the surface [n_tau][n_dop]; else partials [n_mg][n_tau][n_dop]
+    int accumulate;       // n_mg == 1: add to the surface instead of writing it
 };
 
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b)
@@ -179,7 +186,7 @@ __device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, cons
 // butterfly (b, i) loads its R samples t = i + r L / R of transform b straight from the
 // inputs, forms their lag products and writes the R-point DFT to x[b][i R + r]. Lanes run
 // over b first, so a wave's loads are runs of consecutive samples.
-template <int LB>
+template <int LB, bool SIGNS>
 __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P, int m0, int mb, int d, int tid)
 {
     constexpr int L = 1 << LB, S = dft_row_stride<LB>();
@@ -217,7 +224,7 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const Lag z = lag_product(sv[c][r], rv[c][r]);
-            u[r] = make_float2(z.zr, z.zi);
+            u[r] = SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
         }
         if constexpr (R > 1) small_dft<R>(u);
 #pragma unroll
@@ -226,7 +233,7 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
 }
 
 // Grid: x = phase group (MB phases), y strides over the delays. Dynamic LDS: the table.
-template <int LB>
+template <int LB, bool SIGNS>
 __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
 {
     constexpr int L = 1 << LB, S = dft_row_stride<LB>();
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
     for (int l = blockIdx.y; l < P.n_tau; l += gridDim.y) {
         const int d = P.tau0 + l;
         // lag products of samples m0 + j + M t (j < mb, t < L), transformed into X[j]
-        fill_first_pass<LB>(X, P, m0, mb, d, tid);
+        fill_first_pass<LB, SIGNS>(X, P, m0, mb, d, tid);
         __syncthreads(); // also orders the table build before its first use
         constexpr int LB0 = LB >= 3 ? 3 : LB; // bits of the first pass
         fft_passes<LB, LB - LB0>(X, mb, 1 << LB0, n, coarse, fine, P.tb, tid);
@@ -267,6 +274,8 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
                 acc.y = fmaf(w.x, y.y, fmaf(w.y, y.x, acc.y));
                 w = cmulf(w, step);
             }
+            if (SIGNS && p == 0) acc = make_float2(0.0f, 0.0f);
+            if (P.accumulate) acc = caddf(acc, dst[q]);
             dst[q] = acc;
         }
         __syncthreads(); // X is refilled for the next delay
@@ -274,13 +283,14 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
 }
 
 // A[e] = sum over the phase groups g = 0 .. n_mg - 1 of part[g][e], in that order.
+// accumulate: A[e] += that sum (A[e] first, then the groups in order).
 __global__ __launch_bounds__(256) void dft12b_reduce_kernel(const float2 *part, int n_mg, long long cells,
-                                                            float2 *A)
+                                                            float2 *A, int accumulate)
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= cells) return;
-    float2 acc = part[e];
-    for (int g = 1; g < n_mg; ++g) acc = caddf(acc, part[(long long)g * cells + e]);
+    float2 acc = accumulate ? A[e] : make_float2(0.0f, 0.0f);
+    for (int g = 0; g < n_mg; ++g) acc = caddf(acc, part[(long long)g * cells + e]);
     A[e] = acc;
 }
 

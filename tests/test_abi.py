@@ -103,7 +103,8 @@ def test_workspace_query_is_consistent():
     plan = ctypes.c_int32()
     ks = ctypes.c_int32()
     assert lib.ndft_get_plan(0, 65536, 1024, -256, 512, ctypes.byref(plan), ctypes.byref(ks)) == 0
-    assert 0 <= plan.value < lib.ndft_plan_count(0) and ks.value >= 1
+    # ksplit counts matrix-core sample chunks: 0 for a plan without a matrix part
+    assert 0 <= plan.value < lib.ndft_plan_count(0) and ks.value >= 0
 
 
 def test_plan_table():

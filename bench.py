@@ -159,7 +159,7 @@ def bench_other_surfaces(nd, synth, torch, args):
     rows = np.array([0, 37, 511, 1023])
     out_all = {}
     for eq, fn, wsfn, forms in (("caf12b", nd.caf12b, nd.caf12b_workspace_bytes, ("fp32",)),
-                                ("caf12c", nd.caf12c, nd.caf12c_workspace_bytes, ("bf16x2", "fp8"))):
+                                ("caf12c", nd.caf12c, nd.caf12c_workspace_bytes, ("fp32", "bf16x2", "fp8"))):
         res = {"workload": "%s_n65536_tau1024_dop512" % eq}
         ref = None
         if not args.no_cpu_baseline:

@@ -118,10 +118,10 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
  * with d, p, the zero reference before the record, the layout and the limits of
  * ndft_caf. The lag product's component signs are exact (FP64 from the complex64
  * inputs); its value enters in FP32.
- * Only the sign-split forms compute it: prec NDFT_BF16X2 or NDFT_FP8 (their plans are
- * the only candidates, for any Doppler window); NDFT_FP32 returns NDFT_E_UNSUPPORTED
- * and ndft_caf12c_workspace then returns 0. ndft_set_plan overrides apply when they
- * name a sign-split plan. Errors, workspace and stream as for ndft_caf.
+ * Only the sign-split plans compute it (the only candidates, for any Doppler window):
+ * NDFT_BF16X2 / NDFT_FP8 with the twiddle half on the matrix cores, NDFT_FP32 with it as
+ * an FFT of the exact lag signs. ndft_set_plan overrides apply when they name a
+ * sign-split plan. Errors, workspace and stream as for ndft_caf.
  * ------------------------------------------------------------------------------- */
 size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
                              ndft_prec prec);

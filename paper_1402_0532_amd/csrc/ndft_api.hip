@@ -218,8 +218,7 @@ Plan make_fftd_plan(const char *name)
 {
     Plan p = make_split_plan<8, 2, 128, true>(name, 1.0);
     p.kfn[0] = nullptr;
-    p.lag_kfn_lin = nullptr;
-    p.fft_d = true;
+    p.fft_d = true; // lag_kfn_lin kept: the Eq. (12c) surface in FP32 the same way
     p.cost_scale = 0.05; // far below the FP32 contraction wherever it is eligible
     return p;
 }
@@ -492,7 +491,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
             // Eq. (12c) surface has no other form: the walk is exact for any base)
             if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
             // the FFT of the twiddle half wants a power-of-two factor of at least 64 in n
-            if (ps[k].fft_d && n % 64 != 0) continue;
+            if (!lin && ps[k].fft_d && n % 64 != 0) continue;
             const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
             double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
@@ -805,15 +804,15 @@ ndft_status ws_ok(void *ws, size_t ws_bytes, size_t need)
     return NDFT_OK;
 }
 
-template <bool SIGNS>
+template <int SRC>
 const void *dft12b_fn(int lb)
 {
     static const void *fns[kDftMaxLog + 1] = {
-        reinterpret_cast<const void *>(&dft12b_kernel<0, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<1, SIGNS>),
-        reinterpret_cast<const void *>(&dft12b_kernel<2, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<3, SIGNS>),
-        reinterpret_cast<const void *>(&dft12b_kernel<4, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<5, SIGNS>),
-        reinterpret_cast<const void *>(&dft12b_kernel<6, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<7, SIGNS>),
-        reinterpret_cast<const void *>(&dft12b_kernel<8, SIGNS>), reinterpret_cast<const void *>(&dft12b_kernel<9, SIGNS>)};
+        reinterpret_cast<const void *>(&dft12b_kernel<0, SRC>), reinterpret_cast<const void *>(&dft12b_kernel<1, SRC>),
+        reinterpret_cast<const void *>(&dft12b_kernel<2, SRC>), reinterpret_cast<const void *>(&dft12b_kernel<3, SRC>),
+        reinterpret_cast<const void *>(&dft12b_kernel<4, SRC>), reinterpret_cast<const void *>(&dft12b_kernel<5, SRC>),
+        reinterpret_cast<const void *>(&dft12b_kernel<6, SRC>), reinterpret_cast<const void *>(&dft12b_kernel<7, SRC>),
+        reinterpret_cast<const void *>(&dft12b_kernel<8, SRC>), reinterpret_cast<const void *>(&dft12b_kernel<9, SRC>)};
     static_assert(kDftMaxLog == 9, "one instance per transform length");
     return fns[lb];
 }
@@ -821,16 +820,17 @@ const void *dft12b_fn(int lb)
 std::once_flag g_dft_attr_once;
 hipError_t g_dft_attr_err = hipSuccess;
 
-// The decimated DFT of the lag products (signs = false: the Eq. (12b) surface) or of their
-// exact signs (signs = true: the twiddle half of the Eq. (12a) sign-split form, bin 0 left
-// out), written to A or, with accumulate, added to it. ws holds the partial surfaces.
+// The decimated DFT of the lag products (src DFT_LAG: the Eq. (12b) surface) or of their
+// exact signs (DFT_SIGNS / DFT_LIN_SIGNS: the twiddle half of the Eq. (12a) / Eq. (12c)
+// sign-split forms, bin 0 left out), written to A or, with accumulate, added to it. ws
+// holds the partial surfaces.
 ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t tau0,
-                       int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, bool signs, bool accumulate,
+                       int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, int src, bool accumulate,
                        hipStream_t s)
 {
     std::call_once(g_dft_attr_once, [] {
         for (int lb = 0; lb <= kDftMaxLog; ++lb)
-            for (const void *fn : {dft12b_fn<false>(lb), dft12b_fn<true>(lb)}) {
+            for (const void *fn : {dft12b_fn<DFT_LAG>(lb), dft12b_fn<DFT_SIGNS>(lb), dft12b_fn<DFT_LIN_SIGNS>(lb)}) {
                 hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
                 if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
             }
@@ -857,7 +857,8 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
     // is built once per work-group)
     const int64_t ydim = std::max<int64_t>(1, cdiv(8LL * device_cu_count(), L.n_mg));
     const dim3 grid((unsigned)L.n_mg, (unsigned)std::min<int64_t>(std::min<int64_t>(n_tau, ydim), 65535));
-    const void *fn = signs ? dft12b_fn<true>(L.lb) : dft12b_fn<false>(L.lb);
+    const void *fn = src == DFT_SIGNS ? dft12b_fn<DFT_SIGNS>(L.lb)
+                     : (src == DFT_LIN_SIGNS ? dft12b_fn<DFT_LIN_SIGNS>(L.lb) : dft12b_fn<DFT_LAG>(L.lb));
     ProfScope prof(s);
     hipError_t e = hipLaunchKernel(fn, grid, dim3(kDftThreads), args, L.dyn_bytes, s);
     prof.stop();
@@ -1128,7 +1129,7 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
             if (st != NDFT_OK) return st;
             return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n,
                               tau0, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A),
-                              static_cast<char *>(ws) + L.dft_off, true, true, s);
+                              static_cast<char *>(ws) + L.dft_off, DFT_SIGNS, true, s);
         }
     } else {
         uint4 *planes =
@@ -1163,7 +1164,12 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
                       tau0, part, ws, s);
     if (st != NDFT_OK) return st;
-    return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+    st = launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+    if (st != NDFT_OK || !L.plan->fft_d) return st;
+    // FP32: the twiddle half by FFT of the exact signs of the ordinary lag products
+    return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
+                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), static_cast<char *>(ws) + L.dft_off,
+                      DFT_LIN_SIGNS, true, s);
 }
 
 size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
@@ -1184,7 +1190,7 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     return launch_dft(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
-                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), ws, false, false,
+                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), ws, DFT_LAG, false,
                       reinterpret_cast<hipStream_t>(stream));
 }
 

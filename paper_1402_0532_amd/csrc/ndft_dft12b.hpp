@@ -16,11 +16,13 @@
 // (L >= 8). The pad after every 8 entries spreads the strided writes of the first passes
 // over the banks; the odd row stride spreads the fill, whose lanes run across transforms.
 //
-// SIGNS: the same DFT of the exact lag signs, D(l, p) = sum_i W^{ip} csgn(z_l[i]), which is
-// the twiddle half of the Eq. (12a) sign-split form (see ndft_signsplit.hpp): the FP32
-// form of that surface takes it from here instead of the matrix cores. Bin p = 0 is left
-// out there (the twiddle-sign kernel sums base 0 whole), and the result is added to the
-// surface the reduction of the other half wrote.
+// SRC selects what is transformed: DFT_LAG the lag products (the Eq. (12b) surface);
+// DFT_SIGNS their exact signs, D(l, p) = sum_i W^{ip} csgn(z_l[i]), the twiddle half of the
+// Eq. (12a) sign-split form (see ndft_signsplit.hpp), which its FP32 form takes from here
+// instead of the matrix cores; DFT_LIN_SIGNS the exact signs of the ordinary lag product
+// s conj(r), the same half of the Eq. (12c) surface. For the halves, bin p = 0 is left out
+// (the twiddle-sign kernel sums base 0 whole) and the result is added to the surface the
+// reduction of the other half wrote.
 //
 // FP32 throughout; twiddles come from the two-level table (exact 0 / +-1 at quadrant
 // points, a few ulp elsewhere), the FFT's inner twiddles as powers of one table entry.
@@ -33,6 +35,7 @@ namespace ndft {
 constexpr int kDftTile = 8192;    // complex samples per work-group
 constexpr int kDftThreads = 512;
 constexpr int kDftMaxLog = 9;     // L <= 512
+constexpr int DFT_LAG = 0, DFT_SIGNS = 1, DFT_LIN_SIGNS = 2;
 
 struct Dft12bParams {
     const float2 *s, *r;  // complex64 inputs, n samples each
@@ -186,7 +189,7 @@ __device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, cons
 // butterfly (b, i) loads its R samples t = i + r L / R of transform b straight from the
 // inputs, forms their lag products and writes the R-point DFT to x[b][i R + r]. Lanes run
 // over b first, so a wave's loads are runs of consecutive samples.
-template <int LB, bool SIGNS>
+template <int LB, int SRC>
 __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P, int m0, int mb, int d, int tid)
 {
     constexpr int L = 1 << LB, S = dft_row_stride<LB>();
@@ -223,8 +226,16 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
         float2 u[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const Lag z = lag_product(sv[c][r], rv[c][r]);
-            u[r] = SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
+            if constexpr (SRC == DFT_LIN_SIGNS) {
+                // s conj(r) in FP64: both FP32 x FP32 products are exact there, so one
+                // rounding of their sum keeps the sign
+                const double sx = sv[c][r].x, sy = sv[c][r].y, rx = rv[c][r].x, ry = rv[c][r].y;
+                const double zr = fma(sx, rx, sy * ry), zi = fma(sy, rx, -(sx * ry));
+                u[r] = make_float2((float)((zr > 0.0) - (zr < 0.0)), (float)((zi > 0.0) - (zi < 0.0)));
+            } else {
+                const Lag z = lag_product(sv[c][r], rv[c][r]);
+                u[r] = SRC == DFT_SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
+            }
         }
         if constexpr (R > 1) small_dft<R>(u);
 #pragma unroll
@@ -233,7 +244,7 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
 }
 
 // Grid: x = phase group (MB phases), y strides over the delays. Dynamic LDS: the table.
-template <int LB, bool SIGNS>
+template <int LB, int SRC>
 __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
 {
     constexpr int L = 1 << LB, S = dft_row_stride<LB>();
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
     for (int l = blockIdx.y; l < P.n_tau; l += gridDim.y) {
         const int d = P.tau0 + l;
         // lag products of samples m0 + j + M t (j < mb, t < L), transformed into X[j]
-        fill_first_pass<LB, SIGNS>(X, P, m0, mb, d, tid);
+        fill_first_pass<LB, SRC>(X, P, m0, mb, d, tid);
         __syncthreads(); // also orders the table build before its first use
         constexpr int LB0 = LB >= 3 ? 3 : LB; // bits of the first pass
         fft_passes<LB, LB - LB0>(X, mb, 1 << LB0, n, coarse, fine, P.tb, tid);
@@ -274,7 +285,7 @@ __global__ __launch_bounds__(kDftThreads) void dft12b_kernel(Dft12bParams P)
                 acc.y = fmaf(w.x, y.y, fmaf(w.y, y.x, acc.y));
                 w = cmulf(w, step);
             }
-            if (SIGNS && p == 0) acc = make_float2(0.0f, 0.0f);
+            if (SRC != DFT_LAG && p == 0) acc = make_float2(0.0f, 0.0f);
             if (P.accumulate) acc = caddf(acc, dst[q]);
             dst[q] = acc;
         }

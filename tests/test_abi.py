@@ -140,10 +140,8 @@ def test_caf12c_precisions_and_workspace():
     assert lib.ndft_caf12c(None, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == INVAL
     assert lib.ndft_caf12c(odd, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == INVAL
     assert lib.ndft_caf12c(p, p, 16, 0, 4, 0, 4, p, 7, p, 4096, None) == INVAL
-    # only the sign-split forms compute Eq. (12c): FP32 has none
-    assert lib.ndft_caf12c(p, p, 16, 0, 4, 0, 4, p, 0, p, 4096, None) == UNSUPPORTED
-    assert lib.ndft_caf12c_workspace(16, 0, 4, 0, 4, 0) == 0
-    for prec in (1, 2):
+    # only the sign-split forms compute Eq. (12c); every precision has one
+    for prec in (0, 1, 2):
         need = lib.ndft_caf12c_workspace(65536, 0, 1024, -256, 512, prec)
         assert need > 0
         assert lib.ndft_caf12c(p, p, 65536, 0, 1024, -256, 512, p, prec, None, 0, None) == WORKSPACE

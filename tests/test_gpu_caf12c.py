@@ -1,8 +1,9 @@
 """GPU parity of the Eq. (12c) surface (ndft_caf12c) against the FP64 oracle.
 
 Eq. (12c): the ordinary lag product s[i] conj(r[i - d]) (Eq. (11)), then the Eq. (6)
-operator with the twiddle W^{ip}. Only the sign-split forms compute it, so every
-sign-split plan of both precisions is forced here (ndft_set_plan) over shapes that reach
+operator with the twiddle W^{ip}. Only the sign-split forms compute it (split-BF16 and
+FP8 with the twiddle half on the matrix cores, FP32 with it as an FFT of the exact lag
+signs), so every sign-split plan of the three precisions is forced here (ndft_set_plan) over shapes that reach
 their code paths, plus the built-in choice at the N = 65536 surface on sampled rows.
 Data include lag products whose real part is a tiny exact value (+-2^-46) that FP32
 arithmetic would round to 0: the exact lag sign then decides a whole twiddle term.
@@ -16,8 +17,8 @@ import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {1: 1e-4, 2: 1e-4}
-SPLIT_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_")
+TOL = {0: 1e-5, 1: 1e-4, 2: 1e-4}
+SPLIT_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_", "fp32s_")
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +28,7 @@ def nd():
     import paper_1402_0532_amd as m
 
     yield m
-    for p in (1, 2):
+    for p in (0, 1, 2):
         m.set_plan(p, -1, 0)
 
 
@@ -96,7 +97,7 @@ def split_plans():
     import paper_1402_0532_amd as m
 
     try:
-        return [(p, k) for p in (1, 2) for k in range(m.plan_count(p))
+        return [(p, k) for p in (0, 1, 2) for k in range(m.plan_count(p))
                 if m.plan_name(p, k).startswith(SPLIT_PREFIXES)]
     except Exception:  # no library: the module fixture skips
         return [(1, 0)]
@@ -116,7 +117,7 @@ def test_caf12c_plan_vs_oracle(nd, orc, prec, plan, shape):
     assert rel_err(A, Ao, sc) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("shape", SHAPES[:5], ids=[f"n{s[0]}_{s[6]}" for s in SHAPES[:5]])
 def test_caf12c_builtin_choice(nd, orc, prec, shape):
     n, tau0, n_tau, p0, n_dop, _, kind = shape
@@ -126,11 +127,9 @@ def test_caf12c_builtin_choice(nd, orc, prec, shape):
     assert rel_err(A, Ao, sc) <= TOL[prec]
 
 
-def test_caf12c_needs_a_split_precision(nd):
-    s, r = synth.random_pair(256, seed=3)
-    with pytest.raises(RuntimeError, match="UNSUPPORTED"):
-        nd.caf12c(dev(s), dev(r), 0, 8, -4, 8, prec=0)
-    assert nd._lib.load().ndft_caf12c_workspace(256, 0, 8, -4, 8, 0) == 0
+def test_caf12c_fp32_takes_the_fft_plan(nd):
+    plan, ks = nd.get_plan(0, 65536, 1024, -256, 512)
+    assert nd.plan_name(0, plan).startswith("fp32s_") and ks == 0
 
 
 def test_caf12c_differs_from_caf12a(nd, orc):
@@ -144,7 +143,7 @@ def test_caf12c_differs_from_caf12a(nd, orc):
     assert rel_err(A12a, Ao, sc) > 1e-2
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_caf12c_n65536_sampled_rows(nd, orc, prec):
     c = synth.config3()
     rng = np.random.default_rng(34)

@@ -265,3 +265,45 @@ def test_invalid_arguments_raise(nd):
                         prec=nd.FP8)
     with pytest.raises(TypeError):
         nd.caf(s.real.contiguous(), s, 0, 4, 0, 4)
+
+
+@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b"])
+def test_fft_paths_graph_replay(nd, which):
+    """The FFT-based paths (the FP32 sign-split surface: twiddle-sign kernel, reduction,
+    then the FFT of the exact lag signs added on top; the Eq. (12b) surface: FFT kernel and
+    the reduction of its partial surfaces) captured into a graph: every replay, with
+    unrelated eager work and a scrambled workspace between, equals the eager call."""
+    n, tau0, n_tau, p0, n_dop = 16384, 3, 100, -64, 128
+    s, r = synth.random_pair(n, seed=22, zeros=0.02)
+    S, R = dev(s), dev(r)
+    if which == "fp32_fft_half":
+        plan, _ = nd.get_plan(0, n, n_tau, p0, n_dop)
+        assert nd.plan_name(0, plan).startswith("fp32s_")
+        nbytes = nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
+        call = lambda out, ws: nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=0, out=out, ws=ws)
+    else:
+        nbytes = nd.caf12b_workspace_bytes(n, tau0, n_tau, p0, n_dop)
+        call = lambda out, ws: nd.caf12b(S, R, tau0, n_tau, p0, n_dop, out=out, ws=ws)
+    assert nbytes > 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    eager = call(None, ws)
+    out = torch.zeros_like(eager)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        call(out, ws)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        call(out, ws)
+    for rep in range(3):
+        out.fill_(1.0)
+        ws.fill_(255)
+        junk = torch.randn(1 << 20, device="cuda") * 2
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        del junk

@@ -227,11 +227,25 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (SRC == DFT_LIN_SIGNS) {
-                // s conj(r) in FP64: both FP32 x FP32 products are exact there, so one
-                // rounding of their sum keeps the sign
-                const double sx = sv[c][r].x, sy = sv[c][r].y, rx = rv[c][r].x, ry = rv[c][r].y;
-                const double zr = fma(sx, rx, sy * ry), zi = fma(sy, rx, -(sx * ry));
-                u[r] = make_float2((float)((zr > 0.0) - (zr < 0.0)), (float)((zi > 0.0) - (zi < 0.0)));
+                // s conj(r) from FP32 products: the rounded sum carries the exact sign when it
+                // exceeds 2^-22 of the parts' magnitude (each product and the sum are off by
+                // at most 2^-24 of their size, or 2^-150 below the normal range, which the
+                // 2^-100 floor covers); a zero sample gives exact zeros; otherwise FP64, where
+                // both FP32 x FP32 products are exact and one rounding of their sum keeps
+                // the sign
+                const float2 a = sv[c][r], b = rv[c][r];
+                const float p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.y * b.x, p4 = a.x * b.y;
+                const float zr = p1 + p2, zi = p3 - p4;
+                const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
+                const bool zero = (a.x == 0.0f && a.y == 0.0f) || (b.x == 0.0f && b.y == 0.0f);
+                const bool sure = fabsf(zr) > 0x1p-22f * mr && mr >= 0x1p-100f && fabsf(zi) > 0x1p-22f * mi &&
+                                  mi >= 0x1p-100f;
+                u[r] = zero ? make_float2(0.0f, 0.0f) : make_float2(sgnf(zr), sgnf(zi));
+                if (!zero && !sure) {
+                    const double sx = a.x, sy = a.y, rx = b.x, ry = b.y;
+                    const double zr64 = fma(sx, rx, sy * ry), zi64 = fma(sy, rx, -(sx * ry));
+                    u[r] = make_float2((float)((zr64 > 0.0) - (zr64 < 0.0)), (float)((zi64 > 0.0) - (zi64 < 0.0)));
+                }
             } else {
                 const Lag z = lag_product(sv[c][r], rv[c][r]);
                 u[r] = SRC == DFT_SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);

@@ -181,3 +181,49 @@ def random_pair(n: int, seed: int, zeros: float = 0.0, integer: bool = False):
             a.real[mr] = 0.0
             a.imag[mi] = 0.0
     return c64(s), c64(r)
+
+
+# ----------------------------------------------------------------------------------
+# Robustness scenes: targets and clutter under AWGN or eps-contaminated Gaussian noise
+# ----------------------------------------------------------------------------------
+
+def eps_contaminated(rng: np.random.Generator, shape, eps: float, sigma1: float,
+                     sigma2: float) -> np.ndarray:
+    """Complex noise whose real and imaginary parts are drawn independently from
+    N(0, sigma1^2) with probability eps and from N(0, sigma2^2) (the heavy tail) otherwise."""
+    shape = (shape,) if isinstance(shape, int) else tuple(shape)
+    pick = rng.uniform(size=(2,) + shape) < eps
+    g = rng.standard_normal((2,) + shape)
+    parts = np.where(pick, sigma1 * g, sigma2 * g)
+    return parts[0] + 1j * parts[1]
+
+
+# scene -> (targets [(delay, doppler_bin, amp_db)], clutter [(delay, amp_db)]); amplitudes
+# relative to the unit-variance reference, clutter at zero Doppler
+ROBUST_SCENES = {
+    "2 targets 1 clutter": ([(37, 11, -6.0), (80, -23, -8.0)], [(5, 0.0)]),
+    "4 targets 2 clutters": ([(37, 11, -6.0), (80, -23, -8.0), (20, 40, -6.0), (101, -7, -10.0)],
+                             [(5, 0.0), (12, -3.0)]),
+    "1 target 3 clutters": ([(64, 17, -6.0)], [(3, 0.0), (9, -3.0), (15, -6.0)]),
+}
+# noise -> ("awgn", noise_db) or ("eps", eps, sigma1, sigma2)
+ROBUST_NOISES = {
+    "awgn -10 dB": ("awgn", -10.0),
+    "eps 0.9 / 0.25 / 10": ("eps", 0.9, 0.25, 10.0),
+    "eps 0.8 / 0.5 / 20": ("eps", 0.8, 0.5, 20.0),
+}
+
+
+def robustness_pair(scene: str, noise: str, n: int = 8192, seed: int = 0):
+    """(surveillance, reference) complex64 for one scene and noise of the robustness runs:
+    low-pass reference (noise free), delayed / Doppler-shifted copies for the objects."""
+    rng = rng_for(6, seed)
+    r = lowpass_reference(rng, n)
+    targets, clutter = ROBUST_SCENES[scene]
+    s = surveillance(r, rng, targets, clutter, noise_db=-300.0)
+    kind = ROBUST_NOISES[noise]
+    if kind[0] == "awgn":
+        s = s + complex_gaussian(rng, n, math.sqrt(10.0 ** (kind[1] / 10.0)))
+    else:
+        s = s + eps_contaminated(rng, n, *kind[1:])
+    return c64(s), c64(r)

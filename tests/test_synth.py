@@ -2,6 +2,7 @@
 import hashlib
 
 import numpy as np
+import pytest
 
 import synth
 
@@ -53,3 +54,23 @@ def test_config_shapes():
     for c in cp:
         assert 1024 <= c["n"] <= 32768 and 128 <= c["n_tau"] <= 512
         assert c["n_dop"] == 2 * (c["n"] // 16)
+
+
+def test_eps_contaminated_mixture_statistics():
+    rng = np.random.default_rng(5)
+    x = synth.eps_contaminated(rng, 400000, 0.9, 0.25, 10.0)
+    # per part: variance eps sigma1^2 + (1 - eps) sigma2^2, and the share of |part| > 2
+    # (beyond 8 sigma1) is about the heavy-tail probability times P(|N(0, 100)| > 2)
+    var = 0.9 * 0.25 ** 2 + 0.1 * 100.0
+    assert np.var(x.real) == pytest.approx(var, rel=0.03)
+    assert np.var(x.imag) == pytest.approx(var, rel=0.03)
+    frac = np.mean(np.abs(x.real) > 2.0)
+    assert frac == pytest.approx(0.1 * 0.8415, rel=0.05)
+
+
+def test_robustness_pairs_are_seeded():
+    for scene in synth.ROBUST_SCENES:
+        for noise in synth.ROBUST_NOISES:
+            s1, r1 = synth.robustness_pair(scene, noise, n=1024)
+            s2, r2 = synth.robustness_pair(scene, noise, n=1024)
+            assert s1.dtype == np.complex64 and np.array_equal(s1, s2) and np.array_equal(r1, r2)

@@ -836,6 +836,7 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
             }
     });
     if (g_dft_attr_err != hipSuccess) return NDFT_E_HIP;
+    if (L.n_mg > 1 && cdiv((long long)n_tau * n_dop, 256) > (long long)UINT32_MAX) return NDFT_E_INVAL;
     Dft12bParams P;
     std::memset(&P, 0, sizeof(P));
     P.s = surv;

@@ -62,6 +62,10 @@ def _load():
         lib.oracle_caf_lin.restype = ctypes.c_int
         lib.oracle_caf_dft.argtypes = [P, P, I, I, I, I, I, P, I, P, P]
         lib.oracle_caf_dft.restype = ctypes.c_int
+        lib.oracle_nfft.argtypes = [P, I, I, P]
+        lib.oracle_nfft.restype = ctypes.c_int
+        lib.oracle_nfft32.argtypes = [P, I, I, P]
+        lib.oracle_nfft32.restype = ctypes.c_int
         lib.oracle_caf_grad.argtypes = [P, P, I, I, I, I, I, P, P, P]
         lib.oracle_caf_grad.restype = ctypes.c_int
         lib.oracle_caf_loss.argtypes = [P, P, I, I, I, I, I, P]
@@ -176,6 +180,25 @@ def caf(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
     if rc:
         raise ValueError("oracle_caf: invalid arguments")
     return A, sc
+
+
+def nfft(x):
+    """NFFT of Section 3 (radix-2 DIT, twiddle products by Eq. (6)) of each row of x
+    [batch][n] (n a power of two), FP64."""
+    x = np.atleast_2d(_c128(x))
+    X = np.zeros_like(x)
+    if _load().oracle_nfft(_ptr(x), x.shape[0], x.shape[1], _ptr(X)):
+        raise ValueError("oracle_nfft: n must be a power of two")
+    return X
+
+
+def nfft32(x):
+    """The same recursion in FP32 arithmetic (complex64 in and out)."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex64)
+    X = np.zeros_like(x)
+    if _load().oracle_nfft32(_ptr(x), x.shape[0], x.shape[1], _ptr(X)):
+        raise ValueError("oracle_nfft32: n must be a power of two")
+    return X
 
 
 def _surface(fn, s, r, tau0, n_tau, p0, n_dop, rows):

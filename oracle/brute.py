@@ -144,3 +144,20 @@ def caf12b(s: list, r: list, tau0: int, n_tau: int, p0: int, n_dop: int) -> list
             row.append(acc)
         rows.append(row)
     return rows
+
+
+def nfft(x: list) -> list:
+    """Section 3 NFFT: radix-2 decimation in time down to single samples; each butterfly
+    X[k] = E[k] + cop(O[k], W_n^k), X[k + n/2] = E[k] - cop(O[k], W_n^k)."""
+    n = len(x)
+    if n == 1:
+        return [(Fraction(float(x[0].real)), Fraction(float(x[0].imag)))]
+    E = nfft(x[0::2])
+    O = nfft(x[1::2])
+    out = [None] * n
+    for k in range(n // 2):
+        wr, wi = twiddle(k, n)
+        t = cop(O[k], (Fraction(wr), Fraction(wi)))
+        out[k] = (E[k][0] + t[0], E[k][1] + t[1])
+        out[k + n // 2] = (E[k][0] - t[0], E[k][1] - t[1])
+    return out

@@ -20,6 +20,8 @@
  *              the lag product of the surveillance sample and the conjugated reference
  *              sample (the conjugate is the one written in Eq. (11)), then one NDFT per
  *              range bin. Reference samples before the start of the record are zero.
+ *   NFFT       Section 3, Eq. (10): radix-2 decimation in time with every butterfly's
+ *              twiddle product replaced by the operator of Eq. (6) (FP64, and FP32).
  *   CAF (12b)  Eq. (12b): the lag product of Eq. (6), then the ordinary DFT (complex
  *              products with W^{ip}).
  *   CAF (12c)  Eq. (12c): the ordinary lag product s[i] conj(r[i-d]) (Eq. (11)), then
@@ -564,4 +566,103 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------------ */
+/* NFFT, Section 3 (Eq. (10)): radix-2 decimation in time, recursively down to     */
+/* single samples, with every twiddle product of a butterfly replaced by the       */
+/* operator of Eq. (6): X[k] = E[k] + cop(O[k], W_n^k), X[k + n/2] = E[k] -        */
+/* cop(O[k], W_n^k), E / O the NFFTs of the even / odd samples (W_n^0 = 1 included: */
+/* no ordinary multiplication is left). The sign of every intermediate decides a    */
+/* jump of the result, so besides FP64 the same recursion is given in FP32 (the     */
+/* GPU's precision) with twiddles rounded once from FP64.                           */
+/* ------------------------------------------------------------------------------ */
+static void nfft64_rec(const double *x, int64_t n, int64_t stride, int64_t N, double *X, double *tmp)
+{
+    if (n == 1) {
+        X[0] = x[0];
+        X[1] = x[1];
+        return;
+    }
+    const int64_t h = n / 2;
+    double *E = tmp, *O = tmp + 2 * h, *sub = tmp + 4 * h;
+    nfft64_rec(x, h, 2 * stride, N, E, sub);
+    nfft64_rec(x + 2 * stride, h, 2 * stride, N, O, sub);
+    for (int64_t k = 0; k < h; ++k) {
+        double w[2], t[2];
+        oracle_twiddle(k * (N / n), N, w);
+        oracle_cop(O + 2 * k, w, t);
+        X[2 * k] = E[2 * k] + t[0];
+        X[2 * k + 1] = E[2 * k + 1] + t[1];
+        X[2 * (k + h)] = E[2 * k] - t[0];
+        X[2 * (k + h) + 1] = E[2 * k + 1] - t[1];
+    }
+}
+
+static float rop32(float a, float b)
+{
+    const int s = sign_of_product((double)a, (double)b);
+    if (s == 0) return 0.0f;
+    const float m = fabsf(a) + fabsf(b);
+    return s > 0 ? m : -m;
+}
+
+static void nfft32_rec(const float *x, int64_t n, int64_t stride, int64_t N, const float *tw, float *X, float *tmp)
+{
+    if (n == 1) {
+        X[0] = x[0];
+        X[1] = x[1];
+        return;
+    }
+    const int64_t h = n / 2;
+    float *E = tmp, *O = tmp + 2 * h, *sub = tmp + 4 * h;
+    nfft32_rec(x, h, 2 * stride, N, tw, E, sub);
+    nfft32_rec(x + 2 * stride, h, 2 * stride, N, tw, O, sub);
+    for (int64_t k = 0; k < h; ++k) {
+        const float *w = tw + 2 * (k * (N / n));
+        const float orr = O[2 * k], oi = O[2 * k + 1];
+        const float tr = rop32(orr, w[0]) - rop32(oi, w[1]);
+        const float ti = rop32(oi, w[0]) + rop32(w[1], orr);
+        X[2 * k] = E[2 * k] + tr;
+        X[2 * k + 1] = E[2 * k + 1] + ti;
+        X[2 * (k + h)] = E[2 * k] - tr;
+        X[2 * (k + h) + 1] = E[2 * k + 1] - ti;
+    }
+}
+
+static int is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+/* x, X: [batch][n][2] FP64; n a power of two. */
+int oracle_nfft(const double *x, int64_t batch, int64_t n, double *X)
+{
+    if (!is_pow2(n) || batch < 0) return 1;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t b = 0; b < batch; ++b) {
+        double *tmp = (double *)malloc(sizeof(double) * 8 * (size_t)n + 16);
+        nfft64_rec(x + 2 * b * n, n, 1, n, X + 2 * b * n, tmp);
+        free(tmp);
+    }
+    return 0;
+}
+
+/* The same in FP32: x, X [batch][n][2] float; twiddle W_n^m = e^{-j 2 pi m / n} rounded
+ * to FP32 from the FP64 values of oracle_twiddle (exact at the quadrant points). */
+int oracle_nfft32(const float *x, int64_t batch, int64_t n, float *X)
+{
+    if (!is_pow2(n) || batch < 0) return 1;
+    float *tw = (float *)malloc(sizeof(float) * 2 * (size_t)n);
+    for (int64_t m = 0; m < n; ++m) {
+        double w[2];
+        oracle_twiddle(m, n, w);
+        tw[2 * m] = (float)w[0];
+        tw[2 * m + 1] = (float)w[1];
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t b = 0; b < batch; ++b) {
+        float *tmp = (float *)malloc(sizeof(float) * 8 * (size_t)n + 16);
+        nfft32_rec(x + 2 * b * n, n, 1, n, tw, X + 2 * b * n, tmp);
+        free(tmp);
+    }
+    free(tw);
+    return 0;
 }

@@ -484,3 +484,55 @@ def test_caf12b_invariants(orc):
     assert Ad[0, 0].imag == 0.0
     want = 2.0 * np.sum(np.abs(s64.real) + np.abs(s64.imag))
     assert Ad[0, 0].real == pytest.approx(want, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------------
+# P-12: the NFFT of Section 3 (radix-2 DIT, twiddle products by Eq. (6)), FP64 and FP32.
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
+def test_brute_force_nfft(orc, n):
+    rng = np.random.default_rng(n + 70)
+    for x in (rng.standard_normal(n) + 1j * rng.standard_normal(n),
+              (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(complex)):
+        X = orc.nfft(x)[0]
+        B = np.array([complex(float(a), float(b)) for a, b in brute.nfft(list(x))])
+        np.testing.assert_allclose(X, B, rtol=0, atol=1e-12 * max(1.0, np.abs(B).max()))
+
+
+def test_nfft_two_and_four_point_by_hand(orc):
+    # N = 2: X = x0 +- 1 (x) x1, and 1 (x) x = sgn(x_r)(1 + |x_r|) + j sgn(x_i)(1 + |x_i|)
+    x = np.array([2.0 - 1.0j, -3.0 + 0.5j])
+    X = orc.nfft(x)[0]
+    t = -4.0 + 1.5j
+    np.testing.assert_array_equal(X, [x[0] + t, x[0] - t])
+    # N = 4, x = (1, j, 0, 2), by hand: E = NFFT(1, 0) = (1, 1) since 1 (x) 0 = 0;
+    # O = NFFT(j, 2) = (j + 3, j - 3) since 1 (x) 2 = 3. Then with W_4^0 = 1:
+    # (3 + j) (x) 1 = (3 (x) 1 - 1 (x) 0) + j (1 (x) 1 + 0 (x) 3) = 4 + 2j, and with W_4^1 = -j:
+    # (-3 + j) (x) (-j) = ((-3) (x) 0 - 1 (x) (-1)) + j (1 (x) 0 + (-1) (x) (-3)) = 2 + 4j.
+    x = np.array([1.0, 1.0j, 0.0, 2.0])
+    X = orc.nfft(x)[0]
+    np.testing.assert_array_equal(X, [1 + (4 + 2j), 1 + (2 + 4j), 1 - (4 + 2j), 1 - (2 + 4j)])
+
+
+@pytest.mark.parametrize("n", [8, 64, 1024])
+def test_nfft_invariants_fp64_and_fp32(orc, n):
+    rng = np.random.default_rng(n)
+    x = (rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))).astype(np.complex64)
+    for f in (orc.nfft, orc.nfft32):
+        X = f(x)
+        np.testing.assert_array_equal(f(-x), -X)
+        np.testing.assert_array_equal(f((1j * x).astype(np.complex64)), (1j * X).astype(X.dtype))
+        assert np.all(f(np.zeros_like(x)) == 0)
+    # FP32 follows FP64 up to rounding (no intermediate of these inputs sits within FP32
+    # rounding of zero)
+    X64, X32 = orc.nfft(x), orc.nfft32(x)
+    assert np.max(np.abs(X64 - X32)) <= 1e-5 * np.abs(X64).max()
+
+
+def test_nfft_is_not_the_ndft(orc):
+    # the operator is not linear, so the radix-2 regrouping changes the values (Section 3)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    X1, _ = orc.ndft(x[None])
+    X2 = orc.nfft(x)
+    assert np.max(np.abs(X1 - X2)) > 1.0

@@ -194,6 +194,29 @@ def bench_other_surfaces(nd, synth, torch, args):
     return out_all
 
 
+def bench_nfft(nd, torch, args):
+    """Batched NFFT (Section 3): 4096 rows of N = 8192, one work-group per row in LDS."""
+    rows, n = 4096, 8192
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.complex(torch.randn(rows, n, device="cuda", generator=g),
+                      torch.randn(rows, n, device="cuda", generator=g))
+    out = torch.empty_like(x)
+    for _ in range(max(3, args.warmup // 10)):
+        nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
+    torch.cuda.synchronize()
+    reps = max(5, args.steps)
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    hbm = 16.0 * rows * n  # read the rows, write the transforms (complex64)
+    return {"workload": "4096 rows x N=8192", "ms": ms, "transforms_per_s": rows / (ms * 1e-3),
+            "hbm_gb_per_s": hbm / (ms * 1e-3) / 1e9, "hbm_frac_of_8tbs": hbm / (ms * 1e-3) / 8e12}
+
+
 def object_margin(A, objects, guard=3):
     """Detection on a surface magnitude: every object cell (delay row, bin column) against
     the largest magnitude outside +-guard cells of all objects. margin_db =
@@ -402,6 +425,7 @@ def main():
         extras["adjoint"] = bench_adjoint(nd, synth, torch, args)
         extras.update(bench_other_surfaces(nd, synth, torch, args))
         extras["robustness"] = bench_robustness(nd, synth, torch, args)
+        extras["nfft"] = bench_nfft(nd, torch, args)
 
     main_res = results[args.form]
     line = {

@@ -95,6 +95,19 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
+ * NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT with the twiddle
+ * product of every butterfly replaced by the operator of Eq. (6),
+ *   X[k] = E[k] + O[k] (x) W_n^k,  X[k + n/2] = E[k] - O[k] (x) W_n^k,
+ * E / O the NFFTs of the even / odd samples, recursively down to single samples
+ * (W_n^0 = 1 included). Its values differ from the NDFT of Eq. (7) (the operator is
+ * not linear). FP32, evaluated butterfly by butterfly in the recursion's operations;
+ * twiddles are e^{-j 2 pi m / n} rounded once to FP32, exact at the quadrant points.
+ * x, X: [batch][n] complex64 device pointers (X may not alias x); n a power of two,
+ * 1 <= n <= 8192; batch >= 0. No workspace. Returns NDFT_E_INVAL otherwise.
+ * ------------------------------------------------------------------------------- */
+ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------------------
  * The Eq. (12b) surface of Section 4: the lag product of Eq. (6), then the ordinary DFT,
  *   A[l][q] = sum_{i=0}^{N-1} ( s[i] (x) conj(r[i - d]) ) W^{i p mod N},
  * with d, p, the zero reference before the record, the layout and the limits of

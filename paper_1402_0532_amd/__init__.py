@@ -19,7 +19,7 @@ FP8 = 2
 PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
 
 __all__ = [
-    "FP32", "BF16X2", "FP8", "forward", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
+    "FP32", "BF16X2", "FP8", "forward", "nfft", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
     "pack_batch",
     "NDFTCaf", "dbg_signs", "plan_count", "plan_name", "set_plan", "get_plan",
     "prof_enable", "prof_read", "version",
@@ -97,6 +97,19 @@ def caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop:
     st = lib.ndft_caf(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
                       p, _ptr(ws), nbytes, _stream_handle())
     _lib.check(st, "ndft_caf")
+    return out
+
+
+def nfft(x: torch.Tensor) -> torch.Tensor:
+    """NFFT of Section 3 (radix-2 DIT, twiddle products by Eq. (6)) of each row of
+    x [batch, n] complex64, n a power of two up to 8192; FP32."""
+    lib = _lib.load()
+    if x.dim() == 1:
+        return nfft(x[None])[0]
+    _check_c64(x, "x", 2)
+    batch, n = x.shape
+    out = torch.empty_like(x)
+    _lib.check(lib.ndft_nfft(_ptr(x), _ptr(out), batch, n, _stream_handle()), "ndft_nfft")
     return out
 
 

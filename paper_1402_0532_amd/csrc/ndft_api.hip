@@ -19,6 +19,7 @@
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
 #include "ndft_dft12b.hpp"
+#include "ndft_nfft.hpp"
 #include "ndft_signsplit.hpp"
 #include "ndft_surface_bf16.hpp"
 
@@ -1193,6 +1194,30 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     return launch_dft(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
                       n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), ws, DFT_LAG, false,
                       reinterpret_cast<hipStream_t>(stream));
+}
+
+ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, void *stream)
+{
+    if (n < 1 || n > kNfftMaxN || (n & (n - 1)) != 0 || batch < 0) return NDFT_E_INVAL;
+    if (batch == 0) return NDFT_OK;
+    if (!x || !X || !aligned(x, 8) || !aligned(X, 8)) return NDFT_E_INVAL;
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+        attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&nfft_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(kNfftMaxN + kNfftMaxN / 2) * (int)sizeof(float2));
+    });
+    if (attr != hipSuccess) return NDFT_E_HIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t shmem = (size_t)(n + n / 2) * sizeof(float2);
+    // rows loop inside: at most about eight work-groups per compute unit
+    const int64_t grid = std::min<int64_t>(batch, 8LL * device_cu_count());
+    ProfScope prof(s);
+    hipLaunchKernelGGL(nfft_kernel, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s,
+                       reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(X), (long long)batch, (int)n);
+    prof.stop();
+    return check_launch();
 }
 
 ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,

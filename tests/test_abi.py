@@ -164,3 +164,13 @@ def test_caf12b_arguments_and_workspace():
     # N = 65536: 128 phases in groups of 16, eight partial surfaces of 1024 x 512
     assert lib.ndft_caf12b_workspace(65536, 0, 1024, -256, 512, 0) == 8 * 1024 * 512 * 8
     assert lib.ndft_caf12b(p, p, 65536, 0, 1024, -256, 512, p, 0, None, 0, None) == WORKSPACE
+
+
+def test_nfft_arguments():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    for n in (0, 3, 12, 16384, -4):
+        assert lib.ndft_nfft(p, p, 1, n, None) == INVAL
+    assert lib.ndft_nfft(p, p, -1, 8, None) == INVAL
+    assert lib.ndft_nfft(None, p, 1, 8, None) == INVAL
+    assert lib.ndft_nfft(p, p, 0, 8, None) == 0  # nothing to do

@@ -195,26 +195,33 @@ def bench_other_surfaces(nd, synth, torch, args):
 
 
 def bench_nfft(nd, torch, args):
-    """Batched NFFT (Section 3): 4096 rows of N = 8192, one work-group per row in LDS."""
-    rows, n = 4096, 8192
-    g = torch.Generator(device="cuda").manual_seed(5)
-    x = torch.complex(torch.randn(rows, n, device="cuda", generator=g),
-                      torch.randn(rows, n, device="cuda", generator=g))
-    out = torch.empty_like(x)
-    for _ in range(max(3, args.warmup // 10)):
-        nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
-    torch.cuda.synchronize()
-    reps = max(5, args.steps)
-    e0, e1 = _events(torch)
-    e0.record()
-    for _ in range(reps):
-        nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    hbm = 16.0 * rows * n  # read the rows, write the transforms (complex64)
-    return {"workload": "4096 rows x N=8192", "ms": ms, "transforms_per_s": rows / (ms * 1e-3),
-            "hbm_gb_per_s": hbm / (ms * 1e-3) / 1e9, "hbm_frac_of_8tbs": hbm / (ms * 1e-3) / 8e12}
+    """Batched NFFT (Section 3): 32 Mi points as 4096 rows of N = 8192 (one row per
+    work-group) and as 131072 rows of N = 256 (32 rows per work-group)."""
+    res = {}
+    lib = nd._lib.load()
+    for rows, n in ((4096, 8192), (131072, 256)):
+        g = torch.Generator(device="cuda").manual_seed(5)
+        x = torch.complex(torch.randn(rows, n, device="cuda", generator=g),
+                          torch.randn(rows, n, device="cuda", generator=g))
+        out = torch.empty_like(x)
+        run = lambda: nd._lib.check(lib.ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
+        for _ in range(max(3, args.warmup // 10)):
+            run()
+        torch.cuda.synchronize()
+        reps = max(5, args.steps)
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        hbm = 16.0 * rows * n  # read the rows, write the transforms (complex64)
+        res["%d x N=%d" % (rows, n)] = {"ms": ms, "transforms_per_s": rows / (ms * 1e-3),
+                                         "hbm_gb_per_s": hbm / (ms * 1e-3) / 1e9,
+                                         "hbm_frac_of_8tbs": hbm / (ms * 1e-3) / 8e12}
+        del x, out
+    return res
 
 
 def object_margin(A, objects, guard=3):

@@ -1210,12 +1210,15 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
     });
     if (attr != hipSuccess) return NDFT_E_HIP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const size_t shmem = (size_t)(n + n / 2) * sizeof(float2);
-    // rows loop inside: at most about eight work-groups per compute unit
-    const int64_t grid = std::min<int64_t>(batch, 8LL * device_cu_count());
+    // 8192 / n rows per work-group at a time; the row groups loop inside, at most about
+    // eight work-groups per compute unit
+    const int rpb = (int)(kNfftMaxN / n);
+    const size_t shmem = ((size_t)rpb * n + n / 2) * sizeof(float2);
+    const int64_t grid = std::min<int64_t>(cdiv(batch, rpb), 8LL * device_cu_count());
     ProfScope prof(s);
     hipLaunchKernelGGL(nfft_kernel, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s,
-                       reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(X), (long long)batch, (int)n);
+                       reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(X), (long long)batch, (int)n,
+                       rpb);
     prof.stop();
     return check_launch();
 }

@@ -267,12 +267,13 @@ def test_invalid_arguments_raise(nd):
         nd.caf(s.real.contiguous(), s, 0, 4, 0, 4)
 
 
-@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b"])
+@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft"])
 def test_fft_paths_graph_replay(nd, which):
-    """The FFT-based paths (the FP32 sign-split surface: twiddle-sign kernel, reduction,
-    then the FFT of the exact lag signs added on top; the Eq. (12b) surface: FFT kernel and
-    the reduction of its partial surfaces) captured into a graph: every replay, with
-    unrelated eager work and a scrambled workspace between, equals the eager call."""
+    """The FFT-based paths (the FP32 sign-split surfaces of Eq. (12a) and (12c):
+    twiddle-sign kernel, reduction, then the FFT of the exact lag signs added on top; the
+    Eq. (12b) surface: FFT kernel and the reduction of its partial surfaces; the NFFT)
+    captured into a graph: every replay, with unrelated eager work and a scrambled
+    workspace between, equals the eager call."""
     n, tau0, n_tau, p0, n_dop = 16384, 3, 100, -64, 128
     s, r = synth.random_pair(n, seed=22, zeros=0.02)
     S, R = dev(s), dev(r)
@@ -281,9 +282,21 @@ def test_fft_paths_graph_replay(nd, which):
         assert nd.plan_name(0, plan).startswith("fp32s_")
         nbytes = nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
         call = lambda out, ws: nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=0, out=out, ws=ws)
-    else:
+    elif which == "caf12b":
         nbytes = nd.caf12b_workspace_bytes(n, tau0, n_tau, p0, n_dop)
         call = lambda out, ws: nd.caf12b(S, R, tau0, n_tau, p0, n_dop, out=out, ws=ws)
+    elif which == "caf12c_fp32":
+        nbytes = nd.caf12c_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
+        call = lambda out, ws: nd.caf12c(S, R, tau0, n_tau, p0, n_dop, prec=0, out=out, ws=ws)
+    else:
+        rows = dev(np.stack([s[:4096], r[:4096]] * 40))
+        nbytes = 1
+
+        def call(out, ws):
+            res = out if out is not None else torch.empty_like(rows)
+            nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(rows), nd._ptr(res), rows.shape[0], rows.shape[1],
+                                                   nd._stream_handle()))
+            return res
     assert nbytes > 0
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     eager = call(None, ws)

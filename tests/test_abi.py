@@ -174,3 +174,21 @@ def test_nfft_arguments():
     assert lib.ndft_nfft(p, p, -1, 8, None) == INVAL
     assert lib.ndft_nfft(None, p, 1, 8, None) == INVAL
     assert lib.ndft_nfft(p, p, 0, 8, None) == 0  # nothing to do
+
+
+def test_fp32_plan_choice_rules():
+    # the FP32 sign-split plan (twiddle half by FFT) is the built-in choice for narrow
+    # Doppler windows when N has a power-of-two factor of at least 64, else a contraction
+    lib = _lib.load()
+    plan = ctypes.c_int32()
+    ks = ctypes.c_int32()
+
+    def name(n, n_cols, p0, n_bins):
+        assert lib.ndft_get_plan(0, n, n_cols, p0, n_bins, ctypes.byref(plan), ctypes.byref(ks)) == 0
+        return lib.ndft_plan_name(0, plan.value).decode()
+
+    assert name(65536, 1024, -256, 512).startswith("fp32s_") and ks.value == 0
+    assert name(16384, 100, -64, 128).startswith("fp32s_")
+    assert not name(4096, 256, 0, 4096).startswith("fp32s_")   # bases up to N / 2
+    assert not name(65540, 3, -2, 5).startswith("fp32s_")      # N = 4 x odd
+    assert not name(1000, 64, -3, 7).startswith("fp32s_")      # N = 8 x 125

@@ -23,7 +23,8 @@
  *     only enqueue work on it and never synchronize; results are visible after the
  *     stream is synchronized. All calls are asynchronous and thread-safe.
  *   - Arguments are validated on the host before anything is enqueued; a rejected
- *     call returns NDFT_E_INVAL (or NDFT_E_WORKSPACE) and touches no memory.
+ *     call returns NDFT_E_INVAL, NDFT_E_UNSUPPORTED or NDFT_E_WORKSPACE and touches no
+ *     memory. A workspace query returns 0 for a call that would be rejected.
  *   - Inputs must be finite, with magnitudes below 1e30.
  *   - Doppler / frequency bins are taken mod N, so negative starts are allowed.
  *   - Results are deterministic for a fixed plan: no floating-point atomics.
@@ -206,6 +207,28 @@ ndft_status ndft_caf_backward(const ndft_c64 *surv, const ndft_c64 *ref, int64_t
 ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
                            int64_t n_tau, int64_t p0, int64_t n_dop, int8_t *tw_sign,
                            int8_t *lag_sign, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Test hook: the sign operands of the sign-split plans, taken from the hot path itself.
+ * With a (x) b = csgn(a) b + a csgn(b) (Eq. (1)-(2) applied to the four real operators of
+ * Eq. (6)), each surface cell splits into T = sum_i csgn(W^{ip}) z_l[i] (twiddle signs
+ * against lag values) and D = sum_i W^{ip} csgn(z_l[i]) (twiddles against lag signs).
+ * This call picks the plan that ndft_caf (lin = 0, z the Eq. (6) lag product) or
+ * ndft_caf12c (lin = 1, z = s conj(r), Eq. (11)) would pick for the same arguments, and
+ * runs that plan's lag kernel exactly as the surface call does, without the rest:
+ *   lag_sign[l][i][2] (int8, may be NULL): the exact lag signs (sign Re, sign Im) of
+ *       z_l[i] as the lag kernel encodes them for the matrix-core half (2-bit code words),
+ *       decoded; values in {-1, 0, 1} (2 would mark an invalid code);
+ *   T[l][q] (complex64, may be NULL): the lag kernel's own partial sums reduced alone,
+ *       i.e. T at every requested bin, except bins p = 0 mod n, which that kernel sums
+ *       whole (T + D, the twiddle there being 1).
+ * ws: the workspace of ndft_caf_workspace (lin = 0) or ndft_caf12c_workspace (lin = 1)
+ * for the same arguments. Returns NDFT_E_UNSUPPORTED when the chosen plan is not a
+ * sign-split plan (ndft_set_plan can force one). Limits and errors as ndft_caf.
+ * ------------------------------------------------------------------------------- */
+ndft_status ndft_dbg_split(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                           int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec, int32_t lin,
+                           int8_t *lag_sign, ndft_c64 *T, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * Tile plans (used by the autotuner). A plan is a tile shape of the contraction

@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
 __all__ = [
     "FP32", "BF16X2", "FP8", "forward", "nfft", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
     "pack_batch",
-    "NDFTCaf", "dbg_signs", "plan_count", "plan_name", "set_plan", "get_plan",
+    "NDFTCaf", "dbg_signs", "dbg_split", "plan_count", "plan_name", "set_plan", "get_plan",
     "prof_enable", "prof_read", "version",
 ]
 
@@ -51,10 +51,29 @@ def _check_c64(t: torch.Tensor, name: str, ndim: int) -> None:
         raise ValueError("%s must have %d dimension(s)" % (name, ndim))
 
 
+def _check_out(out: torch.Tensor, shape, device) -> None:
+    """A caller-supplied output must be a contiguous complex64 tensor of exactly the
+    result's shape on the inputs' device (the kernels write every element of it)."""
+    _check_c64(out, "out", len(shape))
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError("out must have shape %s, got %s" % (tuple(shape), tuple(out.shape)))
+    if out.device != device:
+        raise ValueError("out must be on %s" % (device,))
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor | None:
     if nbytes == 0:
         return None
     return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def _ws_for(ws: torch.Tensor | None, nbytes: int, device) -> torch.Tensor | None:
+    """The caller's workspace if it is a contiguous byte tensor of at least nbytes on
+    device, else a new one."""
+    if (ws is None or not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or not ws.is_contiguous()
+            or ws.device != device or ws.numel() < nbytes):
+        return _workspace(nbytes, device)
+    return ws
 
 
 def version() -> str:
@@ -89,11 +108,14 @@ def caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop:
     if r.shape[0] != n:
         raise ValueError("surv and ref must have the same length")
     p = _prec(prec)
+    if r.device != s.device:
+        raise ValueError("surv and ref must be on the same device")
     if out is None:
         out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device)
+    else:
+        _check_out(out, (n_tau, n_dop), s.device)
     nbytes = lib.ndft_caf_workspace(n, tau0, n_tau, p0, n_dop, p)
-    if ws is None or ws.numel() < nbytes:
-        ws = _workspace(nbytes, s.device)
+    ws = _ws_for(ws, nbytes, s.device)
     st = lib.ndft_caf(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
                       p, _ptr(ws), nbytes, _stream_handle())
     _lib.check(st, "ndft_caf")
@@ -124,11 +146,14 @@ def caf12b(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_d
     if r.shape[0] != n:
         raise ValueError("surv and ref must have the same length")
     p = _prec(prec)
+    if r.device != s.device:
+        raise ValueError("surv and ref must be on the same device")
     if out is None:
         out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device)
+    else:
+        _check_out(out, (n_tau, n_dop), s.device)
     nbytes = lib.ndft_caf12b_workspace(n, tau0, n_tau, p0, n_dop, p)
-    if nbytes and (ws is None or ws.numel() < nbytes):
-        ws = _workspace(nbytes, s.device)
+    ws = _ws_for(ws, nbytes, s.device)
     st = lib.ndft_caf12b(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
                          p, _ptr(ws) if nbytes else None, nbytes, _stream_handle())
     _lib.check(st, "ndft_caf12b")
@@ -142,7 +167,8 @@ def caf12b_workspace_bytes(n: int, tau0: int, n_tau: int, p0: int, n_dop: int, p
 def caf12c(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
            prec=BF16X2, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
     """Eq. (12c) surface A[n_tau, n_dop] (ordinary lag product, then the Eq. (6) operator
-    with the twiddle); BF16X2 or FP8 only (the sign-split forms)."""
+    with the twiddle). Every precision runs a sign-split plan: BF16X2 and FP8 take the
+    twiddle half on the matrix cores, FP32 as an FFT of the exact lag signs."""
     lib = _lib.load()
     _check_c64(s, "surv", 1)
     _check_c64(r, "ref", 1)
@@ -150,11 +176,14 @@ def caf12c(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_d
     if r.shape[0] != n:
         raise ValueError("surv and ref must have the same length")
     p = _prec(prec)
+    if r.device != s.device:
+        raise ValueError("surv and ref must be on the same device")
     if out is None:
         out = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device)
+    else:
+        _check_out(out, (n_tau, n_dop), s.device)
     nbytes = lib.ndft_caf12c_workspace(n, tau0, n_tau, p0, n_dop, p)
-    if ws is None or ws.numel() < nbytes:
-        ws = _workspace(nbytes, s.device)
+    ws = _ws_for(ws, nbytes, s.device)
     st = lib.ndft_caf12c(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), _ptr(out),
                          p, _ptr(ws), nbytes, _stream_handle())
     _lib.check(st, "ndft_caf12c")
@@ -245,6 +274,15 @@ class BatchPlan:
         _check_c64(surv_pool, "surv_pool", 1)
         _check_c64(ref_pool, "ref_pool", 1)
         _check_c64(out_pool, "out_pool", 1)
+        if not (surv_pool.device == ref_pool.device == out_pool.device == self.ws.device):
+            raise ValueError("pools and workspace must be on one device")
+        # the kernels read and write every element the descriptors name
+        need_s = max(c.surv_off + c.n for c in self._arr)
+        need_r = max(c.ref_off + c.n for c in self._arr)
+        need_o = max(c.out_off + c.n_tau * c.n_dop for c in self._arr)
+        if surv_pool.numel() < need_s or ref_pool.numel() < need_r or out_pool.numel() < need_o:
+            raise ValueError("pools too small for the batch: need surv %d, ref %d, out %d elements"
+                             % (need_s, need_r, need_o))
         st = lib.ndft_caf_batched(ctypes.byref(self.batch), _ptr(surv_pool), _ptr(ref_pool),
                                   _ptr(out_pool), _ptr(self.ws), self.ws_bytes, _stream_handle())
         _lib.check(st, "ndft_caf_batched")
@@ -287,6 +325,28 @@ def dbg_signs(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, twiddle: bool = 
                             _ptr(tw), _ptr(lg), _stream_handle())
     _lib.check(st, "ndft_dbg_signs")
     return tw, lg
+
+
+def dbg_split(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, prec=BF16X2, lin: bool = False,
+              lag: bool = True, T: bool = True):
+    """Sign operands of the sign-split plans, from the plan's own lag kernel: (lag [n_tau, n, 2]
+    int8 lag signs as the matrix-core half consumes them, T [n_tau, n_dop] complex64 twiddle-
+    sign half; bins p = 0 mod n hold the whole cell). lin selects the Eq. (12c) lag product."""
+    lib = _lib.load()
+    _check_c64(s, "surv", 1)
+    _check_c64(r, "ref", 1)
+    n = s.shape[0]
+    if r.shape[0] != n:
+        raise ValueError("surv and ref must have the same length")
+    p = _prec(prec)
+    lg = torch.empty((n_tau, n, 2), dtype=torch.int8, device=s.device) if lag else None
+    tt = torch.empty((n_tau, n_dop), dtype=torch.complex64, device=s.device) if T else None
+    nbytes = (lib.ndft_caf12c_workspace if lin else lib.ndft_caf_workspace)(n, tau0, n_tau, p0, n_dop, p)
+    ws = _workspace(nbytes, s.device)
+    st = lib.ndft_dbg_split(_ptr(s), _ptr(r), n, int(tau0), int(n_tau), int(p0), int(n_dop), p,
+                            1 if lin else 0, _ptr(lg), _ptr(tt), _ptr(ws), nbytes, _stream_handle())
+    _lib.check(st, "ndft_dbg_split")
+    return lg, tt
 
 
 def plan_count(prec=FP32) -> int:

@@ -332,6 +332,7 @@ struct Launch {
     size_t plane_off;       // offset of the planes in the workspace
     int grp_stride;
     int lin;           // sign-split: the Eq. (12c) lag product (lag_kfn_lin)
+    int fits;          // the twiddle table fits the plan's dynamic LDS (else NDFT_E_UNSUPPORTED)
     Dft12bLaunch dft;  // fft_d plans: the twiddle half's decimated FFT
     size_t dft_off;    // fft_d plans: offset of its partial surfaces in the workspace
 };
@@ -515,6 +516,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     int max_split = (int)std::max<int64_t>(1, cdiv(n, gran));
     const int cus = device_cu_count();
     choose_table(n, plan_max_dynamic(*L.plan), &L.tb, &L.n_coarse, &L.tw_exact);
+    L.fits = (int64_t)(L.n_coarse + (1 << L.tb)) * (int64_t)sizeof(float2) <= plan_max_dynamic(*L.plan) ? 1 : 0;
     // work-group slots: compute units times the plan's work-groups per unit
     const size_t dyn = L.plan->lag_kfn && !L.plan->planes_kfn ? (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2) : 0;
     const int slots = cus * (L.plan->lag_kfn ? plan_occupancy(*L.plan, prod, dyn) : 1);
@@ -680,8 +682,9 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
 
 // Sign-split form: twiddle planes, lsum_kernel (twiddle-sign part, sign codes, base 0),
 // dsum_kernel (twiddles against the lag signs); the reduction follows.
+// lsum_only: the lag kernel alone (no planes, no matrix part), for the sign test hook.
 ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t n_cols,
-                         int64_t tau0, float4 *partial, void *ws, hipStream_t stream)
+                         int64_t tau0, float4 *partial, void *ws, hipStream_t stream, bool lsum_only = false)
 {
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
@@ -689,7 +692,7 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
     uint4 *planes = reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off);
     const size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
     if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED;
-    if (L.tiles_b > 0 && L.plan->planes_kfn) {
+    if (!lsum_only && L.tiles_b > 0 && L.plan->planes_kfn) {
         DplaneParams Q;
         std::memset(&Q, 0, sizeof(Q));
         Q.planes = planes;
@@ -728,7 +731,7 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         if (hipLaunchKernel(tfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
     }
     ndft_status st = check_launch();
-    if (st != NDFT_OK || L.tiles_b == 0 || L.plan->fft_d) return st; // fft_d: the FFT runs after the reduction
+    if (st != NDFT_OK || lsum_only || L.tiles_b == 0 || L.plan->fft_d) return st; // fft_d: the FFT runs after the reduction
     ContractParams P;
     std::memset(&P, 0, sizeof(P));
     P.n = (int)n;
@@ -1071,7 +1074,8 @@ const char *ndft_version(void) { return "ndft-mi355x 0.1 (gfx950)"; }
 size_t ndft_forward_workspace(int64_t batch, int64_t n, int64_t k0, int64_t k_count, ndft_prec prec)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || batch < 1 || k_count < 1 || k_count > n) return 0;
-    return plan_launch((int)prec, PROD_IDENTITY, n, batch, k0, k_count, batch * (n + kTailPad)).ws_bytes;
+    const Launch L = plan_launch((int)prec, PROD_IDENTITY, n, batch, k0, k_count, batch * (n + kTailPad));
+    return L.plan && L.fits ? L.ws_bytes : 0;
 }
 
 ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int64_t k0, int64_t k_count,
@@ -1084,6 +1088,7 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     if (batch == 0) return NDFT_OK;
     if (batch > INT32_MAX / 2) return NDFT_E_INVAL;
     Launch L = plan_launch((int)prec, PROD_IDENTITY, n, batch, k0, k_count, batch * (n + kTailPad));
+    if (!L.plan || !L.fits) return NDFT_E_UNSUPPORTED; // decided before anything is enqueued
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1099,7 +1104,8 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
 size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
 {
     if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
-    return plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad).ws_bytes;
+    const Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
+    return L.plan && L.fits ? L.ws_bytes : 0;
 }
 
 ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
@@ -1110,6 +1116,7 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
+    if (!L.plan || !L.fits) return NDFT_E_UNSUPPORTED; // decided before anything is enqueued
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1147,7 +1154,7 @@ size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0,
 {
     if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
     Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 0, true);
-    return L.plan ? L.ws_bytes : 0;
+    return L.plan && L.fits ? L.ws_bytes : 0;
 }
 
 ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
@@ -1158,7 +1165,7 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
     if (!prec_ok(prec)) return NDFT_E_INVAL;
     Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 0, true);
-    if (!L.plan) return NDFT_E_UNSUPPORTED;
+    if (!L.plan || !L.fits) return NDFT_E_UNSUPPORTED;
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1237,6 +1244,41 @@ ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
                        reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), (int)n,
                        (int)tau0, (int)mod_n(p0, n), ntw, nlag, tw_sign, lag_sign);
     return check_launch();
+}
+
+ndft_status ndft_dbg_split(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
+                           int64_t p0, int64_t n_dop, ndft_prec prec, int32_t lin, int8_t *lag_sign, ndft_c64 *T,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
+    if (!surv || !ref || !aligned(surv, 8) || !aligned(ref, 8)) return NDFT_E_INVAL;
+    if (T && !aligned(T, 8)) return NDFT_E_INVAL;
+    if (!prec_ok(prec) || (lin != 0 && lin != 1)) return NDFT_E_INVAL;
+    if (n_tau * n > ((int64_t)1 << 40)) return NDFT_E_INVAL;
+    // the plan the surface entry point would take for these arguments
+    Launch L = lin ? plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 0, true)
+                   : plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
+    if (!L.plan || !L.fits || !L.plan->lag_kfn) return NDFT_E_UNSUPPORTED;
+    ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
+    if (st != NDFT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float4 *part = reinterpret_cast<float4 *>(ws);
+    st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
+                      tau0, part, ws, s, true);
+    if (st != NDFT_OK) return st;
+    if (lag_sign) {
+        const uint32_t *codes = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off);
+        const long long total = (long long)n_tau * n;
+        hipLaunchKernelGGL(dbg_decode_codes_kernel, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, codes,
+                           L.n_cols_pad, (int)n, total, lag_sign);
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
+    if (!T) return NDFT_OK;
+    // the lag kernel's partial planes alone: the twiddle-sign half (and base 0 whole)
+    Launch LT = L;
+    LT.ksplit = 0;
+    return launch_reduce(LT, part + (size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad, n, n_tau, p0, n_dop,
+                         reinterpret_cast<float2 *>(T), s);
 }
 
 size_t ndft_caf_backward_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,

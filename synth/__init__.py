@@ -183,6 +183,36 @@ def random_pair(n: int, seed: int, zeros: float = 0.0, integer: bool = False):
     return c64(s), c64(r)
 
 
+def dyadic_pair(n: int, seed: int):
+    """Inputs whose parts are drawn from four separated sets of powers of two: Re s in
+    {+-2, +-4}, Im s = +-1/4, Re r = +-1, Im r = +-1/2 (random signs). Every value is a
+    multiple of 1/4 and no two magnitudes of different parts coincide, so sums of their
+    magnitudes never tie and any FP32 sum of such terms below 2^22 is exact. Returns
+    complex64 (s, r)."""
+    rng = np.random.default_rng([SEED_BASE[0], SEED_BASE[1], 101, int(seed)])
+    sg = lambda: rng.choice([-1.0, 1.0], n)  # noqa: E731
+    s = sg() * rng.choice([2.0, 4.0], n) + 1j * sg() * 0.25
+    r = sg() * 1.0 + 1j * sg() * 0.5
+    return c64(s), c64(r)
+
+
+def sparse_pair(n: int, seed: int, count: int = 48, positions=()):
+    """A surveillance record with only `count` non-zero samples (complex Gaussian), at the
+    given positions plus random distinct others, against a dense complex Gaussian
+    reference: every delay row then holds at most `count` non-zero lag terms, so a single
+    wrong sign operand moves an output by a large fraction of its l1 scale. Returns
+    complex64 (s, r)."""
+    rng = np.random.default_rng([SEED_BASE[0], SEED_BASE[1], 102, int(seed)])
+    pos = sorted({int(p) % n for p in positions})
+    taken = set(pos)
+    rest = [int(k) for k in rng.permutation(n) if int(k) not in taken]
+    pos = pos + rest[: max(0, count - len(pos))]
+    s = np.zeros(n, np.complex128)
+    s[pos] = complex_gaussian(rng, len(pos))
+    r = complex_gaussian(rng, n)
+    return c64(s), c64(r)
+
+
 # ----------------------------------------------------------------------------------
 # Robustness scenes: targets and clutter under AWGN or eps-contaminated Gaussian noise
 # ----------------------------------------------------------------------------------

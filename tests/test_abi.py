@@ -192,3 +192,54 @@ def test_fp32_plan_choice_rules():
     assert not name(4096, 256, 0, 4096).startswith("fp32s_")   # bases up to N / 2
     assert not name(65540, 3, -2, 5).startswith("fp32s_")      # N = 4 x odd
     assert not name(1000, 64, -3, 7).startswith("fp32s_")      # N = 8 x 125
+
+
+@pytest.mark.parametrize(
+    "n,tau0,n_tau,p0,n_dop",
+    [(0, 0, 1, 0, 1), (8, -1, 1, 0, 1), (8, 0, 0, 0, 1), (8, 4, 5, 0, 1), (8, 0, 1, 0, 0),
+     (8, 0, 1, 0, 9), ((1 << 24) + 1, 0, 1, 0, 1)],
+)
+def test_dbg_split_rejects_bad_shapes(n, tau0, n_tau, p0, n_dop):
+    lib = _lib.load()
+    keep, p = _host_buf()
+    assert lib.ndft_dbg_split(p, p, n, tau0, n_tau, p0, n_dop, 1, 0, p, p, p, 4096, None) == INVAL
+
+
+def test_dbg_split_arguments():
+    lib = _lib.load()
+    keep, p = _host_buf()
+    odd = ctypes.c_void_p(p.value + 4)
+    args = (65536, 0, 1024, -256, 512)
+    assert lib.ndft_dbg_split(None, p, *args, 1, 0, p, p, p, 4096, None) == INVAL
+    assert lib.ndft_dbg_split(odd, p, *args, 1, 0, p, p, p, 4096, None) == INVAL
+    assert lib.ndft_dbg_split(p, p, *args, 1, 0, p, odd, p, 4096, None) == INVAL  # misaligned T
+    assert lib.ndft_dbg_split(p, p, *args, 7, 0, p, p, p, 4096, None) == INVAL    # precision
+    assert lib.ndft_dbg_split(p, p, *args, 1, 2, p, p, p, 4096, None) == INVAL    # lin is 0 or 1
+    # the narrow window takes a sign-split plan in every precision: the hook needs the
+    # surface call's workspace
+    for prec in (0, 1, 2):
+        need = lib.ndft_caf_workspace(*args, prec)
+        assert need > 0
+        assert lib.ndft_dbg_split(p, p, *args, prec, 0, p, p, None, 0, None) == WORKSPACE
+        assert lib.ndft_dbg_split(p, p, *args, prec, 1, p, p, None, 0, None) == WORKSPACE
+    # the full-window N = 4096 surface takes a combined (non-split) plan in split-BF16
+    assert lib.ndft_dbg_split(p, p, 4096, 0, 256, 0, 4096, 1, 0, p, p, p, 1 << 40, None) == UNSUPPORTED
+
+
+def test_unsupported_shape_rejected_before_any_launch():
+    # a twiddle table that exceeds the LDS a plan leaves free is refused on the host,
+    # before anything is enqueued (host pointers here: any launch would fault), and the
+    # workspace query reports 0 for it
+    # (no workspace is passed, so an accepted shape stops at the workspace check and
+    # nothing can be launched in either case)
+    lib = _lib.load()
+    keep, p = _host_buf()
+    seen = set()
+    for n in (1 << 22, 1 << 24):
+        for prec in (0, 1, 2):
+            for (n_tau, p0, n_dop) in ((4, -2048, 4096), (4, -4, 8)):
+                need = lib.ndft_caf_workspace(n, 0, n_tau, p0, n_dop, prec)
+                st = lib.ndft_caf(p, p, n, 0, n_tau, p0, n_dop, p, prec, None, 0, None)
+                assert st == (WORKSPACE if need > 0 else UNSUPPORTED), (n, prec, n_dop, need, st)
+                seen.add(st)
+    assert UNSUPPORTED in seen  # some plan's table does not fit at these lengths

@@ -107,6 +107,7 @@ def autotune_batch(descs, surv_pool, ref_pool, out_pool, prec=0, reps: int = 3,
     """Best (plan, chunk) for a batch; returns (BatchPlan prepared with it, record)."""
     p = _prec(prec)
     results = []
+    seen = set()
     for plan in range(plan_count(p)):
         set_plan(p, plan, 0)
         for ch in chunks:
@@ -114,9 +115,19 @@ def autotune_batch(descs, surv_pool, ref_pool, out_pool, prec=0, reps: int = 3,
                 bp = BatchPlan(descs, p, device=surv_pool.device, chunk=ch)
             except RuntimeError:
                 continue
+            # a plan without a batched kernel falls back to the built-in one: time each
+            # (plan actually used, chunk) once
+            used = bp.batch.plan
+            if (used, ch) in seen:
+                del bp
+                continue
+            seen.add((used, ch))
             ms = _time(lambda: bp.run(surv_pool, ref_pool, out_pool), reps)
-            results.append(dict(plan=plan, name=plan_name(p, plan), chunk=ch, ms=ms))
+            results.append(dict(plan=used, name=plan_name(p, used), chunk=ch, ms=ms))
             del bp
+    set_plan(p, -1, 0)
+    if not results:
+        raise RuntimeError("autotune_batch: no batched plan for this precision")
     best = min(results, key=lambda d: d["ms"])
     set_plan(p, best["plan"], 0)
     bp = BatchPlan(descs, p, device=surv_pool.device, chunk=best["chunk"])

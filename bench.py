@@ -318,49 +318,40 @@ def bench_nfft(nd, torch, args):
     return res
 
 
-def object_margin(A, objects, guard=3):
-    """Detection on a surface magnitude: every object cell (delay row, bin column) against
-    the largest magnitude outside +-guard cells of all objects. margin_db =
-    20 log10(that floor / weakest object): below 0 every object stands above it."""
-    import numpy as np
-
-    mag = np.abs(np.asarray(A))
-    mask = np.ones(mag.shape, bool)
-    for l, q in objects:
-        mask[max(0, l - guard):l + guard + 1, max(0, q - guard):q + guard + 1] = False
-    floor = float(mag[mask].max())
-    vals = [float(mag[l, q]) for l, q in objects]
-    return {"detected": int(sum(v > floor for v in vals)), "objects": len(objects),
-            "margin_db": 20.0 * math.log10(floor / max(min(vals), 1e-30))}
-
-
 def bench_robustness(nd, synth, torch, args):
     """Targets and clutter under AWGN and eps-contaminated Gaussian noise (noise-free
     reference): the Eq. (12a) and (12b) surfaces (this library) against the ordinary
-    cross-ambiguity function of Eq. (11) (numpy FFT of the lag products, comparison only)."""
+    cross-ambiguity function of Eq. (11) (numpy FFT of the lag products, comparison only),
+    scored by synth.object_margin (side-lobe floor beyond +-3 cells of every object)."""
     import numpy as np
 
-    n, n_tau, p0, n_dop = 8192, 128, -64, 128
-    res = {"workload": "N=8192, delays 0..127, Doppler bins -64..63; objects per scene; "
-                       "margin_db = 20 log10(max off-object |A| / weakest object |A|), guard +-3 cells"}
+    n, tau0, n_tau, p0, n_dop = synth.ROBUST_WINDOW
+    res = {"workload": "N=%d, delays %d..%d, Doppler bins %d..%d; objects per scene; margin_db = "
+                       "20 log10(max off-object |A| / weakest object |A|), guard +-3 cells"
+                       % (n, tau0, tau0 + n_tau - 1, p0, p0 + n_dop - 1)}
     bins = (p0 + np.arange(n_dop)) % n
-    for scene, (targets, clutter) in synth.ROBUST_SCENES.items():
-        objs = [(d, q - p0) for d, q, _ in targets] + [(d, -p0) for d, _ in clutter]
+    for scene in synth.ROBUST_SCENES:
+        objs = synth.scene_objects(scene, p0)
         res[scene] = {}
         for noise in synth.ROBUST_NOISES:
             s, r = synth.robustness_pair(scene, noise, n)
             S, R = torch.from_numpy(s).cuda(), torch.from_numpy(r).cuda()
             lin = np.empty((n_tau, n_dop), np.complex128)
             s64, r64 = s.astype(np.complex128), r.astype(np.complex128)
-            for l in range(n_tau):
+            for j in range(n_tau):
+                l = tau0 + j
                 rs = np.concatenate([np.zeros(l), r64[:n - l]])
-                lin[l] = np.fft.fft(s64 * np.conj(rs))[bins]
+                lin[j] = np.fft.fft(s64 * np.conj(rs))[bins]
             surfaces = {
-                "eq12a_bf16x2": nd.caf(S, R, 0, n_tau, p0, n_dop, nd.BF16X2).cpu().numpy(),
-                "eq12b_fp32": nd.caf12b(S, R, 0, n_tau, p0, n_dop).cpu().numpy(),
+                "eq12a_bf16x2": nd.caf(S, R, tau0, n_tau, p0, n_dop, nd.BF16X2).cpu().numpy(),
+                "eq12b_fp32": nd.caf12b(S, R, tau0, n_tau, p0, n_dop).cpu().numpy(),
                 "eq11_linear": lin,
             }
-            res[scene][noise] = {k: object_margin(v, objs) for k, v in surfaces.items()}
+            res[scene][noise] = {}
+            for k, v in surfaces.items():
+                m = synth.object_margin(v, objs)
+                res[scene][noise][k] = {"detected": m["detected"], "objects": m["objects"],
+                                        "margin_db": round(m["margin_db"], 3)}
     return res
 
 

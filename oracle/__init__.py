@@ -249,6 +249,24 @@ def caf12c(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, rows=None):
     return A, sc
 
 
+def caf11(s, r, tau0: int, n_tau: int, p0: int, n_dop: int):
+    """The ordinary cross-ambiguity function of Eq. (11): for each delay l the DFT of the
+    lag products s[i] conj(r[i - l]) (r zero before the record) at bins p = p0 + q mod N,
+    in FP64 (numpy's FFT as the DFT step). Comparison surface of the detection runs of
+    Section 5; returns A [n_tau][n_dop] complex128."""
+    s = _c128(s)
+    r = _c128(r)
+    n = s.shape[0]
+    bins = (int(p0) + np.arange(int(n_dop))) % n
+    A = np.zeros((int(n_tau), int(n_dop)), np.complex128)
+    for j in range(int(n_tau)):
+        d = int(tau0) + j
+        rd = np.zeros(n, np.complex128)
+        rd[d:] = r[: n - d]
+        A[j] = np.fft.fft(s * np.conj(rd))[bins]
+    return A
+
+
 def caf_grad(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, G):
     """(grad_r, grad_s) of a real loss with upstream G = dL/dReA + j dL/dImA."""
     s = _c128(s)

@@ -236,12 +236,17 @@ ROBUST_SCENES = {
                              [(5, 0.0), (12, -3.0)]),
     "1 target 3 clutters": ([(64, 17, -6.0)], [(3, 0.0), (9, -3.0), (15, -6.0)]),
 }
-# noise -> ("awgn", noise_db) or ("eps", eps, sigma1, sigma2)
+# noise -> ("awgn", noise_db) or ("eps", eps, sigma1, sigma2): the four noise cases of
+# each scene in the paper's detection tables (AWGN at 3 dB and 6 dB SNR, i.e. noise power
+# 3 / 6 dB below the reference power, and the two contaminated mixtures)
 ROBUST_NOISES = {
-    "awgn -10 dB": ("awgn", -10.0),
+    "awgn 3 dB": ("awgn", -3.0),
+    "awgn 6 dB": ("awgn", -6.0),
     "eps 0.9 / 0.25 / 10": ("eps", 0.9, 0.25, 10.0),
     "eps 0.8 / 0.5 / 20": ("eps", 0.8, 0.5, 20.0),
 }
+# surface window of the detection runs: N = 8192, delays 0..127, Doppler bins -64..63
+ROBUST_WINDOW = (8192, 0, 128, -64, 128)
 
 
 def robustness_pair(scene: str, noise: str, n: int = 8192, seed: int = 0):
@@ -257,3 +262,27 @@ def robustness_pair(scene: str, noise: str, n: int = 8192, seed: int = 0):
     else:
         s = s + eps_contaminated(rng, n, *kind[1:])
     return c64(s), c64(r)
+
+
+def scene_objects(scene: str, p0: int):
+    """(delay row, bin column) of every target and clutter object of a scene on a surface
+    whose first Doppler column is bin p0 (delay rows from 0)."""
+    targets, clutter = ROBUST_SCENES[scene]
+    return [(d, q - p0) for d, q, _ in targets] + [(d, -p0) for d, _ in clutter]
+
+
+def object_margin(A, objects, guard: int = 3):
+    """Detection on a surface magnitude (the side-lobe floor of the detection tables):
+    floor = the largest |A| farther than +-guard cells (delay and Doppler) from every
+    object; an object is detected when its own cell stands above the floor. margin_db =
+    20 log10(floor / weakest object), below 0 when every object is detected.
+    Scoring of the scenes only: no arithmetic of the method."""
+    mag = np.abs(np.asarray(A))
+    mask = np.ones(mag.shape, bool)
+    for l, q in objects:
+        mask[max(0, l - guard):l + guard + 1, max(0, q - guard):q + guard + 1] = False
+    floor = float(mag[mask].max())
+    vals = [float(mag[l, q]) for l, q in objects]
+    return {"detected": int(sum(v > floor for v in vals)), "objects": len(objects),
+            "margin_db": 20.0 * math.log10(floor / max(min(vals), 1e-30)),
+            "object_db": [20.0 * math.log10(max(v, 1e-30) / floor) for v in vals]}

@@ -29,7 +29,7 @@ def build(force: bool = False) -> str:
     ):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+            ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
              "-std=gnu11", "-Wall", "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB_PATH)
@@ -66,6 +66,10 @@ def _load():
         lib.oracle_nfft.restype = ctypes.c_int
         lib.oracle_nfft32.argtypes = [P, I, I, P]
         lib.oracle_nfft32.restype = ctypes.c_int
+        lib.oracle_nfft_outer.argtypes = [P, I, I, P]
+        lib.oracle_nfft_outer.restype = ctypes.c_int
+        lib.oracle_nfft32_outer.argtypes = [P, I, I, P]
+        lib.oracle_nfft32_outer.restype = ctypes.c_int
         lib.oracle_caf_grad.argtypes = [P, P, I, I, I, I, I, P, P, P]
         lib.oracle_caf_grad.restype = ctypes.c_int
         lib.oracle_caf_loss.argtypes = [P, P, I, I, I, I, I, P]
@@ -198,6 +202,26 @@ def nfft32(x):
     X = np.zeros_like(x)
     if _load().oracle_nfft32(_ptr(x), x.shape[0], x.shape[1], _ptr(X)):
         raise ValueError("oracle_nfft32: n must be a power of two")
+    return X
+
+
+def nfft_outer(x):
+    """The printed reading of Eq. (10): ordinary products with W_n^k at every level of the
+    radix-2 recursion, the operator of Eq. (6) in the length-1 sums at its bottom
+    (x (x) 1). FP64, rows of x [batch][n] (n a power of two)."""
+    x = np.atleast_2d(_c128(x))
+    X = np.zeros_like(x)
+    if _load().oracle_nfft_outer(_ptr(x), x.shape[0], x.shape[1], _ptr(X)):
+        raise ValueError("oracle_nfft_outer: n must be a power of two")
+    return X
+
+
+def nfft32_outer(x):
+    """The same recursion in FP32, each product and sum rounded on its own."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex64)
+    X = np.zeros_like(x)
+    if _load().oracle_nfft32_outer(_ptr(x), x.shape[0], x.shape[1], _ptr(X)):
+        raise ValueError("oracle_nfft32_outer: n must be a power of two")
     return X
 
 

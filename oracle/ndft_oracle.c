@@ -630,6 +630,60 @@ static void nfft32_rec(const float *x, int64_t n, int64_t stride, int64_t N, con
     }
 }
 
+/* ------------------------------------------------------------------------------ */
+/* The printed reading of Eq. (10): the twiddle W_n^k in front of the odd half is an  */
+/* ordinary complex product at every level, X[k] = E[k] + W_n^k O[k], X[k + n/2] =   */
+/* E[k] - W_n^k O[k], and the operator of Eq. (6) sits in the sums themselves, whose  */
+/* terms at the bottom of the recursion are single samples against W^0 = 1: the       */
+/* length-1 transform of a sample x is x (x) 1.                                       */
+/* ------------------------------------------------------------------------------ */
+static void nfft64o_rec(const double *x, int64_t n, int64_t stride, int64_t N, double *X, double *tmp)
+{
+    if (n == 1) {
+        const double one[2] = {1.0, 0.0};
+        oracle_cop(x, one, X);
+        return;
+    }
+    const int64_t h = n / 2;
+    double *E = tmp, *O = tmp + 2 * h, *sub = tmp + 4 * h;
+    nfft64o_rec(x, h, 2 * stride, N, E, sub);
+    nfft64o_rec(x + 2 * stride, h, 2 * stride, N, O, sub);
+    for (int64_t k = 0; k < h; ++k) {
+        double w[2];
+        oracle_twiddle(k * (N / n), N, w);
+        const double tr = O[2 * k] * w[0] - O[2 * k + 1] * w[1];
+        const double ti = O[2 * k] * w[1] + O[2 * k + 1] * w[0];
+        X[2 * k] = E[2 * k] + tr;
+        X[2 * k + 1] = E[2 * k + 1] + ti;
+        X[2 * (k + h)] = E[2 * k] - tr;
+        X[2 * (k + h) + 1] = E[2 * k + 1] - ti;
+    }
+}
+
+/* The same in FP32, every product and sum rounded on its own (no fused multiply-add). */
+static void nfft32o_rec(const float *x, int64_t n, int64_t stride, int64_t N, const float *tw, float *X, float *tmp)
+{
+    if (n == 1) {
+        X[0] = rop32(x[0], 1.0f) - rop32(x[1], 0.0f);
+        X[1] = rop32(x[1], 1.0f) + rop32(0.0f, x[0]);
+        return;
+    }
+    const int64_t h = n / 2;
+    float *E = tmp, *O = tmp + 2 * h, *sub = tmp + 4 * h;
+    nfft32o_rec(x, h, 2 * stride, N, tw, E, sub);
+    nfft32o_rec(x + 2 * stride, h, 2 * stride, N, tw, O, sub);
+    for (int64_t k = 0; k < h; ++k) {
+        const float *w = tw + 2 * (k * (N / n));
+        const float orr = O[2 * k], oi = O[2 * k + 1];
+        const float p1 = orr * w[0], p2 = oi * w[1], p3 = orr * w[1], p4 = oi * w[0];
+        const float tr = p1 - p2, ti = p3 + p4;
+        X[2 * k] = E[2 * k] + tr;
+        X[2 * k + 1] = E[2 * k + 1] + ti;
+        X[2 * (k + h)] = E[2 * k] - tr;
+        X[2 * (k + h) + 1] = E[2 * k + 1] - ti;
+    }
+}
+
 static int is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
 
 /* x, X: [batch][n][2] FP64; n a power of two. */
@@ -661,6 +715,40 @@ int oracle_nfft32(const float *x, int64_t batch, int64_t n, float *X)
     for (int64_t b = 0; b < batch; ++b) {
         float *tmp = (float *)malloc(sizeof(float) * 8 * (size_t)n + 16);
         nfft32_rec(x + 2 * b * n, n, 1, n, tw, X + 2 * b * n, tmp);
+        free(tmp);
+    }
+    free(tw);
+    return 0;
+}
+
+
+/* Printed reading of Eq. (10) (see nfft64o_rec): FP64 and FP32. */
+int oracle_nfft_outer(const double *x, int64_t batch, int64_t n, double *X)
+{
+    if (!is_pow2(n) || batch < 0) return 1;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t b = 0; b < batch; ++b) {
+        double *tmp = (double *)malloc(sizeof(double) * 8 * (size_t)n + 16);
+        nfft64o_rec(x + 2 * b * n, n, 1, n, X + 2 * b * n, tmp);
+        free(tmp);
+    }
+    return 0;
+}
+
+int oracle_nfft32_outer(const float *x, int64_t batch, int64_t n, float *X)
+{
+    if (!is_pow2(n) || batch < 0) return 1;
+    float *tw = (float *)malloc(sizeof(float) * 2 * (size_t)n);
+    for (int64_t m = 0; m < n; ++m) {
+        double w[2];
+        oracle_twiddle(m, n, w);
+        tw[2 * m] = (float)w[0];
+        tw[2 * m + 1] = (float)w[1];
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t b = 0; b < batch; ++b) {
+        float *tmp = (float *)malloc(sizeof(float) * 8 * (size_t)n + 16);
+        nfft32o_rec(x + 2 * b * n, n, 1, n, tw, X + 2 * b * n, tmp);
         free(tmp);
     }
     free(tw);

@@ -536,3 +536,66 @@ def test_nfft_is_not_the_ndft(orc):
     X1, _ = orc.ndft(x[None])
     X2 = orc.nfft(x)
     assert np.max(np.abs(X1 - X2)) > 1.0
+
+
+# ---------------------------------------------------------------------------------
+# The printed reading of Eq. (10): ordinary W_n^k products at every level, the operator of
+# Eq. (6) only in the length-1 sums at the bottom (x (x) 1 = x + csgn(x)).
+# ---------------------------------------------------------------------------------
+def test_nfft_outer_by_hand(orc):
+    # one sample: (1 - 2j) (x) 1 = (1 + 1) + j(-(2 + 1)) = 2 - 3j
+    np.testing.assert_array_equal(orc.nfft_outer(np.array([1 - 2j]))[0], [2 - 3j])
+    # two samples (1, 2j): leaves 1 (x) 1 = 2 and (2j) (x) 1 = 3j; X = (2 + 3j, 2 - 3j)
+    np.testing.assert_array_equal(orc.nfft_outer(np.array([1, 2j]))[0], [2 + 3j, 2 - 3j])
+    # four samples (1, j, 0, 2): leaves 2, 2j, 0, 3; E = (2 + 0, 2 - 0) = (2, 2),
+    # O = (2j + 3, 2j - 3); X = E + (1, -j) O, E - (1, -j) O
+    X = orc.nfft_outer(np.array([1.0, 1.0j, 0.0, 2.0]))[0]
+    o0, o1 = 3 + 2j, -3 + 2j
+    np.testing.assert_array_equal(X, [2 + o0, 2 + (-1j) * o1, 2 - o0, 2 - (-1j) * o1])
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 64, 1024, 8192])
+def test_nfft_outer_is_the_fft_of_the_leaf_values(orc, n):
+    # every level above the leaves is an ordinary radix-2 butterfly, so the transform is the
+    # DFT of x (x) 1 = x + csgn(x) (a library FFT here)
+    rng = np.random.default_rng(n + 90)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x[:: max(1, n // 7)] = 0.0  # exact zeros: their leaf value is 0
+    y = x + np.sign(x.real) + 1j * np.sign(x.imag)
+    X = orc.nfft_outer(x)[0]
+    F = np.fft.fft(y)
+    assert np.max(np.abs(X - F)) <= 1e-13 * max(1.0, np.abs(F).max())
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_nfft_outer_equals_ndft_for_ternary_twiddles(orc, n):
+    # for n <= 4 every twiddle is 0 / +-1 / +-j, so the NDFT of Eq. (7) is the DFT of
+    # x + csgn(x) too (S = F): both readings of this transform meet it on integer data
+    rng = np.random.default_rng(n + 91)
+    for _ in range(20):
+        x = (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(complex)
+        Xn, _ = orc.ndft(x[None])
+        np.testing.assert_array_equal(orc.nfft_outer(x)[0], Xn[0])
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_nfft_fp32_equals_fp64_on_small_integers(orc, n):
+    # twiddles 1 and -j and small integer data: every FP32 operation is exact, so both
+    # FP32 recursions equal their FP64 definitions bit for bit
+    rng = np.random.default_rng(n + 92)
+    for _ in range(50):
+        x = (rng.integers(-50, 51, n) + 1j * rng.integers(-50, 51, n)).astype(np.complex64)
+        np.testing.assert_array_equal(orc.nfft32(x)[0].astype(np.complex128), orc.nfft(x)[0])
+        np.testing.assert_array_equal(orc.nfft32_outer(x)[0].astype(np.complex128), orc.nfft_outer(x)[0])
+
+
+@pytest.mark.parametrize("n", [8, 64, 1024, 8192])
+def test_nfft_outer_fp32_within_the_fft_bound(orc, n):
+    # the FP32 recursion of the printed reading is an FFT in FP32 after exact-sign leaves;
+    # its error stays within a few log2(n) ulp of the largest output
+    rng = np.random.default_rng(n + 93)
+    x = (rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))).astype(np.complex64)
+    X64, X32 = orc.nfft_outer(x), orc.nfft32_outer(x)
+    lg = max(1, int(np.log2(n)))
+    assert np.max(np.abs(X64 - X32)) <= 4 * lg * 2.0 ** -24 * np.abs(X64).max() * np.sqrt(n)
+    np.testing.assert_array_equal(orc.nfft32_outer(-x), -X32)

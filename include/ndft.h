@@ -96,6 +96,25 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
+ * ndft_caf without a caller workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same surface, arguments, limits and kernels as
+ * ndft_caf (bit-identical results for the same plan); the call's scratch is a static
+ * device array of NDFT_NOALLOC_SCRATCH_BYTES that each GPU using the library holds
+ * until the process ends. A call whose ndft_caf workspace exceeds that size returns
+ * NDFT_E_WORKSPACE before anything is enqueued (at N = 65536 with 1024 delays x 512
+ * bins: FP32 and BF16X2 fit, FP8 does not). The call allocates nothing (no hipMalloc,
+ * no event records even with ndft_prof_enable on). All calls on one GPU share its
+ * scratch and its contents are left as the last call wrote them: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be serialized by the
+ * caller, e.g. by issuing them on one stream.
+ * ------------------------------------------------------------------------------- */
+#define NDFT_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
+ndft_status ndft_caf_noalloc(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                             int64_t n_tau, int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec,
+                             void *stream);
+
+/* ---------------------------------------------------------------------------------
  * NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT with the twiddle
  * product of every butterfly replaced by the operator of Eq. (6),
  *   X[k] = E[k] + O[k] (x) W_n^k,  X[k + n/2] = E[k] - O[k] (x) W_n^k,

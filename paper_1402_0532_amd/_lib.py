@@ -22,6 +22,7 @@ SIGNATURES = {
     "ndft_forward": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I32, _P, _SZ, _P]),
     "ndft_caf_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P, _SZ, _P]),
+    "ndft_caf_noalloc": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P]),
     "ndft_nfft": (_ST, [_P, _P, _I64, _I64, _P]),
     "ndft_caf12b_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf12b": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P, _SZ, _P]),

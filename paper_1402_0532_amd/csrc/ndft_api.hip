@@ -563,6 +563,8 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
 // ------------------------------------------------------------------------------------
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+// set for the duration of an ndft_caf_noalloc call on this thread: no event records
+thread_local bool t_no_prof = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pending;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -584,7 +586,7 @@ struct ProfScope {
     explicit ProfScope(hipStream_t st) : s(st)
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (!g_prof_on) return;
+        if (!g_prof_on || t_no_prof) return;
         a = take_event();
         b = take_event();
         if (a && b) (void)hipEventRecord(a, s);
@@ -1050,6 +1052,38 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
 
 std::atomic<unsigned long long> g_batch_seq{0};
 
+// ------------------------------------------------------------------------------------
+// static scratch of the no-allocation surface entry point
+// ------------------------------------------------------------------------------------
+// Each device that loads the library holds one copy until the process ends. Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) char scratch[NDFT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch address on device `dev` (nullptr on failure)
+void *scratch_on(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return g_scratch_ptr[dev];
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+    return ptr;
+}
+
 } // namespace
 
 // ======================================================================================
@@ -1148,6 +1182,28 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     }
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+}
+
+ndft_status ndft_caf_noalloc(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,
+                             int64_t p0, int64_t n_dop, ndft_c64 *A, ndft_prec prec, void *stream)
+{
+    // the checks of ndft_caf, then the workspace against the scratch size, all before
+    // anything is enqueued
+    if (!caf_args_ok(n, tau0, n_tau, n_dop)) return NDFT_E_INVAL;
+    if (!surv || !ref || !A || !aligned(surv, 8) || !aligned(ref, 8) || !aligned(A, 8)) return NDFT_E_INVAL;
+    if (!prec_ok(prec)) return NDFT_E_INVAL;
+    const Launch L = plan_launch((int)prec, PROD_LAG, n, n_tau, p0, n_dop, 3 * n + 2 * kTailPad);
+    if (!L.plan || !L.fits) return NDFT_E_UNSUPPORTED;
+    if (L.ws_bytes > NDFT_NOALLOC_SCRATCH_BYTES) return NDFT_E_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int dev = -1;
+    if (s ? hipStreamGetDevice(s, &dev) != hipSuccess : hipGetDevice(&dev) != hipSuccess) return NDFT_E_HIP;
+    void *ws = scratch_on(dev);
+    if (!ws) return NDFT_E_HIP;
+    t_no_prof = true;
+    const ndft_status st = ndft_caf(surv, ref, n, tau0, n_tau, p0, n_dop, A, prec, ws, NDFT_NOALLOC_SCRATCH_BYTES, stream);
+    t_no_prof = false;
+    return st;
 }
 
 size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)

@@ -185,6 +185,37 @@ __device__ __forceinline__ void fft_passes(float2 *X, int mb, int p, int n, cons
     }
 }
 
+// The transformed value of one sample pair (s[i], r[i - d]): the lag product of Eq. (6)
+// (DFT_LAG), its exact signs (DFT_SIGNS), or the exact signs of the ordinary lag product
+// s conj(r) (DFT_LIN_SIGNS).
+template <int SRC>
+__device__ __forceinline__ float2 dft_source(float2 a, float2 b)
+{
+    if constexpr (SRC == DFT_LIN_SIGNS) {
+        // s conj(r) from FP32 products: the rounded sum carries the exact sign when it
+        // exceeds 2^-22 of the parts' magnitude (each product and the sum are off by at
+        // most 2^-24 of their size, or 2^-150 below the normal range, which the 2^-100
+        // floor covers); a zero sample gives exact zeros; otherwise FP64, where both
+        // FP32 x FP32 products are exact and one rounding of their sum keeps the sign
+        const float p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.y * b.x, p4 = a.x * b.y;
+        const float zr = p1 + p2, zi = p3 - p4;
+        const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
+        const bool zero = (a.x == 0.0f && a.y == 0.0f) || (b.x == 0.0f && b.y == 0.0f);
+        const bool sure = fabsf(zr) > 0x1p-22f * mr && mr >= 0x1p-100f && fabsf(zi) > 0x1p-22f * mi &&
+                          mi >= 0x1p-100f;
+        float2 u = zero ? make_float2(0.0f, 0.0f) : make_float2(sgnf(zr), sgnf(zi));
+        if (!zero && !sure) {
+            const double sx = a.x, sy = a.y, rx = b.x, ry = b.y;
+            const double zr64 = fma(sx, rx, sy * ry), zi64 = fma(sy, rx, -(sx * ry));
+            u = make_float2((float)((zr64 > 0.0) - (zr64 < 0.0)), (float)((zi64 > 0.0) - (zi64 < 0.0)));
+        }
+        return u;
+    } else {
+        const Lag z = lag_product(a, b);
+        return SRC == DFT_SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
+    }
+}
+
 // The lag products and the first Stockham pass (p = 1: no inner twiddles) in one step:
 // butterfly (b, i) loads its R samples t = i + r L / R of transform b straight from the
 // inputs, forms their lag products and writes the R-point DFT to x[b][i R + r]. Lanes run
@@ -226,30 +257,7 @@ __device__ __forceinline__ void fill_first_pass(float2 *X, const Dft12bParams &P
         float2 u[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if constexpr (SRC == DFT_LIN_SIGNS) {
-                // s conj(r) from FP32 products: the rounded sum carries the exact sign when it
-                // exceeds 2^-22 of the parts' magnitude (each product and the sum are off by
-                // at most 2^-24 of their size, or 2^-150 below the normal range, which the
-                // 2^-100 floor covers); a zero sample gives exact zeros; otherwise FP64, where
-                // both FP32 x FP32 products are exact and one rounding of their sum keeps
-                // the sign
-                const float2 a = sv[c][r], b = rv[c][r];
-                const float p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.y * b.x, p4 = a.x * b.y;
-                const float zr = p1 + p2, zi = p3 - p4;
-                const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
-                const bool zero = (a.x == 0.0f && a.y == 0.0f) || (b.x == 0.0f && b.y == 0.0f);
-                const bool sure = fabsf(zr) > 0x1p-22f * mr && mr >= 0x1p-100f && fabsf(zi) > 0x1p-22f * mi &&
-                                  mi >= 0x1p-100f;
-                u[r] = zero ? make_float2(0.0f, 0.0f) : make_float2(sgnf(zr), sgnf(zi));
-                if (!zero && !sure) {
-                    const double sx = a.x, sy = a.y, rx = b.x, ry = b.y;
-                    const double zr64 = fma(sx, rx, sy * ry), zi64 = fma(sy, rx, -(sx * ry));
-                    u[r] = make_float2((float)((zr64 > 0.0) - (zr64 < 0.0)), (float)((zi64 > 0.0) - (zi64 < 0.0)));
-                }
-            } else {
-                const Lag z = lag_product(sv[c][r], rv[c][r]);
-                u[r] = SRC == DFT_SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
-            }
+            u[r] = dft_source<SRC>(sv[c][r], rv[c][r]);
         }
         if constexpr (R > 1) small_dft<R>(u);
 #pragma unroll

@@ -365,3 +365,45 @@ def test_impulses_n4096_all_bins_every_plan(nd, sparse4096, prec, plan):
     e = rel_err(A[rows], Ao, sc)
     log("  max l1-relative error", e)
     assert e <= TOL[prec]
+
+
+# ------------------------------------------------------------------------------------
+# rounding of the twiddle-sign half on DC-heavy rows at the largest admitted base
+# ------------------------------------------------------------------------------------
+def dc_pair(n, seed):
+    """Records whose lag products keep one sign and nearly one value along each row (a
+    strong constant plus 1% noise per part): the prefix sums the crossing walk reads grow
+    linearly along the row while T itself stays small, the hardest case for its rounding."""
+    rng = np.random.default_rng(seed)
+    s = (1.0 + 0.01 * rng.standard_normal(n)) + 1j * (0.7 + 0.01 * rng.standard_normal(n))
+    r = (0.9 + 0.01 * rng.standard_normal(n)) - 1j * (0.6 + 0.01 * rng.standard_normal(n))
+    return synth.c64(s), synth.c64(r)
+
+
+@pytest.fixture(scope="module")
+def dc65536(orc):
+    # bins -256..255: the largest base 256 has 256 b = N, the limit where the built-in
+    # choice still takes the sign-split plans
+    n, tau0, n_tau, p0, n_dop = 65536, 0, 64, -256, 512
+    s, r = dc_pair(n, 61)
+    rows = np.array([0, 1, 17, 40, 63])
+    z, sg = oracle_lag_rows(orc, s, r, tau0 + rows)
+    T = oracle_T(orc, z, sg, n, p0, n_dop)
+    A, sc = orc.caf(s, r, tau0, n_tau, p0, n_dop, rows=rows)
+    return (s, r, n, tau0, n_tau, p0, n_dop, rows), T, A, sc
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_twiddle_sign_half_rounding_dc_rows(nd, dc65536, prec):
+    (s, r, n, tau0, n_tau, p0, n_dop, rows), Tref, Aref, sc = dc65536
+    plan, _ = nd.get_plan(prec, n, n_tau, p0, n_dop)
+    name = nd.plan_name(prec, plan)
+    assert name.startswith(SPLIT_PREFIX), name
+    _, T = nd.dbg_split(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=prec, lag=False)
+    eT = rel_err(T.cpu().numpy()[rows], Tref, sc)
+    A = nd.caf(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=prec).cpu().numpy()
+    eA = rel_err(A[rows], Aref, sc)
+    log("DC rows, plan", name, "T half l1-relative error", eT, "whole cell", eA)
+    # the twiddle-sign half alone within half the FP32 budget; the cell within the form's
+    assert eT <= 5e-6
+    assert eA <= TOL[prec]

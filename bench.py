@@ -149,6 +149,54 @@ def bench_batched(nd, tune, synth, torch, args):
         del g, bp
     res["speedup_bf16x2_vs_fp32"] = res["fp32"]["ms_per_batch"] / res["bf16x2"]["ms_per_batch"]
     tune.reset()
+    # the same batch with the CPI descriptors in device memory (no host preparation), its
+    # planning kernel inside the replayed graph
+    from paper_1402_0532_amd import _lib
+
+    lib = _lib.load()
+    arr = (_lib.NdftCpi * len(descs))()
+    for k, d in enumerate(descs):
+        for f in nd.CPI_FIELDS:
+            setattr(arr[k], f, int(d[f]))
+    table = nd.cpi_table(descs)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res["device_descriptors"] = {}
+    for form in ("fp32", "bf16x2"):
+        prec = nd.PRECISIONS[form]
+        # a workspace that fits the layout of any plan at the default chunk
+        need = 0
+        for p in range(nd.plan_count(prec)):
+            nd.set_plan(prec, p, 0)
+            need = max(need, int(lib.ndft_caf_batched_workspace(arr, len(descs), prec, 0)))
+        nd.set_plan(prec, -1, 0)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        run = lambda: nd.caf_batched_dev(s_pool, r_pool, out, table, prec=prec, ws=ws)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            run()
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=st):
+            run()
+        g.replay()
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 4)
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        lib.ndft_caf_batched_dev_status(nd._ptr(ws), nd._ptr(status), nd._stream_handle())
+        torch.cuda.synchronize()
+        plan_id = int(ws[12:16].view(torch.int32).item())
+        res["device_descriptors"][form] = {
+            "ms_per_batch": ms, "cells_per_s": cells / (ms * 1e-3), "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
+            "plan": nd.plan_name(prec, plan_id - 100 * prec), "status": int(status.item())}
+        del g, ws
     return res
 
 
@@ -289,32 +337,40 @@ def bench_other_surfaces(nd, synth, torch, args):
 
 
 def bench_nfft(nd, torch, args):
-    """Batched NFFT (Section 3): 32 Mi points as 4096 rows of N = 8192 (one row per
-    work-group) and as 131072 rows of N = 256 (32 rows per work-group)."""
+    """Batched NFFT (Section 3), both readings of Eq. (10): 32 Mi points as 4096 rows of
+    N = 8192 (one row per work-group), as 131072 rows of N = 256 (32 rows per work-group),
+    and as 32 rows of N = 2^20 (the top levels over global memory)."""
     res = {}
     lib = nd._lib.load()
-    for rows, n in ((4096, 8192), (131072, 256)):
+    for rows, n in ((4096, 8192), (131072, 256), (32, 1 << 20)):
         g = torch.Generator(device="cuda").manual_seed(5)
         x = torch.complex(torch.randn(rows, n, device="cuda", generator=g),
                           torch.randn(rows, n, device="cuda", generator=g))
         out = torch.empty_like(x)
-        run = lambda: nd._lib.check(lib.ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, nd._stream_handle()))
-        for _ in range(max(3, args.warmup // 10)):
-            run()
-        torch.cuda.synchronize()
-        reps = max(5, args.steps)
-        e0, e1 = _events(torch)
-        e0.record()
-        for _ in range(reps):
-            run()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        hbm = 16.0 * rows * n  # read the rows, write the transforms (complex64)
-        res["%d x N=%d" % (rows, n)] = {"ms": ms, "transforms_per_s": rows / (ms * 1e-3),
-                                         "hbm_gb_per_s": hbm / (ms * 1e-3) / 1e9,
-                                         "hbm_frac_of_8tbs": hbm / (ms * 1e-3) / 8e12}
-        del x, out
+        wsb = int(lib.ndft_nfft_workspace(rows, n))
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+        for reading, name in ((0, "every_butterfly"), (1, "printed")):
+            run = lambda: nd._lib.check(lib.ndft_nfft(nd._ptr(x), nd._ptr(out), rows, n, reading,
+                                                      nd._ptr(ws) if wsb else None, wsb, nd._stream_handle()))
+            for _ in range(max(3, args.warmup // 10)):
+                run()
+            torch.cuda.synchronize()
+            reps = max(5, args.steps)
+            e0, e1 = _events(torch)
+            e0.record()
+            for _ in range(reps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            # read the rows, write the transforms (complex64); long rows: each top level
+            # reads and writes the rows once more
+            levels = max(0, int(math.log2(n)) - 13)
+            hbm = 16.0 * rows * n * (1 + levels)
+            res["%d x N=%d %s" % (rows, n, name)] = {
+                "ms": ms, "transforms_per_s": rows / (ms * 1e-3), "hbm_gb_per_s": hbm / (ms * 1e-3) / 1e9,
+                "hbm_frac_of_8tbs": hbm / (ms * 1e-3) / 8e12}
+        del x, out, ws
     return res
 
 
@@ -370,7 +426,10 @@ def main():
     ap.add_argument("--plan", action="append", default=[], metavar="FORM=NAME:KSPLIT",
                     help="force a tile plan and split count for a form (no autotuning for it)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched (64 CPIs) and adjoint (N=8192) sections")
+                    help="skip every extra section (same as --extras '')")
+    ap.add_argument("--extras", default="config2,batched,adjoint,surfaces,robustness,nfft",
+                    help="extra sections to run (comma list of config2, batched, adjoint, surfaces, "
+                         "robustness, nfft)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -545,12 +604,18 @@ def main():
             results[form]["err_rows_checked"] = int(len(allrows))
 
     extras = {}
-    if not args.no_extras:
+    want = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    if "config2" in want:
         extras["config2"] = bench_config2(nd, synth, torch, args)
+    if "batched" in want:
         extras["batched"] = bench_batched(nd, tune, synth, torch, args)
+    if "adjoint" in want:
         extras["adjoint"] = bench_adjoint(nd, synth, torch, args)
+    if "surfaces" in want:
         extras.update(bench_other_surfaces(nd, synth, torch, args))
+    if "robustness" in want:
         extras["robustness"] = bench_robustness(nd, synth, torch, args)
+    if "nfft" in want:
         extras["nfft"] = bench_nfft(nd, torch, args)
 
     main_res = results[args.form]

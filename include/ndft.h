@@ -115,17 +115,29 @@ ndft_status ndft_caf_noalloc(const ndft_c64 *surv, const ndft_c64 *ref, int64_t 
                              void *stream);
 
 /* ---------------------------------------------------------------------------------
- * NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT with the twiddle
- * product of every butterfly replaced by the operator of Eq. (6),
- *   X[k] = E[k] + O[k] (x) W_n^k,  X[k + n/2] = E[k] - O[k] (x) W_n^k,
- * E / O the NFFTs of the even / odd samples, recursively down to single samples
- * (W_n^0 = 1 included). Its values differ from the NDFT of Eq. (7) (the operator is
- * not linear). FP32, evaluated butterfly by butterfly in the recursion's operations;
- * twiddles are e^{-j 2 pi m / n} rounded once to FP32, exact at the quadrant points.
- * x, X: [batch][n] complex64 device pointers (X may not alias x); n a power of two,
- * 1 <= n <= 8192; batch >= 0. No workspace. Returns NDFT_E_INVAL otherwise.
+ * NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT whose butterflies carry
+ * the operator of Eq. (6), E / O the transforms of the even / odd samples, recursively
+ * down to single samples. Two readings of the printed equation (`reading`):
+ *   NDFT_NFFT_EVERY_BUTTERFLY: every butterfly's twiddle product is the operator,
+ *     X[k] = E[k] + O[k] (x) W_n^k,  X[k + n/2] = E[k] - O[k] (x) W_n^k (W_n^0 = 1
+ *     included): the multiplication-free transform the text describes;
+ *   NDFT_NFFT_PRINTED: the twiddle in front of the odd half is an ordinary complex
+ *     product, X[k] = E[k] + W_n^k O[k], and the operator sits in the sums, whose
+ *     length-1 terms at the bottom are x (x) 1 (so the result is the DFT of x + csgn(x)).
+ * Either way the values differ from the NDFT of Eq. (7) for n > 4 (the operator is not
+ * linear). FP32, evaluated butterfly by butterfly in the recursion's operations (products
+ * and sums rounded one by one); twiddles are e^{-j 2 pi m / n} rounded once to FP32, exact
+ * at the quadrant points. x, X: [batch][n] complex64 device pointers (X may not alias x);
+ * n a power of two, 1 <= n <= 2^24; batch >= 0. Rows longer than 8192 need the workspace
+ * of ndft_nfft_workspace (ping-pong rows and a twiddle table; 0 otherwise, and for invalid
+ * arguments). Returns NDFT_E_INVAL for invalid arguments, NDFT_E_WORKSPACE for a missing
+ * or small workspace.
  * ------------------------------------------------------------------------------- */
-ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, void *stream);
+#define NDFT_NFFT_EVERY_BUTTERFLY 0
+#define NDFT_NFFT_PRINTED 1
+size_t ndft_nfft_workspace(int64_t batch, int64_t n);
+ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int32_t reading, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * The Eq. (12b) surface of Section 4: the lag product of Eq. (6), then the ordinary DFT,
@@ -134,8 +146,8 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
  * ndft_caf. The outer transform is linear and is computed as a decimated DFT (length-L
  * FFTs, L the largest power of two dividing n up to 512, then n / L terms per requested
  * bin), in FP32: prec must be NDFT_FP32 (NDFT_BF16X2 / NDFT_FP8 return
- * NDFT_E_UNSUPPORTED). ndft_caf12b_workspace returns the bytes of partial surfaces
- * (0 when none are needed, and for invalid arguments); ws may be NULL when it is 0.
+ * NDFT_E_UNSUPPORTED). ndft_caf12b_workspace returns the bytes of the transform's scratch
+ * (the inputs with their signs, or partial surfaces; 0 for invalid arguments).
  * Errors and stream as for ndft_caf.
  * ------------------------------------------------------------------------------- */
 size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
@@ -197,6 +209,33 @@ ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_p
                                      void *ws, size_t ws_bytes, ndft_batch *batch);
 ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool, const ndft_c64 *ref_pool,
                              ndft_c64 *out_pool, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Device-described batches: the same surfaces, with the CPI descriptors in DEVICE memory
+ * (cpis_dev[n_cpi], 8-byte aligned; 1 <= n_cpi <= 4096) and no host-side preparation.
+ * A planning kernel reads the descriptors, lays out `ws` as ndft_caf_batched_prepare
+ * would for the same descriptors, plan and default chunk, doubling the sample chunk while
+ * the partial sums do not fit ws_bytes (fewer chunks: the same surfaces up to rounding
+ * order), and the batched kernels follow on `stream`. The call enqueues kernels only (no copies, no allocation, no synchronization),
+ * so descriptors and pools may change between replays of a captured graph. The tile plan
+ * is the ndft_set_plan override when it has a batched form, else a fixed choice per
+ * precision.
+ * Errors found on the host (pointers, alignment, n_cpi, workspace smaller than the
+ * tables) return before anything is enqueued. Errors only the device can see (an invalid
+ * descriptor: the ndft_caf limits or a negative offset; a workspace too small even with
+ * one chunk per surface) leave every output untouched and are reported by
+ * ndft_caf_batched_dev_status, which copies the batch's status (0 = ran, else an
+ * ndft_status value) to the caller's device int32 on `stream`. Pool bounds are the
+ * caller's: offsets must keep every surface inside its pool.
+ * ndft_caf_batched_dev_workspace: a size that fits any n_cpi CPIs with n <= max_n,
+ * n_tau <= max_tau and n_dop <= max_dop at the default chunk (0 for invalid maxima).
+ * ------------------------------------------------------------------------------- */
+size_t ndft_caf_batched_dev_workspace(int32_t n_cpi, int64_t max_n, int64_t max_tau, int64_t max_dop,
+                                      ndft_prec prec);
+ndft_status ndft_caf_batched_dev(const ndft_c64 *surv_pool, const ndft_c64 *ref_pool, ndft_c64 *out_pool,
+                                 const ndft_cpi *cpis_dev, int32_t n_cpi, ndft_prec prec, void *ws,
+                                 size_t ws_bytes, void *stream);
+ndft_status ndft_caf_batched_dev_status(const void *ws, int32_t *status, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * Adjoint of the surface with respect to the reference (and optionally the

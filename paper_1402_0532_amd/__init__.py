@@ -19,7 +19,7 @@ FP8 = 2
 PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp8": FP8}
 
 __all__ = [
-    "FP32", "BF16X2", "FP8", "forward", "nfft", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "BatchPlan",
+    "FP32", "BF16X2", "FP8", "forward", "nfft", "caf", "caf12b", "caf12c", "caf_backward", "caf_batched", "caf_batched_dev", "BatchPlan",
     "pack_batch",
     "NDFTCaf", "dbg_signs", "dbg_split", "plan_count", "plan_name", "set_plan", "get_plan",
     "prof_enable", "prof_read", "version",
@@ -122,16 +122,25 @@ def caf(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop:
     return out
 
 
-def nfft(x: torch.Tensor) -> torch.Tensor:
-    """NFFT of Section 3 (radix-2 DIT, twiddle products by Eq. (6)) of each row of
-    x [batch, n] complex64, n a power of two up to 8192; FP32."""
+NFFT_EVERY_BUTTERFLY = 0
+NFFT_PRINTED = 1
+
+
+def nfft(x: torch.Tensor, reading: int = NFFT_EVERY_BUTTERFLY, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """NFFT of Section 3 (radix-2 DIT with the operator of Eq. (6) in the butterflies) of
+    each row of x [batch, n] complex64, n a power of two up to 2^24; FP32. reading:
+    NFFT_EVERY_BUTTERFLY (every twiddle product by Eq. (6)) or NFFT_PRINTED (ordinary
+    twiddle products, the operator in the length-1 sums)."""
     lib = _lib.load()
     if x.dim() == 1:
-        return nfft(x[None])[0]
+        return nfft(x[None], reading, ws)[0]
     _check_c64(x, "x", 2)
     batch, n = x.shape
     out = torch.empty_like(x)
-    _lib.check(lib.ndft_nfft(_ptr(x), _ptr(out), batch, n, _stream_handle()), "ndft_nfft")
+    nbytes = int(lib.ndft_nfft_workspace(batch, n))
+    ws = _ws_for(ws, nbytes, x.device)
+    _lib.check(lib.ndft_nfft(_ptr(x), _ptr(out), batch, n, int(reading), _ptr(ws) if nbytes else None, nbytes,
+                             _stream_handle()), "ndft_nfft")
     return out
 
 
@@ -291,6 +300,46 @@ class BatchPlan:
 
 def caf_batched(plan: BatchPlan, surv_pool, ref_pool, out_pool):
     return plan.run(surv_pool, ref_pool, out_pool)
+
+
+CPI_FIELDS = ("n", "surv_off", "ref_off", "out_off", "tau0", "n_tau", "p0", "n_dop")
+
+
+def cpi_table(descs, device="cuda") -> torch.Tensor:
+    """CPI descriptors as the device table ndft_caf_batched_dev reads: int64 [n_cpi, 8]."""
+    return torch.tensor([[int(d[f]) for f in CPI_FIELDS] for d in descs], dtype=torch.int64, device=device)
+
+
+def caf_batched_dev_workspace_bytes(n_cpi: int, max_n: int, max_tau: int, max_dop: int, prec=FP32) -> int:
+    return int(_lib.load().ndft_caf_batched_dev_workspace(int(n_cpi), int(max_n), int(max_tau), int(max_dop),
+                                                          _prec(prec)))
+
+
+def caf_batched_dev(surv_pool, ref_pool, out_pool, cpis_dev: torch.Tensor, prec=FP32, ws: torch.Tensor = None,
+                    status: torch.Tensor = None) -> torch.Tensor:
+    """Batched surfaces from device-resident descriptors (cpis_dev int64 [n_cpi, 8], see
+    cpi_table) with no host-side preparation; ws: a uint8 device buffer (its size bounds
+    the work-item chunking). status (optional int32 [1] device tensor) receives the
+    batch's status after the call (0 = ran); nothing is synchronized here."""
+    lib = _lib.load()
+    for t, name in ((surv_pool, "surv_pool"), (ref_pool, "ref_pool"), (out_pool, "out_pool")):
+        _check_c64(t, name, 1)
+    if cpis_dev.dtype != torch.int64 or cpis_dev.dim() != 2 or cpis_dev.shape[1] != 8 or not cpis_dev.is_contiguous():
+        raise ValueError("cpis_dev must be a contiguous int64 [n_cpi, 8] tensor")
+    if ws is None or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 device tensor")
+    devs = {surv_pool.device, ref_pool.device, out_pool.device, cpis_dev.device, ws.device}
+    if len(devs) != 1:
+        raise ValueError("pools, descriptors and workspace must be on one device")
+    st = lib.ndft_caf_batched_dev(_ptr(surv_pool), _ptr(ref_pool), _ptr(out_pool), _ptr(cpis_dev),
+                                  int(cpis_dev.shape[0]), _prec(prec), _ptr(ws), ws.numel(), _stream_handle())
+    _lib.check(st, "ndft_caf_batched_dev")
+    if status is not None:
+        if status.dtype != torch.int32 or status.numel() < 1 or status.device != ws.device:
+            raise ValueError("status must be an int32 device tensor")
+        _lib.check(lib.ndft_caf_batched_dev_status(_ptr(ws), _ptr(status), _stream_handle()),
+                   "ndft_caf_batched_dev_status")
+    return out_pool
 
 
 def pack_batch(cpis):

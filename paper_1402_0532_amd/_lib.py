@@ -23,7 +23,8 @@ SIGNATURES = {
     "ndft_caf_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P, _SZ, _P]),
     "ndft_caf_noalloc": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P]),
-    "ndft_nfft": (_ST, [_P, _P, _I64, _I64, _P]),
+    "ndft_nfft_workspace": (_SZ, [_I64, _I64]),
+    "ndft_nfft": (_ST, [_P, _P, _I64, _I64, _I32, _P, _SZ, _P]),
     "ndft_caf12b_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf12b": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _I32, _P, _SZ, _P]),
     "ndft_caf12c_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
@@ -31,6 +32,9 @@ SIGNATURES = {
     "ndft_caf_batched_workspace": (_SZ, [_P, _I32, _I32, _I32]),
     "ndft_caf_batched_prepare": (_ST, [_P, _I32, _I32, _I32, _P, _SZ, _P]),
     "ndft_caf_batched": (_ST, [_P, _P, _P, _P, _P, _SZ, _P]),
+    "ndft_caf_batched_dev_workspace": (_SZ, [_I32, _I64, _I64, _I64, _I32]),
+    "ndft_caf_batched_dev": (_ST, [_P, _P, _P, _P, _I32, _I32, _P, _SZ, _P]),
+    "ndft_caf_batched_dev_status": (_ST, [_P, _P, _P]),
     "ndft_caf_backward_workspace": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "ndft_caf_backward": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P, _SZ, _P]),
     "ndft_dbg_signs": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P]),

@@ -16,9 +16,11 @@
 
 #include "ndft.h"
 #include "ndft_backward.hpp"
+#include "ndft_batch.hpp"
 #include "ndft_contract.hpp"
 #include "ndft_debug.hpp"
 #include "ndft_dft12b.hpp"
+#include "ndft_dft512.hpp"
 #include "ndft_nfft.hpp"
 #include "ndft_signsplit.hpp"
 #include "ndft_surface_bf16.hpp"
@@ -307,6 +309,7 @@ void set_kernel_attributes()
 
 struct Dft12bLaunch {
     int lb, M, MB, n_mg, tb, n_coarse;
+    int fast;         // L = 512: dft512_kernel (a work-group per delay row, no partials)
     size_t dyn_bytes; // the twiddle table (dynamic LDS)
     size_t ws_bytes;  // partial surfaces when a delay takes more than one work-group
 };
@@ -335,6 +338,7 @@ struct Launch {
     int fits;          // the twiddle table fits the plan's dynamic LDS (else NDFT_E_UNSUPPORTED)
     Dft12bLaunch dft;  // fft_d plans: the twiddle half's decimated FFT
     size_t dft_off;    // fft_d plans: offset of its partial surfaces in the workspace
+    size_t absmax_off; // FP8 combined plans: two words of data maxima (0: none)
 };
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -445,7 +449,9 @@ int64_t lsum_groups(const Launch &L)
 // the Eq. (12b) surface: decimated DFT of the lag-product rows
 // ------------------------------------------------------------------------------------
 
-Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop)
+// whole_rows: allow the whole-row kernel (the Eq. (12c) signs stay on the phase-group
+// kernel, which measured faster for them)
+Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop, bool whole_rows = true)
 {
     Dft12bLaunch L;
     std::memset(&L, 0, sizeof(L));
@@ -456,7 +462,13 @@ Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop)
     int exact = 0;
     choose_table(n, 65536, &L.tb, &L.n_coarse, &exact);
     L.dyn_bytes = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
-    L.ws_bytes = L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0;
+    // the whole-row kernel wherever it has enough rows to fill the device (or a row is a
+    // single group of transforms anyway)
+    L.fast = whole_rows && L.lb == 9 && n_dop <= kD5MaxBins && (n_tau >= 128 || L.M <= kD5Group) ? 1 : 0;
+    if (L.fast) L.n_mg = 1;
+    // whole-row kernel: the signed inputs s4[n], r4[2 n]; else the partial surfaces
+    L.ws_bytes = L.fast ? align256((size_t)n * sizeof(float4)) + align256((size_t)2 * n * sizeof(float4))
+                        : (L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0);
     return L;
 }
 
@@ -551,9 +563,13 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
     }
     if (L.plan->fft_d) {
-        L.dft = plan_dft12b(n, n_cols, n_bins);
+        L.dft = plan_dft12b(n, n_cols, n_bins, !lin);
         L.dft_off = L.ws_bytes;
         L.ws_bytes += L.dft.ws_bytes;
+    }
+    if (prec == NDFT_FP8 && !L.plan->lag_kfn) { // the e4m3 data exponent of the combined kernel
+        L.absmax_off = L.ws_bytes;
+        L.ws_bytes += 256;
     }
     return L;
 }
@@ -616,9 +632,21 @@ ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, i
     return check_launch();
 }
 
+// FP8 combined kernel: the largest |re| + |im| of each input (one word each) into the
+// workspace slot, cleared first by a kernel of its own (no memset in the stream).
+ndft_status launch_absmax(unsigned *w, const float2 *a, int64_t na, const float2 *b, int64_t nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(absmax_zero_kernel, dim3(1), dim3(64), 0, s, w, 2);
+    const auto grid = [](int64_t c) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(c, 256), 1024))); };
+    hipLaunchKernelGGL(absmax_kernel, grid(na), dim3(256), 0, s, a, (long long)na, w);
+    if (b) hipLaunchKernelGGL(absmax_kernel, grid(nb), dim3(256), 0, s, b, (long long)nb, w + 1);
+    return check_launch();
+}
+
 ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const float4 *r4, long long col_stride,
                             int64_t n, int64_t n_cols, int64_t tau0, float4 *partial, hipStream_t stream,
-                            uint4 *planes = nullptr, const float2 *s_raw = nullptr, const float2 *r_raw = nullptr)
+                            uint4 *planes = nullptr, const float2 *s_raw = nullptr, const float2 *r_raw = nullptr,
+                            const unsigned *absmax = nullptr)
 {
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
@@ -645,6 +673,8 @@ ndft_status launch_contract(const Launch &L, int prod, const float4 *s4, const f
     P.n_bases_pad = L.n_bases_pad;
     P.n_cols_pad = L.n_cols_pad;
     P.partial = partial;
+    P.absmax = absmax;
+    if (L.prec == NDFT_FP8 && !absmax) return NDFT_E_INVAL;
     void *args[] = {&P};
     size_t shmem = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
     if ((int)shmem > plan_max_dynamic(*L.plan)) return NDFT_E_UNSUPPORTED; // FP8 stages leave less LDS
@@ -823,6 +853,12 @@ const void *dft12b_fn(int lb)
     return fns[lb];
 }
 
+template <int SRC>
+const void *dft512_fn()
+{
+    return reinterpret_cast<const void *>(&dft512_kernel<SRC>);
+}
+
 std::once_flag g_dft_attr_once;
 hipError_t g_dft_attr_err = hipSuccess;
 
@@ -840,6 +876,10 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
                 hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
                 if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
             }
+        for (const void *fn : {dft512_fn<DFT_LAG>(), dft512_fn<DFT_SIGNS>(), dft512_fn<DFT_LIN_SIGNS>()}) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
+        }
     });
     if (g_dft_attr_err != hipSuccess) return NDFT_E_HIP;
     if (L.n_mg > 1 && cdiv((long long)n_tau * n_dop, 256) > (long long)UINT32_MAX) return NDFT_E_INVAL;
@@ -860,6 +900,25 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
     P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : A;
     P.accumulate = L.n_mg > 1 ? 0 : (accumulate ? 1 : 0);
     void *args[] = {&P};
+    if (L.fast) {
+        // the inputs with their exact signs (the reference after n zeros), then two
+        // work-groups per compute unit, each taking whole delay rows in turn
+        float4 *s4 = static_cast<float4 *>(ws);
+        float4 *r4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + align256((size_t)n * sizeof(float4)));
+        ndft_status st = launch_prep(surv, s4, n, 1, n, 0, 1.0f, s);
+        if (st == NDFT_OK) st = launch_prep(ref, r4, n, 1, 2 * n, n, 1.0f, s);
+        if (st != NDFT_OK) return st;
+        P.s4 = s4;
+        P.r4 = r4;
+        const dim3 grid((unsigned)std::min<int64_t>(n_tau, 2LL * device_cu_count()));
+        const void *fn = src == DFT_SIGNS ? dft512_fn<DFT_SIGNS>()
+                         : (src == DFT_LIN_SIGNS ? dft512_fn<DFT_LIN_SIGNS>() : dft512_fn<DFT_LAG>());
+        ProfScope prof(s);
+        hipError_t e = hipLaunchKernel(fn, grid, dim3(kD5Threads), args, L.dyn_bytes, s);
+        prof.stop();
+        if (e != hipSuccess) return NDFT_E_HIP;
+        return check_launch();
+    }
     // about eight work-groups per compute unit, each looping over its delays (the table
     // is built once per work-group)
     const int64_t ydim = std::max<int64_t>(1, cdiv(8LL * device_cu_count(), L.n_mg));
@@ -905,7 +964,8 @@ struct BatchGeom {
     int table_bytes = 0;
     int max_red_blocks = 1;
     int max_prep_blocks = 1;
-    size_t off_params = 0, off_red = 0, off_outoff = 0, off_prep = 0, off_items = 0, total = 0;
+    BatchRegions rg;
+    size_t total = 0;
     std::vector<ContractParams> params;
     std::vector<ReduceParams> red;
     std::vector<long long> outoff;
@@ -913,128 +973,103 @@ struct BatchGeom {
     std::vector<int4> items;
 };
 
-constexpr int kMaxBatch = 16384;
-constexpr int kDefaultChunk = 4096;
-
-bool cpi_ok(const ndft_cpi &c)
+BatchPlanGeom batch_plan_geom(const Plan &P, int prec)
 {
-    return caf_args_ok(c.n, c.tau0, c.n_tau, c.n_dop) && c.surv_off >= 0 && c.ref_off >= 0 && c.out_off >= 0;
+    BatchPlanGeom g;
+    g.bt = P.bt;
+    g.lt = P.lt;
+    g.max_dynamic = plan_max_dynamic(P);
+    g.sign_scale = P.sign_scale;
+    g.fp8 = prec == NDFT_FP8 ? 1 : 0;
+    return g;
 }
 
-// Pick the plan (override or least summed cost), lay out the workspace and build the
-// tables; `base` is the workspace address (nullptr when only sizing).
-ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk, char *base, BatchGeom &G)
+// The plan of a batch: the override if it has a batched kernel, else the least summed
+// cost over the CPIs (padded cells times samples, scaled per plan).
+int batch_plan_choice(const ndft_cpi *cpis, int n_cpi, int prec)
 {
-    if (!cpis || n_cpi < 1 || n_cpi > kMaxBatch || chunk < 0) return NDFT_E_INVAL;
-    for (int c = 0; c < n_cpi; ++c)
-        if (!cpi_ok(cpis[c])) return NDFT_E_INVAL;
     const std::vector<Plan> &ps = plans(prec);
     int pi;
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         pi = g_plan_override[prec];
     }
-    if (pi < 0 || pi >= (int)ps.size() || !ps[pi].kfn_batched) {
-        double best = -1.0;
-        pi = 0;
-        for (int k = 0; k < (int)ps.size(); ++k) {
-            if (!ps[k].kfn_batched) continue;
-            double cost = 0.0;
-            for (int c = 0; c < n_cpi; ++c) {
-                int nb;
-                make_base_map(cpis[c].n, cpis[c].p0, cpis[c].n_dop, &nb);
-                double rows = (double)(cdiv(nb, ps[k].bt) * ps[k].bt);
-                double cols = (double)(cdiv(cpis[c].n_tau, ps[k].lt) * ps[k].lt);
-                cost += rows * cols * (double)cpis[c].n * ps[k].cost_scale;
-            }
-            if (best < 0 || cost < best * 0.999) {
-                best = cost;
-                pi = k;
-            }
+    if (pi >= 0 && pi < (int)ps.size() && ps[pi].kfn_batched) return pi;
+    double best = -1.0;
+    pi = 0;
+    for (int k = 0; k < (int)ps.size(); ++k) {
+        if (!ps[k].kfn_batched) continue;
+        double cost = 0.0;
+        for (int c = 0; c < n_cpi; ++c) {
+            int nb;
+            make_base_map(cpis[c].n, cpis[c].p0, cpis[c].n_dop, &nb);
+            double rows = (double)(cdiv(nb, ps[k].bt) * ps[k].bt);
+            double cols = (double)(cdiv(cpis[c].n_tau, ps[k].lt) * ps[k].lt);
+            cost += rows * cols * (double)cpis[c].n * ps[k].cost_scale;
+        }
+        if (best < 0 || cost < best * 0.999) {
+            best = cost;
+            pi = k;
         }
     }
-    const Plan &P = ps[pi];
+    return pi;
+}
+
+// Pick the plan, lay out the workspace (ndft_batch.hpp) and build the tables; `base` is
+// the workspace address (nullptr when only sizing).
+ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk, char *base, BatchGeom &G)
+{
+    if (!cpis || n_cpi < 1 || n_cpi > kMaxBatch || chunk < 0) return NDFT_E_INVAL;
+    for (int c = 0; c < n_cpi; ++c)
+        if (!cpi_valid(cpis[c])) return NDFT_E_INVAL;
+    const int pi = batch_plan_choice(cpis, n_cpi, prec);
+    const Plan &P = plans(prec)[pi];
+    const BatchPlanGeom g = batch_plan_geom(P, prec);
     G.plan = pi;
     G.chunk = (int)(cdiv(chunk > 0 ? chunk : kDefaultChunk, P.kgran) * P.kgran);
+    G.rg = batch_regions(n_cpi);
     G.params.resize(n_cpi);
     G.red.resize(n_cpi);
     G.outoff.resize(n_cpi);
     G.prep.resize(2 * n_cpi);
     G.items.clear();
-    std::vector<long long> cost;
-    size_t off = 256; // header
-    G.off_params = off;
-    off = align256(off + sizeof(ContractParams) * n_cpi);
-    G.off_red = off;
-    off = align256(off + sizeof(ReduceParams) * n_cpi);
-    G.off_outoff = off;
-    off = align256(off + sizeof(long long) * n_cpi);
-    G.off_prep = off;
-    off = align256(off + sizeof(PrepDesc) * 2 * n_cpi);
+    std::vector<CpiLayout> lay(n_cpi);
     int64_t total_items = 0;
     for (int c = 0; c < n_cpi; ++c) {
-        const ndft_cpi &d = cpis[c];
-        int nb;
-        BaseMap bm = make_base_map(d.n, d.p0, d.n_dop, &nb);
-        int tiles_b = (int)cdiv(nb, P.bt), tiles_l = (int)cdiv(d.n_tau, P.lt);
-        int ks = (int)cdiv(d.n, G.chunk);
-        total_items += (int64_t)tiles_b * tiles_l * ks;
+        if (!cpi_layout(cpis[c], g, G.chunk, lay[c])) return NDFT_E_UNSUPPORTED; // table beyond the LDS
+        total_items += lay[c].items;
     }
-    if (total_items > (int64_t)1 << 30) return NDFT_E_INVAL;
-    G.off_items = off;
-    off = align256(off + sizeof(int4) * (size_t)total_items);
+    if (total_items >= (int64_t)1 << 30) return NDFT_E_INVAL;
+    size_t off = balign(G.rg.items + sizeof(int4) * (size_t)total_items);
+    std::vector<long long> cost;
+    unsigned *absmax = base ? reinterpret_cast<unsigned *>(base + G.rg.absmax) : nullptr;
     for (int c = 0; c < n_cpi; ++c) {
         const ndft_cpi &d = cpis[c];
-        ContractParams &C = G.params[c];
-        std::memset(&C, 0, sizeof(C));
-        int nb;
-        C.bm = make_base_map(d.n, d.p0, d.n_dop, &nb);
-        C.n = (int)d.n;
-        C.n_cols = (int)d.n_tau;
-        C.tau0 = (int)d.tau0;
-        C.n_bases = nb;
-        choose_table(d.n, plan_max_dynamic(P), &C.tb, &C.n_coarse, &C.tw_exact);
-        G.table_bytes = std::max(G.table_bytes, (int)((C.n_coarse + (1 << C.tb)) * sizeof(float2)));
-        C.kchunk = G.chunk;
-        C.ksplit = (int)cdiv(d.n, G.chunk);
-        C.tiles_b = (int)cdiv(nb, P.bt);
-        C.tiles_l = (int)cdiv(d.n_tau, P.lt);
-        C.n_bases_pad = C.tiles_b * P.bt;
-        C.n_cols_pad = C.tiles_l * P.lt;
-        size_t s4_off = off;
-        off = align256(off + sizeof(float4) * (size_t)(d.n + kTailPad));
-        size_t r4_off = off;
-        off = align256(off + sizeof(float4) * (size_t)(2 * d.n + kTailPad));
-        size_t part_off = off;
-        off = align256(off + sizeof(float4) * (size_t)C.ksplit * C.n_cols_pad * C.n_bases_pad);
-        C.s4 = base ? reinterpret_cast<const float4 *>(base + s4_off) : nullptr;
-        C.r4 = base ? reinterpret_cast<const float4 *>(base + r4_off) : nullptr;
-        C.partial = base ? reinterpret_cast<float4 *>(base + part_off) : nullptr;
-        ReduceParams &R = G.red[c];
-        std::memset(&R, 0, sizeof(R));
-        R.partial = C.partial;
-        R.ksplit = C.ksplit;
-        R.n_cols_pad = C.n_cols_pad;
-        R.n_bases_pad = C.n_bases_pad;
-        R.n_cols = C.n_cols;
-        R.n_bases = nb;
-        R.bm = C.bm;
-        R.n = C.n;
-        R.p0n = (int)mod_n(d.p0, d.n);
-        R.n_bins = (int)d.n_dop;
+        CpiLayout &o = lay[c];
+        G.table_bytes = std::max(G.table_bytes, o.table_bytes);
+        const size_t s4_off = off, r4_off = off + o.s4_bytes, part_off = off + o.s4_bytes + o.r4_bytes;
+        off = part_off + o.part_bytes;
+        float4 *s4 = base ? reinterpret_cast<float4 *>(base + s4_off) : nullptr;
+        float4 *r4 = base ? reinterpret_cast<float4 *>(base + r4_off) : nullptr;
+        float4 *part = base ? reinterpret_cast<float4 *>(base + part_off) : nullptr;
+        o.C.s4 = s4;
+        o.C.r4 = r4;
+        o.C.partial = part;
+        o.C.absmax = g.fp8 && absmax ? absmax + 2 * c : nullptr;
+        o.R.partial = part;
+        G.params[c] = o.C;
+        G.red[c] = o.R;
         G.outoff[c] = (long long)d.out_off;
-        C.s_raw_off = (long long)d.surv_off;
-        C.r_raw_off = (long long)d.ref_off;
-        G.prep[2 * c] = PrepDesc{(long long)d.surv_off, base ? reinterpret_cast<float4 *>(base + s4_off) : nullptr,
-                                 (int)d.n, 0, (long long)(d.n + kTailPad), P.sign_scale};
-        G.prep[2 * c + 1] = PrepDesc{(long long)d.ref_off, base ? reinterpret_cast<float4 *>(base + r4_off) : nullptr,
-                                     (int)d.n, (int)d.n, (long long)(2 * d.n + kTailPad), P.sign_scale};
+        G.prep[2 * c] = PrepDesc{(long long)d.surv_off, s4, (int)d.n, 0, (long long)(d.n + kTailPad), P.sign_scale,
+                                 g.fp8 && absmax ? absmax + 2 * c : nullptr};
+        G.prep[2 * c + 1] = PrepDesc{(long long)d.ref_off, r4, (int)d.n, (int)d.n, (long long)(2 * d.n + kTailPad),
+                                     P.sign_scale, g.fp8 && absmax ? absmax + 2 * c + 1 : nullptr};
         G.max_prep_blocks = std::max(G.max_prep_blocks, (int)std::min<int64_t>(cdiv(2 * d.n + kTailPad, 256), 1024));
         G.max_red_blocks =
-            std::max(G.max_red_blocks, (int)std::min<int64_t>(cdiv((int64_t)C.n_cols * nb, 256), 4096));
-        for (int tl = 0; tl < C.tiles_l; ++tl)
-            for (int tbi = 0; tbi < C.tiles_b; ++tbi)
-                for (int kc = 0; kc < C.ksplit; ++kc) {
+            std::max(G.max_red_blocks, (int)std::min<int64_t>(cdiv((int64_t)o.C.n_cols * o.C.n_bases, 256), 4096));
+        for (int tl = 0; tl < o.C.tiles_l; ++tl)
+            for (int tbi = 0; tbi < o.C.tiles_b; ++tbi)
+                for (int kc = 0; kc < o.C.ksplit; ++kc) {
                     G.items.push_back(make_int4(c, tbi, tl, kc));
                     cost.push_back(std::min<long long>(G.chunk, d.n - (long long)kc * G.chunk));
                 }
@@ -1048,6 +1083,15 @@ ndft_status batch_geometry(const ndft_cpi *cpis, int n_cpi, int prec, int chunk,
     G.items.swap(sorted);
     G.total = off;
     return NDFT_OK;
+}
+
+// The plan of a device-planned batch (descriptors unknown on the host): the override if it
+// has a batched kernel, else the least cost on a representative CPI (N = 8192, 256
+// delays, bins -512..511).
+int dev_batch_plan(int prec)
+{
+    const ndft_cpi rep = {8192, 0, 0, 0, 0, 256, -512, 1024};
+    return batch_plan_choice(&rep, 1, prec);
 }
 
 std::atomic<unsigned long long> g_batch_seq{0};
@@ -1130,7 +1174,11 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     float4 *x4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
     st = launch_prep(reinterpret_cast<const float2 *>(x), x4, n, batch, n + kTailPad, 0, L.plan->sign_scale, s);
     if (st != NDFT_OK) return st;
-    st = launch_contract(L, PROD_IDENTITY, x4, nullptr, n + kTailPad, n, batch, 0, part, s);
+    unsigned *amax = L.absmax_off ? reinterpret_cast<unsigned *>(static_cast<char *>(ws) + L.absmax_off) : nullptr;
+    if (amax && (st = launch_absmax(amax, reinterpret_cast<const float2 *>(x), batch * n, nullptr, 0, s)) != NDFT_OK)
+        return st;
+    st = launch_contract(L, PROD_IDENTITY, x4, nullptr, n + kTailPad, n, batch, 0, part, s, nullptr, nullptr, nullptr,
+                         amax);
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, batch, k0, k_count, reinterpret_cast<float2 *>(X), s);
 }
@@ -1177,8 +1225,12 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     } else {
         uint4 *planes =
             L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
+        unsigned *amax = L.absmax_off ? reinterpret_cast<unsigned *>(static_cast<char *>(ws) + L.absmax_off) : nullptr;
+        if (amax && (st = launch_absmax(amax, reinterpret_cast<const float2 *>(surv), n,
+                                        reinterpret_cast<const float2 *>(ref), n, s)) != NDFT_OK)
+            return st;
         st = launch_contract(L, PROD_LAG, s4, r4, 0, n, n_tau, tau0, part, s, planes,
-                             reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref));
+                             reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), amax);
     }
     if (st != NDFT_OK) return st;
     return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
@@ -1259,29 +1311,78 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
                       reinterpret_cast<hipStream_t>(stream));
 }
 
-ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, void *stream)
+size_t ndft_nfft_workspace(int64_t batch, int64_t n)
 {
-    if (n < 1 || n > kNfftMaxN || (n & (n - 1)) != 0 || batch < 0) return NDFT_E_INVAL;
+    if (n < 1 || n > kNfftMaxLong || (n & (n - 1)) != 0 || batch < 0) return 0;
+    if (n <= kNfftMaxN || batch == 0) return 0;
+    // ping-pong rows for the top levels, then the twiddle table W_n^m, m < n / 2
+    return align256((size_t)batch * n * sizeof(float2)) + align256((size_t)(n / 2) * sizeof(float2));
+}
+
+ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int32_t reading, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > kNfftMaxLong || (n & (n - 1)) != 0 || batch < 0) return NDFT_E_INVAL;
+    if (reading != NDFT_NFFT_EVERY_BUTTERFLY && reading != NDFT_NFFT_PRINTED) return NDFT_E_INVAL;
     if (batch == 0) return NDFT_OK;
     if (!x || !X || !aligned(x, 8) || !aligned(X, 8)) return NDFT_E_INVAL;
+    if (batch * n > ((int64_t)1 << 40)) return NDFT_E_INVAL;
+    const size_t need = ndft_nfft_workspace(batch, n);
+    ndft_status st = ws_ok(ws, ws_bytes, need);
+    if (st != NDFT_OK) return st;
     static std::once_flag once;
     static hipError_t attr = hipSuccess;
     std::call_once(once, [] {
-        attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&nfft_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(kNfftMaxN + kNfftMaxN / 2) * (int)sizeof(float2));
+        for (const void *fn : {reinterpret_cast<const void *>(&nfft_kernel<false>),
+                               reinterpret_cast<const void *>(&nfft_kernel<true>)}) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)(kNfftMaxN + kNfftMaxN / 2) * (int)sizeof(float2));
+            if (e != hipSuccess && attr == hipSuccess) attr = e;
+        }
     });
     if (attr != hipSuccess) return NDFT_E_HIP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // 8192 / n rows per work-group at a time; the row groups loop inside, at most about
-    // eight work-groups per compute unit
-    const int rpb = (int)(kNfftMaxN / n);
-    const size_t shmem = ((size_t)rpb * n + n / 2) * sizeof(float2);
-    const int64_t grid = std::min<int64_t>(cdiv(batch, rpb), 8LL * device_cu_count());
+    const bool outer = reading == NDFT_NFFT_PRINTED;
+    const float2 *xin = reinterpret_cast<const float2 *>(x);
+    float2 *Xo = reinterpret_cast<float2 *>(X);
+    // rows of up to 8192 samples: in LDS, 8192 / L rows per work-group at a time; longer
+    // rows: their 2^lev decimated sequences of 8192 samples in LDS, then lev top levels
+    int lev = 0;
+    while ((kNfftMaxN << lev) < n) ++lev;
+    const int L = (int)std::min<int64_t>(n, kNfftMaxN);
+    const int sub = 1 << lev;
+    const long long rows = (long long)batch * sub;
+    float2 *buf = need ? static_cast<float2 *>(ws) : nullptr;
+    float2 *tw = need ? reinterpret_cast<float2 *>(static_cast<char *>(ws) + align256((size_t)batch * n * sizeof(float2)))
+                      : nullptr;
+    // the last top level writes X: the LDS stage writes X after an even number of levels
+    float2 *first = (lev % 2 == 0) ? Xo : buf;
+    const int rpb = kNfftMaxN / L;
+    const size_t shmem = ((size_t)rpb * L + L / 2) * sizeof(float2);
+    const int64_t grid = std::min<int64_t>(cdiv(rows, rpb), 8LL * device_cu_count());
     ProfScope prof(s);
-    hipLaunchKernelGGL(nfft_kernel, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s,
-                       reinterpret_cast<const float2 *>(x), reinterpret_cast<float2 *>(X), (long long)batch, (int)n,
-                       rpb);
+    if (outer)
+        hipLaunchKernelGGL(nfft_kernel<true>, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s, xin, first, rows, L,
+                           rpb, sub, (long long)n);
+    else
+        hipLaunchKernelGGL(nfft_kernel<false>, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s, xin, first, rows,
+                           L, rpb, sub, (long long)n);
+    if ((st = check_launch()) != NDFT_OK) return st;
+    if (lev > 0) {
+        hipLaunchKernelGGL(nfft_table_kernel, dim3((unsigned)cdiv(n / 2, 256)), dim3(256), 0, s, tw, (int)n);
+        const unsigned cgrid = (unsigned)std::min<int64_t>(cdiv(batch * (n / 2), 256), 8LL * device_cu_count());
+        float2 *src = first;
+        for (int S = sub / 2; S >= 1; S /= 2) {
+            float2 *dst = src == Xo ? buf : Xo;
+            if (outer)
+                hipLaunchKernelGGL(nfft_combine_kernel<true>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
+                                   (long long)batch, (int)n, S);
+            else
+                hipLaunchKernelGGL(nfft_combine_kernel<false>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
+                                   (long long)batch, (int)n, S);
+            src = dst;
+        }
+    }
     prof.stop();
     return check_launch();
 }
@@ -1415,7 +1516,7 @@ ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_p
     unsigned long long tag = (++g_batch_seq) ^
         ((unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() << 20);
     // host image of the tables (header .. items), copied in one blocking transfer
-    std::vector<char> img(G.off_items + sizeof(int4) * G.items.size(), 0);
+    std::vector<char> img(G.rg.items + sizeof(int4) * G.items.size(), 0);
     BatchHeader hdr;
     std::memset(&hdr, 0, sizeof(hdr));
     hdr.counter = 0;
@@ -1423,12 +1524,13 @@ ndft_status ndft_caf_batched_prepare(const ndft_cpi *cpis, int32_t n_cpi, ndft_p
     hdr.n_cpi = n_cpi;
     hdr.plan_id = (int)prec * 100 + G.plan;
     hdr.tag = tag;
+    hdr.status = 0;
     std::memcpy(img.data(), &hdr, sizeof(hdr));
-    std::memcpy(img.data() + G.off_params, G.params.data(), sizeof(ContractParams) * n_cpi);
-    std::memcpy(img.data() + G.off_red, G.red.data(), sizeof(ReduceParams) * n_cpi);
-    std::memcpy(img.data() + G.off_outoff, G.outoff.data(), sizeof(long long) * n_cpi);
-    std::memcpy(img.data() + G.off_prep, G.prep.data(), sizeof(PrepDesc) * 2 * n_cpi);
-    std::memcpy(img.data() + G.off_items, G.items.data(), sizeof(int4) * G.items.size());
+    std::memcpy(img.data() + G.rg.params, G.params.data(), sizeof(ContractParams) * n_cpi);
+    std::memcpy(img.data() + G.rg.red, G.red.data(), sizeof(ReduceParams) * n_cpi);
+    std::memcpy(img.data() + G.rg.outoff, G.outoff.data(), sizeof(long long) * n_cpi);
+    std::memcpy(img.data() + G.rg.prep, G.prep.data(), sizeof(PrepDesc) * 2 * n_cpi);
+    std::memcpy(img.data() + G.rg.items, G.items.data(), sizeof(int4) * G.items.size());
     if (hipMemcpy(ws, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return NDFT_E_HIP;
     std::memset(batch, 0, sizeof(*batch));
     batch->prec = (int32_t)prec;
@@ -1462,24 +1564,21 @@ ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool,
     if (st != NDFT_OK) return st;
     std::call_once(g_attr_once, set_kernel_attributes);
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
-    // offsets of the tables: recomputed from the header layout rules (same order as prepare)
     char *base = static_cast<char *>(ws);
     BatchHeader *hdr = reinterpret_cast<BatchHeader *>(base);
-    size_t off = 256;
-    const ContractParams *params = reinterpret_cast<const ContractParams *>(base + off);
-    off = align256(off + sizeof(ContractParams) * batch->n_cpi);
-    const ReduceParams *red = reinterpret_cast<const ReduceParams *>(base + off);
-    off = align256(off + sizeof(ReduceParams) * batch->n_cpi);
-    const long long *outoff = reinterpret_cast<const long long *>(base + off);
-    off = align256(off + sizeof(long long) * batch->n_cpi);
-    const PrepDesc *prep = reinterpret_cast<const PrepDesc *>(base + off);
-    off = align256(off + sizeof(PrepDesc) * 2 * batch->n_cpi);
-    const int4 *items = reinterpret_cast<const int4 *>(base + off);
+    const BatchRegions rg = batch_regions(batch->n_cpi);
+    const ContractParams *params = reinterpret_cast<const ContractParams *>(base + rg.params);
+    const ReduceParams *red = reinterpret_cast<const ReduceParams *>(base + rg.red);
+    const long long *outoff = reinterpret_cast<const long long *>(base + rg.outoff);
+    const PrepDesc *prep = reinterpret_cast<const PrepDesc *>(base + rg.prep);
+    unsigned *absmax = reinterpret_cast<unsigned *>(base + rg.absmax);
+    const int4 *items = reinterpret_cast<const int4 *>(base + rg.items);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned long long tag = batch->tag;
     int plan_id = batch->prec * 100 + batch->plan;
     const Plan &P = plans(batch->prec)[batch->plan];
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, hdr);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, hdr,
+                       batch->prec == NDFT_FP8 ? absmax : nullptr, 2 * batch->n_cpi);
     if ((st = check_launch()) != NDFT_OK) return st;
     const float2 *pool_s = reinterpret_cast<const float2 *>(surv_pool);
     const float2 *pool_r = reinterpret_cast<const float2 *>(ref_pool);
@@ -1499,6 +1598,98 @@ ndft_status ndft_caf_batched(const ndft_batch *batch, const ndft_c64 *surv_pool,
     }
     hipLaunchKernelGGL(reduce_batched_kernel, dim3((unsigned)batch->max_red_blocks, (unsigned)batch->n_cpi), dim3(256),
                        0, s, hdr, red, outoff, reinterpret_cast<float2 *>(out_pool), tag);
+    return check_launch();
+}
+
+size_t ndft_caf_batched_dev_workspace(int32_t n_cpi, int64_t max_n, int64_t max_tau, int64_t max_dop, ndft_prec prec)
+{
+    if (!prec_ok(prec) || n_cpi < 1 || n_cpi > kMaxDevBatch) return 0;
+    // every CPI within the maxima takes at most what one CPI at the maxima takes, with
+    // all its bins on one side (the most bases)
+    const ndft_cpi worst = {max_n, 0, 0, 0, 0, max_tau, 0, std::min<int64_t>(max_dop, max_n / 2 + 1)};
+    if (!cpi_valid(worst) || max_dop < 1 || max_dop > max_n) return 0;
+    const int pi = dev_batch_plan((int)prec);
+    const Plan &P = plans((int)prec)[pi];
+    const int chunk = (int)(cdiv(kDefaultChunk, P.kgran) * P.kgran);
+    CpiLayout o;
+    if (!cpi_layout(worst, batch_plan_geom(P, (int)prec), chunk, o)) return 0;
+    const BatchRegions rg = batch_regions(n_cpi);
+    const unsigned long long items = (unsigned long long)n_cpi * (unsigned long long)o.items;
+    if (items >= (1ULL << 30)) return 0;
+    return balign(rg.items + sizeof(int4) * (size_t)items) +
+           (size_t)n_cpi * (o.s4_bytes + o.r4_bytes + o.part_bytes);
+}
+
+ndft_status ndft_caf_batched_dev(const ndft_c64 *surv_pool, const ndft_c64 *ref_pool, ndft_c64 *out_pool,
+                                 const ndft_cpi *cpis_dev, int32_t n_cpi, ndft_prec prec, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!surv_pool || !ref_pool || !out_pool || !cpis_dev) return NDFT_E_INVAL;
+    if (!aligned(surv_pool, 8) || !aligned(ref_pool, 8) || !aligned(out_pool, 8) || !aligned(cpis_dev, 8))
+        return NDFT_E_INVAL;
+    if (!prec_ok(prec) || n_cpi < 1 || n_cpi > kMaxDevBatch) return NDFT_E_INVAL;
+    const BatchRegions rg = batch_regions(n_cpi);
+    ndft_status st = ws_ok(ws, ws_bytes, rg.items);
+    if (st != NDFT_OK) return st;
+    std::call_once(g_attr_once, set_kernel_attributes);
+    if (g_attr_err != hipSuccess) return NDFT_E_HIP;
+    const int pi = dev_batch_plan((int)prec);
+    const Plan &P = plans((int)prec)[pi];
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DevPlanArgs A;
+    A.cpis = cpis_dev;
+    A.n_cpi = n_cpi;
+    A.g = batch_plan_geom(P, (int)prec);
+    A.kgran = P.kgran;
+    A.chunk = (int)(cdiv(kDefaultChunk, P.kgran) * P.kgran);
+    A.ws = static_cast<char *>(ws);
+    A.ws_bytes = ws_bytes;
+    A.tag = ((++g_batch_seq) ^ ((unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() << 20)) |
+            1ULL; // never 0 (the planner's "did not run" tag)
+    A.plan_id = (int)prec * 100 + pi;
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, A);
+    if ((st = check_launch()) != NDFT_OK) return st;
+    char *base = static_cast<char *>(ws);
+    BatchHeader *hdr = reinterpret_cast<BatchHeader *>(base);
+    const ContractParams *params = reinterpret_cast<const ContractParams *>(base + rg.params);
+    const ReduceParams *red = reinterpret_cast<const ReduceParams *>(base + rg.red);
+    const long long *outoff = reinterpret_cast<const long long *>(base + rg.outoff);
+    const PrepDesc *prep = reinterpret_cast<const PrepDesc *>(base + rg.prep);
+    unsigned *absmax = reinterpret_cast<unsigned *>(base + rg.absmax);
+    const int4 *items = reinterpret_cast<const int4 *>(base + rg.items);
+    unsigned long long tag = A.tag;
+    int plan_id = A.plan_id;
+    // the queue counter is set by the planner; the maxima are cleared here (FP8)
+    if (prec == NDFT_FP8) {
+        hipLaunchKernelGGL(absmax_zero_kernel, dim3(1), dim3(256), 0, s, absmax, 2 * n_cpi);
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
+    const float2 *pool_s = reinterpret_cast<const float2 *>(surv_pool);
+    const float2 *pool_r = reinterpret_cast<const float2 *>(ref_pool);
+    if (!P.raw_inputs) {
+        hipLaunchKernelGGL(prep_batched_kernel, dim3(64, (unsigned)(2 * n_cpi)), dim3(256), 0, s, hdr, prep, pool_s,
+                           pool_r, tag);
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
+    {
+        void *args[] = {&hdr, &params, &items, &tag, &plan_id, &pool_s, &pool_r};
+        ProfScope prof(s);
+        hipError_t e = hipLaunchKernel(P.kfn_batched, dim3((unsigned)device_cu_count()), dim3((unsigned)P.nt), args,
+                                       (size_t)plan_max_dynamic(P), s);
+        prof.stop();
+        if (e != hipSuccess) return NDFT_E_HIP;
+        if ((st = check_launch()) != NDFT_OK) return st;
+    }
+    hipLaunchKernelGGL(reduce_batched_kernel, dim3(64, (unsigned)n_cpi), dim3(256), 0, s, hdr, red, outoff,
+                       reinterpret_cast<float2 *>(out_pool), tag);
+    return check_launch();
+}
+
+ndft_status ndft_caf_batched_dev_status(const void *ws, int32_t *status, void *stream)
+{
+    if (!ws || !status || !aligned(ws, 256) || !aligned(status, 4)) return NDFT_E_INVAL;
+    hipLaunchKernelGGL(batch_status_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream),
+                       static_cast<const BatchHeader *>(ws), reinterpret_cast<int *>(status));
     return check_launch();
 }
 

@@ -74,6 +74,9 @@ struct ContractParams {
     int tiles_b, tiles_l;
     int n_bases_pad, n_cols_pad;
     float4 *partial;      // [ksplit][n_cols_pad][n_bases_pad] of (U, V, X, Y)
+    // FP8: the largest |re| + |im| of the surveillance (or identity rows) and of the
+    // reference, as float bits (absmax_kernel); it fixes the data exponent of the e4m3 terms
+    const unsigned *absmax;
     // precomputed twiddle operand (register-lag surface kernels with planes): per base
     // tile, `plane_stages` consecutive stage blocks in the LDS order of a stage
     const uint4 *planes;
@@ -150,6 +153,71 @@ __device__ __forceinline__ void fp8_terms_pair(float g1, float v1, float g2, flo
     }
 }
 
+// Data exponent of the FP8 form. Every data component is bounded by M: a lag component
+// |z| <= max(|s_r| + |s_i|) + max(|r_r| + |r_i|) (each Eq. (1) operator is |a| + |b|), an
+// identity entry by max(|x_r| + |x_i|). The lag side carries z 2^-e with e the exponent
+// that puts M / 2^e in [32, 64), where the four-term split holds. In each K block a
+// twiddle sign meets a lag value (that product needs weight 2^e) and a twiddle value meets
+// a lag sign (weight 1), so e is spread over the operands: the twiddle signs are carried
+// as +-2^ea (A side), the lag signs as +-2^-eb (B side), the twiddle values as terms of
+// w 2^-x, and the MFMA scales the B block by 2^eb and the A block by 2^x (on top of the
+// term weight), with ea + eb + x = e. The sign magnitudes stay exact e4m3 (2^-9 .. 2^8),
+// so ea <= 8, eb <= 9; x > 0 (twiddle terms 2^x coarser) only when e > 17, up to 6: M <
+// 2^29. Beyond, the data terms are made NaN so the surface is NaN, never silently wrong
+// (the API documents the limit).
+struct Fp8Exp {
+    float a_sign; // 2^ea, twiddle-sign bytes
+    float a_val;  // 2^-x, twiddle values
+    float b_sign; // 2^-eb, lag-sign bytes
+    float b_val;  // 2^-e, lag values (NaN when M is out of range)
+    int scale_a;  // x, added to the E8M0 exponent of the term weight
+    int scale_b;  // E8M0 exponent of 2^eb
+};
+
+__device__ __forceinline__ Fp8Exp fp8_exponent(const unsigned *absmax, bool two)
+{
+    const float m = __uint_as_float(absmax[0]) + (two ? __uint_as_float(absmax[1]) : 0.0f);
+    int e = 0;
+    if (m > 0.0f) {
+        int ex;
+        (void)frexpf(m, &ex); // m = f 2^ex, f in [0.5, 1)
+        e = ex - 6;           // m / 2^e = f 2^6 in [32, 64)
+    }
+    const bool bad = !(m < 0x1p29f); // also NaN or infinity
+    e = max(e, -17);
+    const int x = min(max(e - 17, 0), 6);
+    const int ea = min(max(e - x, -9), 8);
+    const int eb = min(e - x - ea, 9);
+    Fp8Exp f;
+    f.a_sign = ldexpf(1.0f, ea);
+    f.a_val = ldexpf(1.0f, -x);
+    f.b_sign = ldexpf(1.0f, -eb);
+    f.b_val = bad ? __builtin_nanf("") : ldexpf(1.0f, -(ea + eb + x));
+    f.scale_a = x;
+    f.scale_b = 127 + eb;
+    return f;
+}
+
+// Largest |re| + |im| of `count` complex samples into *out (float bits; atomic maximum of
+// non-negative floats compares as unsigned integers). *out must hold 0 beforehand.
+__global__ __launch_bounds__(256) void absmax_kernel(const float2 *__restrict__ x, long long count,
+                                                     unsigned *__restrict__ out)
+{
+    float m = 0.0f;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < count; k += (long long)gridDim.x * 256) {
+        const float2 v = x[k];
+        m = fmaxf(m, fabsf(v.x) + fabsf(v.y));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void absmax_zero_kernel(unsigned *out, int count)
+{
+    for (int k = threadIdx.x; k < count; k += blockDim.x) out[k] = 0u;
+}
+
 template <int PREC, int PROD, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
 struct ContractCfg {
     static constexpr int NT = 64 * WAVES_B * WAVES_L;
@@ -218,6 +286,8 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
     const int nst = (k_end - k_begin + KS - 1) / KS;
 
     build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, NT);
+    Fp8Exp fx;
+    if (PREC == PREC_FP8) fx = fp8_exponent(P.absmax, PROD == PROD_LAG);
 
     // ---- twiddle slots: base row, sample pair, base b, m = b i mod n, step ----
     int tw_row[TWI], tw_pair[TWI], tw_b[TWI], tw_m[TWI], tw_dm[TWI];
@@ -302,8 +372,10 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
                     uint32_t *A = reinterpret_cast<uint32_t *>(bufA[buf]);
                     const int g = pair >> 3, dw = pair & 7;
                     uint32_t dc[4], dt[4];
-                    fp8_terms_pair<true>((float)g1.c, w1.x, (float)g2.c, w2.x, dc);
-                    fp8_terms_pair<true>((float)g1.t, w1.y, (float)g2.t, w2.y, dt);
+                    fp8_terms_pair<true>((float)g1.c * fx.a_sign, w1.x * fx.a_val, (float)g2.c * fx.a_sign,
+                                         w2.x * fx.a_val, dc);
+                    fp8_terms_pair<true>((float)g1.t * fx.a_sign, w1.y * fx.a_val, (float)g2.t * fx.a_sign,
+                                         w2.y * fx.a_val, dt);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         A[((((g * 2 + 0) * 4 + j) * BT) + row) * 8 + dw] = dc[j];
@@ -362,8 +434,10 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
                     uint32_t *B = reinterpret_cast<uint32_t *>(bufB[buf]);
                     const int g = pair >> 3, dw = pair & 7;
                     uint32_t dr[4], di[4];
-                    fp8_terms_pair<false>(z1.sr, z1.zr, z2.sr, z2.zr, dr);
-                    fp8_terms_pair<false>(z1.si, z1.zi, z2.si, z2.zi, di);
+                    fp8_terms_pair<false>(z1.sr * fx.b_sign, z1.zr * fx.b_val, z2.sr * fx.b_sign, z2.zr * fx.b_val,
+                                          dr);
+                    fp8_terms_pair<false>(z1.si * fx.b_sign, z1.zi * fx.b_val, z2.si * fx.b_sign, z2.zi * fx.b_val,
+                                          di);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         B[((((g * 2 + 0) * 4 + j) * LT) + col) * 8 + dw] = dr[j];
@@ -427,7 +501,7 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
 #pragma unroll
                 for (int mm = 0; mm < 2; ++mm) {
                     const int j0 = 2 * mm, j1 = 2 * mm + 1;
-                    const int scale_a = 127 - 4 * (2 * mm + h);
+                    const int scale_a = 127 - 4 * (2 * mm + h) + fx.scale_a;
                     i32x8 a[WB][2], b[WL][2];
 #pragma unroll
                     for (int i = 0; i < WB; ++i)
@@ -456,7 +530,8 @@ __device__ __forceinline__ void contract_tile(const ContractParams &P, const int
 #pragma unroll
                                 for (int tb = 0; tb < 2; ++tb)
                                     acc[i][jj][ta * 2 + tb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                                        a[i][ta], b[jj][tb], acc[i][jj][ta * 2 + tb], 0, 0, 0, scale_a, 0, 127);
+                                        a[i][ta], b[jj][tb], acc[i][jj][ta * 2 + tb], 0, 0, 0, scale_a, 0,
+                                        fx.scale_b);
                 }
             }
         } else {
@@ -572,6 +647,8 @@ struct BatchHeader {
     int n_cpi;
     int plan_id;
     unsigned long long tag; // identifies the prepare call that wrote the tables
+    int status;             // device planner: 0, or why the batch did not run (ndft_status)
+    int pad;
 };
 
 // Persistent form for a batch of surfaces: each work-group takes items (cpi, tile_b,
@@ -602,9 +679,13 @@ __global__ __launch_bounds__(64 * WAVES_B * WAVES_L, 1) void contract_batched_ke
     }
 }
 
-__global__ void batch_reset_kernel(BatchHeader *hdr)
+// Resets the work queue and the FP8 data maxima of the surfaces (absmax: count words,
+// may be null).
+__global__ void batch_reset_kernel(BatchHeader *hdr, unsigned *absmax, int count)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0;
+    if (absmax)
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) absmax[k] = 0u;
 }
 
 struct ReduceParams {
@@ -671,7 +752,8 @@ struct PrepDesc {
     float4 *out;
     int n, lead;
     long long ostride;
-    float g; // sign scale
+    float g;          // sign scale
+    unsigned *absmax; // FP8 plans: the row's largest |re| + |im| (float bits), else null
 };
 
 __global__ __launch_bounds__(256) void prep_batched_kernel(const BatchHeader *hdr, const PrepDesc *pd,
@@ -682,9 +764,17 @@ __global__ __launch_bounds__(256) void prep_batched_kernel(const BatchHeader *hd
     const PrepDesc D = pd[blockIdx.y];
     const float2 *x = (blockIdx.y & 1) ? pool_r : pool_s; // even: surveillance, odd: reference
     x += D.src_off;
+    float m = 0.0f;
     for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < D.ostride; k += (long long)gridDim.x * 256) {
         long long j = k - D.lead;
-        D.out[k] = (j >= 0 && j < D.n) ? with_signs(x[j], D.g) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float2 v = (j >= 0 && j < D.n) ? x[j] : make_float2(0.f, 0.f);
+        m = fmaxf(m, fabsf(v.x) + fabsf(v.y));
+        D.out[k] = (j >= 0 && j < D.n) ? with_signs(v, D.g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (D.absmax) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(D.absmax, __float_as_uint(m));
     }
 }
 

@@ -39,6 +39,9 @@ constexpr int DFT_LAG = 0, DFT_SIGNS = 1, DFT_LIN_SIGNS = 2;
 
 struct Dft12bParams {
     const float2 *s, *r;  // complex64 inputs, n samples each
+    // the whole-row kernel (L = 512): the inputs with their exact signs, (re, im, sign re,
+    // sign im): s4[n] and r4[2 n] (n zeros, then the reference, so r[m < 0] reads 0)
+    const float4 *s4, *r4;
     int n, tau0, n_tau;
     int p0n, n_dop;       // first bin (reduced mod n) and bin count
     int M, MB, n_mg;      // phases, phases per work-group, work-groups per delay
@@ -213,6 +216,76 @@ __device__ __forceinline__ float2 dft_source(float2 a, float2 b)
     } else {
         const Lag z = lag_product(a, b);
         return SRC == DFT_SIGNS ? make_float2(z.sr, z.si) : make_float2(z.zr, z.zi);
+    }
+}
+
+// The same value on the common path only: the lag product's FP32 value (DFT_LAG), or the
+// signs of the FP32 values with `unsure` set where the exact sign needs the slow path of
+// dft_source (a zero component from non-zero operators, or an ordinary lag product too
+// close to cancellation); the caller redoes those samples with dft_source.
+template <int SRC>
+__device__ __forceinline__ float2 dft_source_fast(float2 a, float2 b, bool &unsure)
+{
+    if constexpr (SRC == DFT_LIN_SIGNS) {
+        const float p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.y * b.x, p4 = a.x * b.y;
+        const float zr = p1 + p2, zi = p3 - p4;
+        const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
+        const bool zero = (a.x == 0.0f && a.y == 0.0f) || (b.x == 0.0f && b.y == 0.0f);
+        const bool sure = fabsf(zr) > 0x1p-22f * mr && mr >= 0x1p-100f && fabsf(zi) > 0x1p-22f * mi &&
+                          mi >= 0x1p-100f;
+        unsure = unsure || (!zero && !sure);
+        return zero ? make_float2(0.0f, 0.0f) : make_float2(sgnf(zr), sgnf(zi));
+    } else {
+        const float4 s = with_signs(a), r = with_signs(b);
+        const float t1 = fmaf(s.x, r.z, r.x * s.z); // s_r (x) r_r
+        const float t2 = fmaf(s.y, r.w, r.y * s.w); // s_i (x) r_i
+        const float t3 = fmaf(s.y, r.z, r.x * s.w); // s_i (x) r_r
+        const float t4 = fmaf(r.y, s.z, s.x * r.w); // r_i (x) s_r
+        const float zr = t1 + t2, zi = t3 - t4;
+        if constexpr (SRC == DFT_LAG) {
+            return make_float2(zr, zi);
+        } else {
+            unsure = unsure || (zr == 0.0f && t1 != 0.0f) || (zi == 0.0f && t3 != 0.0f);
+            return make_float2(sgnf(zr), sgnf(zi));
+        }
+    }
+}
+
+// dft_source_fast from inputs that carry their signs (see with_signs), with the test for
+// the slow path kept as a running maximum (`flag` > 0: redo the lane's samples with
+// dft_source) instead of per-sample conditions:
+//   DFT_SIGNS: a component whose FP32 sum is 0 from a non-zero operator (cancellation):
+//     |t1| - 2^30 |zr| > 0 exactly then (a non-zero FP32 sum of t1 and t2 is at least
+//     2^-25 |t1|), and never for an exact zero (t1 = t2 = 0);
+//   DFT_LIN_SIGNS: a component within 2^-22 of its products' magnitude (2^-22 m - |z| > 0),
+//     or, for a sample pair that is not zero, a component whose products are below 2^-100
+//     (the tests of dft_source).
+template <int SRC>
+__device__ __forceinline__ float2 dft_source_signed(float4 s, float4 r, float &flag)
+{
+    if constexpr (SRC == DFT_LIN_SIGNS) {
+        const float p1 = s.x * r.x, p2 = s.y * r.y, p3 = s.y * r.x, p4 = s.x * r.y;
+        const float zr = p1 + p2, zi = p3 - p4;
+        const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
+        const float qr = fmaf(mr, 0x1p-22f, -fabsf(zr)), qi = fmaf(mi, 0x1p-22f, -fabsf(zi));
+        // a zero sample pair gives exact zeros; otherwise a component whose products are
+        // below 2^-100 (possibly underflowed) takes the slow path
+        const bool pair = (fabsf(s.x) + fabsf(s.y)) > 0.0f && (fabsf(r.x) + fabsf(r.y)) > 0.0f;
+        const float tiny = pair && fminf(mr, mi) < 0x1p-100f ? 1.0f : 0.0f;
+        flag = fmaxf(flag, fmaxf(fmaxf(qr, qi), tiny));
+        return make_float2(sgnf(zr), sgnf(zi));
+    } else {
+        const float t1 = fmaf(s.x, r.z, r.x * s.z); // s_r (x) r_r
+        const float t2 = fmaf(s.y, r.w, r.y * s.w); // s_i (x) r_i
+        const float t3 = fmaf(s.y, r.z, r.x * s.w); // s_i (x) r_r
+        const float t4 = fmaf(r.y, s.z, s.x * r.w); // r_i (x) s_r
+        const float zr = t1 + t2, zi = t3 - t4;
+        if constexpr (SRC == DFT_LAG) {
+            return make_float2(zr, zi);
+        } else {
+            flag = fmaxf(flag, fmaxf(fmaf(-0x1p30f, fabsf(zr), fabsf(t1)), fmaf(-0x1p30f, fabsf(zi), fabsf(t3))));
+            return make_float2(sgnf(zr), sgnf(zi));
+        }
     }
 }
 

@@ -1,0 +1,251 @@
+// Decimated DFT of the lag-product rows for transform length L = 512 (N a multiple of 512,
+// at most 1024 requested bins): the fast path of dft12b_kernel (same sum, same readings):
+//   A[l][p] = sum_{m < M} W^{m p} Y_m[p mod 512],  Y_m[k] = sum_{t < 512} z[m + M t] W_512^{t k},
+// N = 512 M, z the lag products of delay d (DFT_LAG) or their exact signs (DFT_SIGNS,
+// DFT_LIN_SIGNS; bin p = 0 left out, see ndft_dft12b.hpp).
+//
+// One work-group of 256 threads owns a whole delay row at a time and keeps its bins in
+// registers, so no partial surfaces are written. The inputs come with their exact signs
+// (a sign-prep pass: s4[n], and r4[2 n] with n zeros in front, so a delayed reference
+// needs no bounds test) through buffer loads whose scalar offset carries the stride of
+// the samples a lane takes. The phases go in groups of 16; each
+// 512-point transform is done as 32 x 16 (t = 16 a + b, k = c + 32 e):
+//   pass 1: thread (j, b) loads the 32 samples a of transform j with residue b, makes their
+//           lag products, takes the 32-point DFT over a in registers and turns output c by
+//           W_512^{b c};
+//   pass 2: after one exchange through LDS, thread (j, c) takes the 16-point DFT over b for
+//           two columns c, giving Y_j[c + 32 e];
+//   bins:   after a second exchange, each thread adds sum_j W^{(m0 + j) p} Y_j[p mod 512] for
+//           its bins, the twiddle stepped by W^p from phase to phase and taken afresh from
+//           the table at every group.
+// Two LDS exchanges and four barriers per 8192 samples, no inner-twiddle passes over LDS.
+//
+// LDS: pass-1 buffer at (c 16 + b) 17 + j (the 16 lanes of a row j are consecutive, the
+// four b of a wave 17 apart); pass-2 buffer at j 516 + k (rows 4 banks apart). The W_N
+// table is the two-level one of ndft_device.hpp; W_512^k is a table of its own.
+#pragma once
+
+#include "ndft_dft12b.hpp"
+
+namespace ndft {
+
+constexpr int kD5Threads = 256;
+constexpr int kD5Group = 16;      // transforms per group
+constexpr int kD5MaxBins = 1024;  // requested bins (4 per thread)
+constexpr int kD5X = 32 * 16 * 17;
+constexpr int kD5YS = 516;
+
+// o times W_32^e = e^{-2 pi j e / 32} (e a constant after unrolling; 0 <= e < 32).
+__device__ __forceinline__ float2 mul_w32(float2 o, int e)
+{
+    // cos and sin of 2 pi k / 32, k = 0 .. 8
+    constexpr float C[9] = {1.0f,
+                            0.98078528040323044913f,
+                            0.92387953251128675613f,
+                            0.83146961230254523708f,
+                            0.70710678118654752440f,
+                            0.55557023301960222474f,
+                            0.38268343236508977173f,
+                            0.19509032201612826785f,
+                            0.0f};
+    float sg = 1.0f;
+    if (e >= 16) { // W_32^{e} = -W_32^{e - 16}
+        e -= 16;
+        sg = -1.0f;
+    }
+    if (e == 0) return make_float2(sg * o.x, sg * o.y);
+    if (e == 8) return make_float2(sg * o.y, -sg * o.x); // -j
+    if (e == 4) {
+        const float h = sg * C[4];
+        return make_float2(h * (o.x + o.y), h * (o.y - o.x));
+    }
+    if (e == 12) {
+        const float h = sg * C[4];
+        return make_float2(h * (o.y - o.x), -h * (o.x + o.y));
+    }
+    // e in 1..15: cos = C[e] (e <= 8) or -C[16 - e]; sin = C[8 - e] (e <= 8) or C[e - 8]
+    const float cs = sg * (e <= 8 ? C[e] : -C[16 - e]);
+    const float sn = sg * (e <= 8 ? C[8 - e] : C[e - 8]);
+    return make_float2(fmaf(o.x, cs, o.y * sn), fmaf(o.y, cs, -(o.x * sn)));
+}
+
+// In-register DFT of 16 points (4 x 4) and of 32 points (8 x 4): input a = R2 a1 + a2,
+// output c = c1 + R1 c2, X[c] = sum_a2 W_N^{a2 c1} W_R2^{a2 c2} sum_a1 u[R2 a1 + a2] W_R1^{a1 c1}.
+__device__ __forceinline__ void reg_dft16(float2 (&u)[16])
+{
+    float2 v[4][4];
+#pragma unroll
+    for (int a2 = 0; a2 < 4; ++a2) {
+        v[a2][0] = u[a2];
+        v[a2][1] = u[4 + a2];
+        v[a2][2] = u[8 + a2];
+        v[a2][3] = u[12 + a2];
+        dft4(v[a2][0], v[a2][1], v[a2][2], v[a2][3]);
+#pragma unroll
+        for (int c1 = 1; c1 < 4; ++c1) v[a2][c1] = mul_w32(v[a2][c1], 2 * a2 * c1); // W_16^{a2 c1}
+    }
+#pragma unroll
+    for (int c1 = 0; c1 < 4; ++c1) {
+        float2 t0 = v[0][c1], t1 = v[1][c1], t2 = v[2][c1], t3 = v[3][c1];
+        dft4(t0, t1, t2, t3);
+        u[c1] = t0;
+        u[c1 + 4] = t1;
+        u[c1 + 8] = t2;
+        u[c1 + 12] = t3;
+    }
+}
+
+__device__ __forceinline__ void reg_dft32(float2 (&u)[32])
+{
+    float2 v[4][8];
+#pragma unroll
+    for (int a2 = 0; a2 < 4; ++a2) {
+#pragma unroll
+        for (int a1 = 0; a1 < 8; ++a1) v[a2][a1] = u[4 * a1 + a2];
+        small_dft<8>(v[a2]);
+#pragma unroll
+        for (int c1 = 1; c1 < 8; ++c1) v[a2][c1] = mul_w32(v[a2][c1], a2 * c1);
+    }
+#pragma unroll
+    for (int c1 = 0; c1 < 8; ++c1) {
+        float2 t0 = v[0][c1], t1 = v[1][c1], t2 = v[2][c1], t3 = v[3][c1];
+        dft4(t0, t1, t2, t3);
+        u[c1] = t0;
+        u[c1 + 8] = t1;
+        u[c1 + 16] = t2;
+        u[c1 + 24] = t3;
+    }
+}
+
+// Grid: x strides over the delays. Dynamic LDS: the two-level table of W_N.
+template <int SRC>
+__global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
+{
+    __shared__ float2 X[kD5X];
+    __shared__ float2 w512[512];
+    extern __shared__ float2 tab[];
+    float2 *coarse = tab, *fine = tab + P.n_coarse;
+    const int tid = threadIdx.x;
+    const int n = P.n, M = P.M;
+    build_twiddle_tables(coarse, fine, n, P.tb, P.n_coarse, tid, kD5Threads);
+    __syncthreads();
+    for (int k = tid; k < 512; k += kD5Threads) w512[k] = table_twiddle(coarse, fine, k * M, P.tb); // k M < n
+    __syncthreads();
+
+    const int j = tid & 15, hb = tid >> 4; // pass 1: residue b = hb; pass 2: columns hb, hb + 16
+    // buffer views of the signed inputs: s4[n], r4[2 n] (bounded: reads past them give 0)
+    const __amdgpu_buffer_rsrc_t srs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)P.s4, (short)0, n * 16, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rrs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)P.r4, (short)0, 2 * n * 16, 0x00020000);
+    // this thread's bins: q = tid + 256 u
+    int bq[4], bp[4];
+    float2 bstep[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = tid + kD5Threads * u;
+        bq[u] = q < P.n_dop ? q : -1;
+        int p = P.p0n + (q < P.n_dop ? q : 0);
+        p = p >= n ? p - n : p;
+        bp[u] = p;
+        bstep[u] = table_twiddle(coarse, fine, p, P.tb);
+    }
+
+    for (int l = blockIdx.x; l < P.n_tau; l += gridDim.x) {
+        const int d = P.tau0 + l;
+        float2 acc[4];
+        int bv[4]; // (m0 p) mod n of the current group
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc[u] = make_float2(0.0f, 0.0f);
+            bv[u] = 0;
+        }
+        for (int m0 = 0; m0 < M; m0 += kD5Group) {
+            const int mb = min(kD5Group, M - m0);
+            // ---- pass 1: lag products of transform j, residue hb; 32-point DFT; W_512^{b c} ----
+            float2 x[32];
+            float flag = 0.0f;
+            if (j < mb) {
+                // sample idx = m0 + j + M (16 a + hb): one vector offset per lane, the step
+                // of a (16 M samples) in the scalar offset of each load
+                const unsigned vs = (unsigned)(m0 + j + M * hb) * 16u;
+                const unsigned vr = (unsigned)(n + m0 + j + M * hb - d) * 16u;
+                const unsigned step = 256u * (unsigned)M;
+#pragma unroll
+                for (int a = 0; a < 32; ++a) {
+                    const float4 sv = __builtin_bit_cast(
+                        float4, __builtin_amdgcn_raw_buffer_load_b128(srs, vs, step * (unsigned)a, 0));
+                    const float4 rv = __builtin_bit_cast(
+                        float4, __builtin_amdgcn_raw_buffer_load_b128(rrs, vr, step * (unsigned)a, 0));
+                    x[a] = dft_source_signed<SRC>(sv, rv, flag);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 32; ++a) x[a] = make_float2(0.0f, 0.0f);
+            }
+            // exact signs the FP32 values cannot give (zero or cancelling lag components):
+            // the lane's samples again through the exact path, rolled (rare)
+            if (SRC != DFT_LAG && __builtin_amdgcn_ballot_w64(flag > 0.0f)) {
+                if (flag > 0.0f) {
+#pragma unroll 1
+                    for (int a = 0; a < 32; ++a) {
+                        const int idx = m0 + j + M * (16 * a + hb);
+                        const float2 rv = idx >= d ? P.r[idx - d] : make_float2(0.0f, 0.0f);
+                        const float2 v = dft_source<SRC>(P.s[idx], rv);
+#pragma unroll
+                        for (int t = 0; t < 32; ++t)
+                            if (t == a) x[t] = v;
+                    }
+                }
+            }
+            reg_dft32(x);
+#pragma unroll
+            for (int c = 1; c < 32; ++c) x[c] = cmulf(x[c], w512[hb * c]); // hb c < 512
+            __syncthreads(); // the previous group's bin reads are done
+#pragma unroll
+            for (int c = 0; c < 32; ++c) X[(c * 16 + hb) * 17 + j] = x[c];
+            __syncthreads();
+            // ---- pass 2: 16-point DFTs over b for columns hb and hb + 16 ----
+            float2 y[2][16];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int b = 0; b < 16; ++b) y[h][b] = X[((hb + 16 * h) * 16 + b) * 17 + j];
+            __syncthreads(); // the pass-1 buffer is read; it becomes the pass-2 buffer
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                reg_dft16(y[h]);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) X[j * kD5YS + hb + 16 * h + 32 * e] = y[h][e];
+            }
+            __syncthreads();
+            // ---- bins: sum_j W^{(m0 + j) p} Y_j[p mod 512] ----
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (bq[u] < 0) continue;
+                const int k = bp[u] & 511;
+                float2 w = table_twiddle(coarse, fine, bv[u], P.tb);
+                float2 a = acc[u];
+                for (int jj = 0; jj < mb; ++jj) {
+                    const float2 yv = X[jj * kD5YS + k];
+                    a.x = fmaf(w.x, yv.x, fmaf(-w.y, yv.y, a.x));
+                    a.y = fmaf(w.x, yv.y, fmaf(w.y, yv.x, a.y));
+                    w = cmulf(w, bstep[u]);
+                }
+                acc[u] = a;
+                bv[u] = (int)(((long long)bv[u] + (long long)kD5Group * bp[u]) % n);
+            }
+        }
+        float2 *dst = P.out + (size_t)l * P.n_dop;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (bq[u] < 0) continue;
+            float2 a = acc[u];
+            if (SRC != DFT_LAG && bp[u] == 0) a = make_float2(0.0f, 0.0f);
+            if (P.accumulate) a = caddf(a, dst[bq[u]]);
+            dst[bq[u]] = a;
+        }
+    }
+}
+
+} // namespace ndft

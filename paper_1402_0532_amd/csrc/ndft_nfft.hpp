@@ -1,22 +1,30 @@
-// NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT with the twiddle
-// product of every butterfly replaced by the complex operator of Eq. (6),
-//   X[k] = E[k] + O[k] (x) W_n^k,   X[k + n/2] = E[k] - O[k] (x) W_n^k,
-// recursively down to single samples (W_n^0 = 1 included, so no multiplication is left;
-// E / O are the NFFTs of the even / odd samples). A work-group takes 8192 / N rows at a
-// time (one for N = 8192): the rows and a twiddle table W_N^m (m < N/2, FP64 cosine and
-// sine rounded once to FP32, exact at the quadrant points) live in LDS, and log2 N
-// radix-2 Stockham passes over all its rows, which evaluate the
-// recursion's butterflies in the same operations (each lane holds its butterflies'
-// outputs between the two barriers of a pass). The operator is not associative, so
-// butterflies cannot be merged into higher radices. FP32 adds only: the result is the
-// recursion evaluated in FP32, bit for bit.
+// NFFT of Section 3 (Eq. (10)): the radix-2 decimation-in-time FFT whose butterflies carry
+// the operator of Eq. (6). Two readings of the printed equation:
+//   OUTER = false (the multiplication-free transform the text describes): every twiddle
+//     product of a butterfly is the operator, X[k] = E[k] + O[k] (x) W_n^k, X[k + n/2] =
+//     E[k] - O[k] (x) W_n^k, recursively down to single samples (W_n^0 = 1 included);
+//   OUTER = true (the equation as printed): the twiddle in front of the odd half is an
+//     ordinary complex product at every level, X[k] = E[k] + W_n^k O[k], and the operator
+//     sits in the sums themselves, whose length-1 terms at the bottom are x (x) 1.
+// E / O are the transforms of the even / odd samples. Both are evaluated butterfly by
+// butterfly in FP32 in the recursion's own operations (products and sums rounded one by
+// one, no fused multiply-add), so the result is the FP32 recursion bit for bit; twiddles
+// are W_n^m = e^{-j 2 pi m / n} rounded once from FP64, exact at the quadrant points.
+//
+// Rows of up to 8192 samples are transformed in LDS by one work-group (8192 / L rows at a
+// time): log2 L radix-2 Stockham passes, each lane holding its butterflies' outputs between
+// the two barriers of a pass. Longer rows (n = 2^s L, L = 8192) take the recursion's lower
+// levels in LDS, as the transforms of the 2^s decimated sequences x[j + 2^s t], and its top
+// s levels as passes over global memory (nfft_combine_kernel): at stride S the transform of
+// x[j::S] is the combination of those of x[j::2S] and x[j + S::2S].
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace ndft {
 
-constexpr int kNfftMaxN = 8192;
+constexpr int kNfftMaxN = 8192;            // rows transformed in LDS
+constexpr int kNfftMaxLong = 1 << 24;      // longest row
 constexpr int kNfftThreads = 1024;
 
 // Eq. (1) with the sign table of Eq. (2), FP32: one rounding
@@ -34,30 +42,54 @@ __device__ __forceinline__ float2 cop32(float2 o, float2 w)
     return make_float2(rop32(o.x, w.x) - rop32(o.y, w.y), rop32(o.y, w.x) + rop32(w.y, o.x));
 }
 
+// ordinary complex product, each product and sum rounded on its own (no contraction into
+// fused multiply-adds)
+__device__ __forceinline__ float2 cmul_rn(float2 o, float2 w)
+{
+#pragma clang fp contract(off)
+    const float p1 = o.x * w.x, p2 = o.y * w.y, p3 = o.x * w.y, p4 = o.y * w.x;
+    return make_float2(p1 - p2, p3 + p4);
+}
+
+// W_n^m, m < n / 2
+__device__ __forceinline__ float2 nfft_twiddle(int m, int n)
+{
+    if ((4LL * m) % n == 0) // quadrant points: exactly 1, -j
+        return (4LL * m) / n == 0 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, -1.0f);
+    const double th = 2.0 * 3.14159265358979323846 * (double)m / (double)n;
+    return make_float2((float)cos(th), (float)(-sin(th)));
+}
+
+// The twiddled odd term of a butterfly in the chosen reading.
+template <bool OUTER>
+__device__ __forceinline__ float2 nfft_odd(float2 o, float2 w)
+{
+    return OUTER ? cmul_rn(o, w) : cop32(o, w);
+}
+
 // Dynamic LDS: rpb rows of n entries, then n / 2 twiddles. Row groups g = blockIdx.x,
-// + gridDim.x, ... of rpb = 8192 / n rows each (n a power of two).
+// + gridDim.x, ... of rpb = 8192 / n rows each (n a power of two). Row r (of `rows`) is
+// read from x + (r / sub) * in_row + (r % sub) with element stride `sub` (sub = 1: plain
+// rows; sub = 2^s: the decimated sequences of a long row of in_row = n sub samples) and
+// written contiguously to X + r n.
+template <bool OUTER>
 __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__restrict__ x, float2 *__restrict__ X,
-                                                           long long batch, int n, int rpb)
+                                                           long long rows_total, int n, int rpb, int sub,
+                                                           long long in_row)
 {
     extern __shared__ float2 nfft_lds[];
     float2 *buf = nfft_lds, *tw = nfft_lds + (size_t)rpb * n;
     constexpr int CNT = kNfftMaxN / 2 / kNfftThreads;
     const int tid = threadIdx.x, h = n >> 1;
     const int lh = 31 - __builtin_clz(max(h, 1)); // log2 of h (h >= 1 when n >= 2)
-    for (int m = tid; m < h; m += kNfftThreads) {
-        float2 w;
-        if ((4 * m) % n == 0) { // quadrant points: exactly 1, -j
-            w = (4 * m) / n == 0 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, -1.0f);
-        } else {
-            const double th = 2.0 * 3.14159265358979323846 * (double)m / (double)n;
-            w = make_float2((float)cos(th), (float)(-sin(th)));
+    for (int m = tid; m < h; m += kNfftThreads) tw[m] = nfft_twiddle(m, n);
+    for (long long b0 = (long long)blockIdx.x * rpb; b0 < rows_total; b0 += (long long)gridDim.x * rpb) {
+        const int rows = (int)min((long long)rpb, rows_total - b0);
+        for (int i = tid; i < rows * n; i += kNfftThreads) {
+            const long long r = b0 + i / n;
+            const float2 v = x[(r / sub) * in_row + (r % sub) + (long long)sub * (i % n)];
+            buf[i] = OUTER ? cop32(v, make_float2(1.0f, 0.0f)) : v; // the length-1 transforms
         }
-        tw[m] = w;
-    }
-    for (long long b0 = (long long)blockIdx.x * rpb; b0 < batch; b0 += (long long)gridDim.x * rpb) {
-        const int rows = (int)min((long long)rpb, batch - b0);
-        const float2 *xr = x + b0 * n;
-        for (int i = tid; i < rows * n; i += kNfftThreads) buf[i] = xr[i];
         __syncthreads(); // also orders the table before its first use
         for (int p = 1; p < n; p <<= 1) {
             float2 y0[CNT], y1[CNT];
@@ -71,7 +103,7 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
                 if (r < rows) {
                     const int k = i & (p - 1);
                     const float2 *row = buf + r * n;
-                    const float2 u0 = row[i], t = cop32(row[i + h], tw[k * tstep]);
+                    const float2 u0 = row[i], t = nfft_odd<OUTER>(row[i + h], tw[k * tstep]);
                     y0[c] = make_float2(u0.x + t.x, u0.y + t.y);
                     y1[c] = make_float2(u0.x - t.x, u0.y - t.y);
                     dst[c] = r * n + (i - k) * 2 + k;
@@ -89,6 +121,38 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
         float2 *Xr = X + b0 * n;
         for (int i = tid; i < rows * n; i += kNfftThreads) Xr[i] = buf[i];
         __syncthreads(); // buf is refilled for the next row
+    }
+}
+
+// W_n^m for m < n / 2 into a table (long rows).
+__global__ __launch_bounds__(256) void nfft_table_kernel(float2 *tw, int n)
+{
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m < n / 2) tw[m] = nfft_twiddle(m, n);
+}
+
+// One top level of a long row (n samples per row): at stride S the transform of x[j::S]
+// (length 2h, h = n / (2 S)) from those of x[j::2S] and x[j + S::2S] (length h each), laid
+// out as [residue][k] per row: src holds 2S sequences of length h, dst S of length 2h.
+// Butterfly (j, k): E = src[j h + k], O = src[(j + S) h + k], twiddle W_{2h}^k = W_n^{k S}.
+template <bool OUTER>
+__global__ __launch_bounds__(256) void nfft_combine_kernel(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                                           const float2 *__restrict__ tw, long long batch, int n,
+                                                           int S)
+{
+    const long long half = (long long)n / 2;
+    const int h = n / (2 * S);
+    const long long total = batch * half;
+    for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < total; w += (long long)gridDim.x * 256) {
+        const long long row = w / half;
+        const int b = (int)(w - row * half); // butterfly of the row: j = b / h, k = b % h
+        const int j = b / h, k = b - (b / h) * h;
+        const float2 *s = src + row * n;
+        const float2 e = s[(long long)j * h + k];
+        const float2 t = nfft_odd<OUTER>(s[(long long)(j + S) * h + k], tw[(long long)k * S]);
+        float2 *d = dst + row * n + (long long)j * 2 * h;
+        d[k] = make_float2(e.x + t.x, e.y + t.y);
+        d[k + h] = make_float2(e.x - t.x, e.y - t.y);
     }
 }
 

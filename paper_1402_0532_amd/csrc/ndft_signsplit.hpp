@@ -168,13 +168,15 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 // i and M - 1 - i of the group's M rows: the rows ascend in b and the crossings per chunk
 // grow with b, so every thread walks about as many as any other.
 //
-// Per part, with P(k) the prefix sum of z over the block's first k samples,
-//   sum_k S(k) z_k = S_end P(K) + sum_{crossings k_i < K} S_i (P(k_i) + P(k_i + e_i))
+// Per part and chunk, with P(k) the prefix sum of z over the chunk's first k samples,
+//   sum_k S(k) z_k = S_end P(C) + sum_{crossings k_i < C} S_i (P(k_i) + P(k_i + e_i))
 // (S_i the sign before crossing i, e_i = 1 when it is exact: the zero sample is then a
-// run of its own; S_end the sign after the last crossing, K the block's samples). Each
-// chunk's tables hold P at its C + 1 sample edges, the earlier chunks' sum included:
-// P(k) + P(k) = 2 P(k) and R(k) = P(k) + P(k + 1), so a crossing costs one row read
-// either way, and the end term comes once per block.
+// run of its own; S_end the sign after the chunk's last crossing). The tables hold P at
+// the chunk's C + 1 sample edges: P(k) + P(k) = 2 P(k) and R(k) = P(k) + P(k + 1), so a
+// crossing costs one row read either way, and the end term comes once per chunk. The
+// prefix sums restart at every chunk, so no term is larger than the sum of 256 |z|: the
+// rounding of T is a few ulp of the chunk sums per crossing, however far the block's
+// prefix sum grows (DC-heavy rows), instead of a few ulp of the block's prefix sum.
 //
 // LIN: the lag product of the Eq. (12c) surface (linear_lag64) instead of Eq. (6).
 template <bool LIN>
@@ -230,9 +232,9 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[j][d][t] = 0.0f;
     }
-    // sum of z over the block's earlier chunks, delays dl0 + h (the prefix tables hold
-    // block prefix sums); base 0 of those delays: counts of negative and zero signs (this
-    // thread's samples; the 32 threads of the pair are added at the end)
+    // sum of z over the block's chunks so far, delays dl0 + h, and counts of negative and
+    // zero signs (this thread's samples; the 32 threads of the pair are added at the end):
+    // base 0 of those delays
     float2 gq[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
     int ngr[2] = {0, 0}, ngi[2] = {0, 0}, zcr[2] = {0, 0}, zci[2] = {0, 0}, nfield = 0;
 
@@ -387,14 +389,14 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             float er[2], ei[2], lr[2], li[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                er[h] = (half_scan32(pr[h]) - pr[h]) + gq[h].x;
-                ei[h] = (half_scan32(pim[h]) - pim[h]) + gq[h].y;
+                er[h] = half_scan32(pr[h]) - pr[h];
+                ei[h] = half_scan32(pim[h]) - pim[h];
                 lr[h] = er[h]; // P(o0 + j)
                 li[h] = ei[h];
             }
             if (g == 0) {
-                ptab[dl0] = gq[0];
-                ptab[dl0 + 1] = gq[1];
+                ptab[dl0] = make_float2(0.0f, 0.0f);
+                ptab[dl0 + 1] = make_float2(0.0f, 0.0f);
             }
 #pragma unroll
             for (int j = 0; j < SPT; ++j) {
@@ -417,8 +419,12 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             }
         }
         __syncthreads(); // prefix tables complete; the windows are free again
-        gq[0] = ptab[prow(C) + dl0];
-        gq[1] = ptab[prow(C) + dl0 + 1];
+        // the block total of z (base 0)
+        {
+            const float2 t0 = ptab[prow(C) + dl0], t1 = ptab[prow(C) + dl0 + 1];
+            gq[0] = make_float2(gq[0].x + t0.x, gq[0].y + t0.y);
+            gq[1] = make_float2(gq[1].x + t1.x, gq[1].y + t1.y);
+        }
 
         if (k0 + C < ke) win_store(nv);
 
@@ -451,24 +457,18 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             };
             walk(std::integral_constant<int, 0>());
             walk(std::integral_constant<int, 1>());
-        }
-        __syncthreads(); // next window stored, prefix tables read
-    }
-    // the sign after the last crossing times the block total (the last table's row C)
-    if (ke > kb) {
+            // the sign after the chunk's last crossing times the chunk total (row C)
 #pragma unroll
-        for (int d = 0; d < DH; ++d) {
-            const float2 q = ptab[prow(C) + dh * DH + d];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int d = 0; d < DH; ++d) {
+                const float2 q = ptab[prow(C) + dh * DH + d];
                 acc[j][d][0] = fmaf(cr[j][0].sg, q.x, acc[j][d][0]);
                 acc[j][d][2] = fmaf(cr[j][0].sg, q.y, acc[j][d][2]);
                 acc[j][d][3] = fmaf(cr[j][1].sg, q.x, acc[j][d][3]);
                 acc[j][d][1] = fmaf(cr[j][1].sg, q.y, acc[j][d][1]);
             }
         }
+        __syncthreads(); // next window stored, prefix tables read
     }
-
     // base 0: W = 1, so the T part is the sum of z and the D part that of the signs
     float4 *out = L.part + (long long)blockIdx.y * L.n_cols_pad * L.n_bases_pad;
 #pragma unroll

@@ -159,21 +159,32 @@ def test_caf12b_arguments_and_workspace():
     assert lib.ndft_caf12b(p, p, 16, 0, 4, 0, 4, p, 1, p, 4096, None) == UNSUPPORTED
     assert lib.ndft_caf12b(p, p, 16, 0, 4, 0, 4, p, 2, p, 4096, None) == UNSUPPORTED
     assert lib.ndft_caf12b_workspace(16, 0, 4, 0, 4, 1) == 0
-    # one work-group per delay (8192 samples or fewer): no partial surfaces
-    assert lib.ndft_caf12b_workspace(4096, 0, 300, -200, 400, 0) == 0
-    # N = 65536: 128 phases in groups of 16, eight partial surfaces of 1024 x 512
-    assert lib.ndft_caf12b_workspace(65536, 0, 1024, -256, 512, 0) == 8 * 1024 * 512 * 8
-    assert lib.ndft_caf12b(p, p, 65536, 0, 1024, -256, 512, p, 0, None, 0, None) == WORKSPACE
+    # transform length 512 and a work-group per delay row: no partial surfaces, only the
+    # inputs with their signs (16 B per sample, the reference after n zeros)
+    assert lib.ndft_caf12b_workspace(4096, 0, 300, -200, 400, 0) == 48 * 4096
+    # N = 65536 with 1024 delays: the same; with few delays the phases of a row split over
+    # work-groups: 128 phases in groups of 16, eight partial surfaces of 4 x 512
+    assert lib.ndft_caf12b_workspace(65536, 0, 1024, -256, 512, 0) == 48 * 65536
+    assert lib.ndft_caf12b_workspace(65536, 0, 4, -256, 512, 0) == 8 * 4 * 512 * 8
+    assert lib.ndft_caf12b(p, p, 65536, 0, 4, -256, 512, p, 0, None, 0, None) == WORKSPACE
+    # more than 1024 bins: the phase-group kernel again
+    assert lib.ndft_caf12b_workspace(65536, 0, 1024, -600, 1200, 0) == 8 * 1024 * 1200 * 8
 
 
 def test_nfft_arguments():
     lib = _lib.load()
     keep, p = _host_buf()
-    for n in (0, 3, 12, 16384, -4):
-        assert lib.ndft_nfft(p, p, 1, n, None) == INVAL
-    assert lib.ndft_nfft(p, p, -1, 8, None) == INVAL
-    assert lib.ndft_nfft(None, p, 1, 8, None) == INVAL
-    assert lib.ndft_nfft(p, p, 0, 8, None) == 0  # nothing to do
+    for n in (0, 3, 12, 1 << 25, -4):
+        assert lib.ndft_nfft(p, p, 1, n, 0, None, 0, None) == INVAL
+        assert lib.ndft_nfft_workspace(1, n) == 0
+    assert lib.ndft_nfft(p, p, -1, 8, 0, None, 0, None) == INVAL
+    assert lib.ndft_nfft(None, p, 1, 8, 0, None, 0, None) == INVAL
+    assert lib.ndft_nfft(p, p, 1, 8, 2, None, 0, None) == INVAL  # no such reading
+    assert lib.ndft_nfft(p, p, 0, 8, 1, None, 0, None) == 0  # nothing to do
+    # rows up to 8192 samples need no workspace; longer ones ping-pong rows and a table
+    assert lib.ndft_nfft_workspace(100, 8192) == 0
+    assert lib.ndft_nfft_workspace(3, 1 << 16) == 3 * (1 << 16) * 8 + (1 << 15) * 8
+    assert lib.ndft_nfft(p, p, 3, 1 << 16, 0, None, 0, None) == WORKSPACE
 
 
 def test_fp32_plan_choice_rules():

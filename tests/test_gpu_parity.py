@@ -267,7 +267,7 @@ def test_invalid_arguments_raise(nd):
         nd.caf(s.real.contiguous(), s, 0, 4, 0, 4)
 
 
-@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft"])
+@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft", "nfft_long"])
 def test_fft_paths_graph_replay(nd, which):
     """The FFT-based paths (the FP32 sign-split surfaces of Eq. (12a) and (12c):
     twiddle-sign kernel, reduction, then the FFT of the exact lag signs added on top; the
@@ -288,14 +288,25 @@ def test_fft_paths_graph_replay(nd, which):
     elif which == "caf12c_fp32":
         nbytes = nd.caf12c_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
         call = lambda out, ws: nd.caf12c(S, R, tau0, n_tau, p0, n_dop, prec=0, out=out, ws=ws)
+    elif which == "nfft_long":
+        # rows of 16384 samples: the LDS stage, then one pass over global memory through
+        # the workspace (printed reading)
+        rows = dev(np.stack([s, r] * 3))
+        nbytes = int(nd._lib.load().ndft_nfft_workspace(rows.shape[0], rows.shape[1]))
+
+        def call(out, ws):
+            res = out if out is not None else torch.empty_like(rows)
+            nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(rows), nd._ptr(res), rows.shape[0], rows.shape[1], 1,
+                                                   nd._ptr(ws), ws.numel(), nd._stream_handle()))
+            return res
     else:
         rows = dev(np.stack([s[:4096], r[:4096]] * 40))
         nbytes = 1
 
         def call(out, ws):
             res = out if out is not None else torch.empty_like(rows)
-            nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(rows), nd._ptr(res), rows.shape[0], rows.shape[1],
-                                                   nd._stream_handle()))
+            nd._lib.check(nd._lib.load().ndft_nfft(nd._ptr(rows), nd._ptr(res), rows.shape[0], rows.shape[1], 0,
+                                                   None, 0, nd._stream_handle()))
             return res
     assert nbytes > 0
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")

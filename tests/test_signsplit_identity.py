@@ -155,9 +155,9 @@ def test_crossing_walk_matches_quarter_rule(n):
 def test_crossing_tables_give_twiddle_sign_sums(shape):
     """The sum the kernel forms over a block that starts at kb, chunk by chunk: for each
     crossing the sign before it times 2 P(k) (or R(k) = P(k) + P(k + 1) when exact), P the
-    prefix sum over the block (each chunk's table starts from the earlier chunks' total),
-    plus the sign after the last crossing times the block total, equals
-    sum_k csgn(W^{bk}) z_k (FP64, random z)."""
+    prefix sum within the chunk (each chunk's table starts from 0), plus, per chunk, the sign
+    after its last crossing times the chunk total, equals sum_k csgn(W^{bk}) z_k (FP64,
+    random z)."""
     n, kb, chunk = shape
     rng = np.random.default_rng(n + kb)
     nch = 3
@@ -169,16 +169,54 @@ def test_crossing_tables_give_twiddle_sign_sums(shape):
         got = [0j, 0j]
         for part in (0, 1):
             nk, rem, sg = first_crossing(b, kb, n, part)
-            g = 0j  # sum over the earlier chunks
             for c in range(nch):
                 zc = z[c * chunk:(c + 1) * chunk]
-                P = g + np.concatenate([[0], np.cumsum(zc)])
+                P = np.concatenate([[0], np.cumsum(zc)])
                 R = P[:-1] + P[1:]
                 while nk < chunk:
                     got[part] += sg * (R[nk] if rem == 0 else 2 * P[nk])
                     nk, rem, sg = crossing_step(nk, rem, sg, b, n)
-                g = P[chunk]
+                got[part] += sg * P[chunk]
                 nk -= chunk
-            got[part] += sg * g
         total = got[0] + 1j * got[1]
         assert abs(total - want) <= 1e-9 * (1 + np.sum(np.abs(z))), (shape, b, total, want)
+
+
+def test_chunk_local_sums_round_less_on_dc_rows():
+    """Why the prefix sums restart at every chunk: on a row whose values keep one sign,
+    block-wide prefix sums grow with the block while T stays small, and the FP32 rounding
+    of every crossing term grows with them; chunk-local sums keep every term within one
+    chunk's sum. Modelled in FP32 (numpy float32 cumulative sums) against FP64."""
+    n, kb, chunk, nch = 65536, 0, 256, 32
+    rng = np.random.default_rng(5)
+    z = (1.0 + 0.01 * rng.standard_normal(nch * chunk)).astype(np.float32)
+    b = n // 256  # the largest base the sign-split plans admit
+    k = kb + np.arange(nch * chunk)
+    sc = np.array([quarter_signs((b * int(kk)) % n, n)[0] for kk in k], np.float64)
+    want = float(np.sum(sc * z.astype(np.float64)))
+
+    def model(local):
+        nk, rem, sg = first_crossing(b, kb, n, 0)
+        acc = np.float32(0.0)
+        g = np.float32(0.0)
+        for c in range(nch):
+            zc = z[c * chunk:(c + 1) * chunk]
+            P = np.concatenate([[np.float32(0.0)], np.cumsum(zc, dtype=np.float32)]) + (np.float32(0.0) if local else g)
+            P = P.astype(np.float32)
+            R = (P[:-1] + P[1:]).astype(np.float32)
+            while nk < chunk:
+                acc = np.float32(acc + np.float32(sg) * (R[nk] if rem == 0 else np.float32(2.0) * P[nk]))
+                nk, rem, sg = crossing_step(nk, rem, sg, b, n)
+            if local:
+                acc = np.float32(acc + np.float32(sg) * P[chunk])
+            g = P[chunk]
+            nk -= chunk
+        if not local:
+            acc = np.float32(acc + np.float32(sg) * g)
+        return float(acc)
+
+    scale = float(np.sum(np.abs(z)))
+    e_local = abs(model(True) - want) / scale
+    e_block = abs(model(False) - want) / scale
+    assert e_local <= 2e-7
+    assert e_local < e_block

@@ -310,6 +310,7 @@ void set_kernel_attributes()
 struct Dft12bLaunch {
     int lb, M, MB, n_mg, tb, n_coarse;
     int fast;         // L = 512: dft512_kernel (a work-group per delay row, no partials)
+    int codes;        // a sign half: the fast kernel reads the twiddle-sign kernel's codes
     size_t dyn_bytes; // the twiddle table (dynamic LDS)
     size_t ws_bytes;  // partial surfaces when a delay takes more than one work-group
 };
@@ -451,7 +452,7 @@ int64_t lsum_groups(const Launch &L)
 
 // whole_rows: allow the whole-row kernel (the Eq. (12c) signs stay on the phase-group
 // kernel, which measured faster for them)
-Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop, bool whole_rows = true)
+Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop, size_t code_bytes = 0)
 {
     Dft12bLaunch L;
     std::memset(&L, 0, sizeof(L));
@@ -463,11 +464,17 @@ Dft12bLaunch plan_dft12b(int64_t n, int64_t n_tau, int64_t n_dop, bool whole_row
     choose_table(n, 65536, &L.tb, &L.n_coarse, &exact);
     L.dyn_bytes = (size_t)(L.n_coarse + (1 << L.tb)) * sizeof(float2);
     // the whole-row kernel wherever it has enough rows to fill the device (or a row is a
-    // single group of transforms anyway)
-    L.fast = whole_rows && L.lb == 9 && n_dop <= kD5MaxBins && (n_tau >= 128 || L.M <= kD5Group) ? 1 : 0;
+    // single group of transforms anyway); the sign halves (code_bytes > 0) read the sign
+    // codes through 32-bit buffer offsets
+    L.fast = L.lb == 9 && n_dop <= kD5MaxBins && (n_tau >= 128 || L.M <= kD5Group) &&
+                     code_bytes < (size_t(1) << 31)
+                 ? 1
+                 : 0;
+    L.codes = code_bytes > 0 ? 1 : 0;
     if (L.fast) L.n_mg = 1;
-    // whole-row kernel: the signed inputs s4[n], r4[2 n]; else the partial surfaces
-    L.ws_bytes = L.fast ? align256((size_t)n * sizeof(float4)) + align256((size_t)2 * n * sizeof(float4))
+    // whole-row kernel on the lag products: the signed inputs s4[n], r4[2 n]; else the
+    // partial surfaces
+    L.ws_bytes = L.fast ? (L.codes ? 0 : align256((size_t)n * sizeof(float4)) + align256((size_t)2 * n * sizeof(float4)))
                         : (L.n_mg > 1 ? align256((size_t)L.n_mg * n_tau * n_dop * sizeof(float2)) : 0);
     return L;
 }
@@ -563,7 +570,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
     }
     if (L.plan->fft_d) {
-        L.dft = plan_dft12b(n, n_cols, n_bins, !lin);
+        L.dft = plan_dft12b(n, n_cols, n_bins, (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
         L.dft_off = L.ws_bytes;
         L.ws_bytes += L.dft.ws_bytes;
     }
@@ -866,9 +873,11 @@ hipError_t g_dft_attr_err = hipSuccess;
 // exact signs (DFT_SIGNS / DFT_LIN_SIGNS: the twiddle half of the Eq. (12a) / Eq. (12c)
 // sign-split forms, bin 0 left out), written to A or, with accumulate, added to it. ws
 // holds the partial surfaces.
+// The fast kernel on a sign half reads the sign codes at `codes` (code_cols columns,
+// code_bytes in all) that the twiddle-sign kernel wrote earlier on the same stream.
 ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t tau0,
                        int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, int src, bool accumulate,
-                       hipStream_t s)
+                       hipStream_t s, const uint32_t *codes = nullptr, int code_cols = 0, size_t code_bytes = 0)
 {
     std::call_once(g_dft_attr_once, [] {
         for (int lb = 0; lb <= kDftMaxLog; ++lb)
@@ -876,7 +885,7 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
                 hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
                 if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
             }
-        for (const void *fn : {dft512_fn<DFT_LAG>(), dft512_fn<DFT_SIGNS>(), dft512_fn<DFT_LIN_SIGNS>()}) {
+        for (const void *fn : {dft512_fn<DFT_LAG>(), dft512_fn<DFT_CODES>()}) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
             if (e != hipSuccess && g_dft_attr_err == hipSuccess) g_dft_attr_err = e;
         }
@@ -901,18 +910,25 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
     P.accumulate = L.n_mg > 1 ? 0 : (accumulate ? 1 : 0);
     void *args[] = {&P};
     if (L.fast) {
-        // the inputs with their exact signs (the reference after n zeros), then two
-        // work-groups per compute unit, each taking whole delay rows in turn
-        float4 *s4 = static_cast<float4 *>(ws);
-        float4 *r4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + align256((size_t)n * sizeof(float4)));
-        ndft_status st = launch_prep(surv, s4, n, 1, n, 0, 1.0f, s);
-        if (st == NDFT_OK) st = launch_prep(ref, r4, n, 1, 2 * n, n, 1.0f, s);
-        if (st != NDFT_OK) return st;
-        P.s4 = s4;
-        P.r4 = r4;
+        // two work-groups per compute unit, each taking whole delay rows in turn
+        if (src == DFT_LAG) {
+            // the inputs with their exact signs (the reference after n zeros)
+            float4 *s4 = static_cast<float4 *>(ws);
+            float4 *r4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + align256((size_t)n * sizeof(float4)));
+            ndft_status st = launch_prep(surv, s4, n, 1, n, 0, 1.0f, s);
+            if (st == NDFT_OK) st = launch_prep(ref, r4, n, 1, 2 * n, n, 1.0f, s);
+            if (st != NDFT_OK) return st;
+            P.s4 = s4;
+            P.r4 = r4;
+        } else {
+            // a sign half: the codes of the call's twiddle-sign kernel
+            if (!L.codes || !codes || code_cols < n_tau || code_bytes >= (size_t(1) << 31)) return NDFT_E_INVAL;
+            P.codes = codes;
+            P.code_cols = code_cols;
+            P.code_bytes = (unsigned)code_bytes;
+        }
         const dim3 grid((unsigned)std::min<int64_t>(n_tau, 2LL * device_cu_count()));
-        const void *fn = src == DFT_SIGNS ? dft512_fn<DFT_SIGNS>()
-                         : (src == DFT_LIN_SIGNS ? dft512_fn<DFT_LIN_SIGNS>() : dft512_fn<DFT_LAG>());
+        const void *fn = src == DFT_LAG ? dft512_fn<DFT_LAG>() : dft512_fn<DFT_CODES>();
         ProfScope prof(s);
         hipError_t e = hipLaunchKernel(fn, grid, dim3(kD5Threads), args, L.dyn_bytes, s);
         prof.stop();
@@ -1220,7 +1236,9 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
             if (st != NDFT_OK) return st;
             return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n,
                               tau0, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A),
-                              static_cast<char *>(ws) + L.dft_off, DFT_SIGNS, true, s);
+                              static_cast<char *>(ws) + L.dft_off, DFT_SIGNS, true, s,
+                              reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off),
+                              L.n_cols_pad, (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
         }
     } else {
         uint4 *planes =
@@ -1286,7 +1304,9 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     // FP32: the twiddle half by FFT of the exact signs of the ordinary lag products
     return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
                       n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), static_cast<char *>(ws) + L.dft_off,
-                      DFT_LIN_SIGNS, true, s);
+                      DFT_LIN_SIGNS, true, s,
+                      reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off), L.n_cols_pad,
+                      (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
 }
 
 size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)

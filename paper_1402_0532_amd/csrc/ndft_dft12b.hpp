@@ -36,12 +36,20 @@ constexpr int kDftTile = 8192;    // complex samples per work-group
 constexpr int kDftThreads = 512;
 constexpr int kDftMaxLog = 9;     // L <= 512
 constexpr int DFT_LAG = 0, DFT_SIGNS = 1, DFT_LIN_SIGNS = 2;
+// DFT_CODES (whole-row kernel only): the exact signs as the 2-bit codes the twiddle-sign
+// kernel wrote (of whichever lag product it formed), read instead of recomputed.
+constexpr int DFT_CODES = 3;
 
 struct Dft12bParams {
     const float2 *s, *r;  // complex64 inputs, n samples each
     // the whole-row kernel (L = 512): the inputs with their exact signs, (re, im, sign re,
     // sign im): s4[n] and r4[2 n] (n zeros, then the reference, so r[m < 0] reads 0)
     const float4 *s4, *r4;
+    // DFT_CODES: the sign codes, [32-sample stage][code_cols][8] words (see ndft_signsplit.hpp),
+    // column l for delay row l; code_bytes of them (< 2^31)
+    const uint32_t *codes;
+    int code_cols;
+    unsigned code_bytes;
     int n, tau0, n_tau;
     int p0n, n_dop;       // first bin (reduced mod n) and bin count
     int M, MB, n_mg;      // phases, phases per work-group, work-groups per delay
@@ -251,42 +259,15 @@ __device__ __forceinline__ float2 dft_source_fast(float2 a, float2 b, bool &unsu
     }
 }
 
-// dft_source_fast from inputs that carry their signs (see with_signs), with the test for
-// the slow path kept as a running maximum (`flag` > 0: redo the lane's samples with
-// dft_source) instead of per-sample conditions:
-//   DFT_SIGNS: a component whose FP32 sum is 0 from a non-zero operator (cancellation):
-//     |t1| - 2^30 |zr| > 0 exactly then (a non-zero FP32 sum of t1 and t2 is at least
-//     2^-25 |t1|), and never for an exact zero (t1 = t2 = 0);
-//   DFT_LIN_SIGNS: a component within 2^-22 of its products' magnitude (2^-22 m - |z| > 0),
-//     or, for a sample pair that is not zero, a component whose products are below 2^-100
-//     (the tests of dft_source).
-template <int SRC>
-__device__ __forceinline__ float2 dft_source_signed(float4 s, float4 r, float &flag)
+// The Eq. (6) lag product from inputs that carry their signs (see with_signs), FP32 (the
+// value dft_source gives for DFT_LAG).
+__device__ __forceinline__ float2 lag_value_signed(float4 s, float4 r)
 {
-    if constexpr (SRC == DFT_LIN_SIGNS) {
-        const float p1 = s.x * r.x, p2 = s.y * r.y, p3 = s.y * r.x, p4 = s.x * r.y;
-        const float zr = p1 + p2, zi = p3 - p4;
-        const float mr = fabsf(p1) + fabsf(p2), mi = fabsf(p3) + fabsf(p4);
-        const float qr = fmaf(mr, 0x1p-22f, -fabsf(zr)), qi = fmaf(mi, 0x1p-22f, -fabsf(zi));
-        // a zero sample pair gives exact zeros; otherwise a component whose products are
-        // below 2^-100 (possibly underflowed) takes the slow path
-        const bool pair = (fabsf(s.x) + fabsf(s.y)) > 0.0f && (fabsf(r.x) + fabsf(r.y)) > 0.0f;
-        const float tiny = pair && fminf(mr, mi) < 0x1p-100f ? 1.0f : 0.0f;
-        flag = fmaxf(flag, fmaxf(fmaxf(qr, qi), tiny));
-        return make_float2(sgnf(zr), sgnf(zi));
-    } else {
-        const float t1 = fmaf(s.x, r.z, r.x * s.z); // s_r (x) r_r
-        const float t2 = fmaf(s.y, r.w, r.y * s.w); // s_i (x) r_i
-        const float t3 = fmaf(s.y, r.z, r.x * s.w); // s_i (x) r_r
-        const float t4 = fmaf(r.y, s.z, s.x * r.w); // r_i (x) s_r
-        const float zr = t1 + t2, zi = t3 - t4;
-        if constexpr (SRC == DFT_LAG) {
-            return make_float2(zr, zi);
-        } else {
-            flag = fmaxf(flag, fmaxf(fmaf(-0x1p30f, fabsf(zr), fabsf(t1)), fmaf(-0x1p30f, fabsf(zi), fabsf(t3))));
-            return make_float2(sgnf(zr), sgnf(zi));
-        }
-    }
+    const float t1 = fmaf(s.x, r.z, r.x * s.z); // s_r (x) r_r
+    const float t2 = fmaf(s.y, r.w, r.y * s.w); // s_i (x) r_i
+    const float t3 = fmaf(s.y, r.z, r.x * s.w); // s_i (x) r_r
+    const float t4 = fmaf(r.y, s.z, s.x * r.w); // r_i (x) s_r
+    return make_float2(t1 + t2, t3 - t4);
 }
 
 // The lag products and the first Stockham pass (p = 1: no inner twiddles) in one step:

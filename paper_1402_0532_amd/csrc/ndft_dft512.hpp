@@ -1,23 +1,26 @@
 // Decimated DFT of the lag-product rows for transform length L = 512 (N a multiple of 512,
 // at most 1024 requested bins): the fast path of dft12b_kernel (same sum, same readings):
 //   A[l][p] = sum_{m < M} W^{m p} Y_m[p mod 512],  Y_m[k] = sum_{t < 512} z[m + M t] W_512^{t k},
-// N = 512 M, z the lag products of delay d (DFT_LAG) or their exact signs (DFT_SIGNS,
-// DFT_LIN_SIGNS; bin p = 0 left out, see ndft_dft12b.hpp).
+// N = 512 M, z the lag products of delay d (DFT_LAG: the Eq. (12b) surface) or their exact
+// signs (DFT_CODES: the twiddle half of the Eq. (12a) and Eq. (12c) sign-split forms, bin
+// p = 0 left out, see ndft_dft12b.hpp).
 //
 // One work-group of 256 threads owns a whole delay row at a time and keeps its bins in
-// registers, so no partial surfaces are written. The inputs come with their exact signs
-// (a sign-prep pass: s4[n], and r4[2 n] with n zeros in front, so a delayed reference
-// needs no bounds test) through buffer loads whose scalar offset carries the stride of
-// the samples a lane takes. The phases go in groups of 16; each
-// 512-point transform is done as 32 x 16 (t = 16 a + b, k = c + 32 e):
+// registers, so no partial surfaces are written. DFT_LAG reads the inputs with their exact
+// signs (a sign-prep pass: s4[n], and r4[2 n] with n zeros in front, so a delayed reference
+// needs no bounds test); DFT_CODES reads the 2-bit sign codes the twiddle-sign kernel wrote
+// for the same call (4 bits a sample instead of 32 bytes, and no lag arithmetic). Both go
+// through buffer loads whose scalar offset carries the stride of the samples a lane takes.
+// The phases go in groups of 16; each 512-point transform is done as 32 x 16 (t = 16 a + b,
+// k = c + 32 e):
 //   pass 1: thread (j, b) loads the 32 samples a of transform j with residue b, makes their
-//           lag products, takes the 32-point DFT over a in registers and turns output c by
-//           W_512^{b c};
+//           lag products (or decodes their signs), takes the 32-point DFT over a in registers
+//           and turns output c by W_512^{b c};
 //   pass 2: after one exchange through LDS, thread (j, c) takes the 16-point DFT over b for
 //           two columns c, giving Y_j[c + 32 e];
-//   bins:   after a second exchange, each thread adds sum_j W^{(m0 + j) p} Y_j[p mod 512] for
-//           its bins, the twiddle stepped by W^p from phase to phase and taken afresh from
-//           the table at every group.
+//   bins:   after a second exchange, each thread adds W^{m0 p} sum_j (W^p)^j Y_j[p mod 512]
+//           for its bins, the inner sum by Horner's rule (four fused multiply-adds a phase),
+//           the group's factor W^{m0 p} from the table.
 // Two LDS exchanges and four barriers per 8192 samples, no inner-twiddle passes over LDS.
 //
 // LDS: pass-1 buffer at (c 16 + b) 17 + j (the 16 lanes of a row j are consecutive, the
@@ -117,10 +120,21 @@ __device__ __forceinline__ void reg_dft32(float2 (&u)[32])
     }
 }
 
+// The two signs of a code field pair as values: the 2-bit field at bits pr + 1 : pr (real
+// part) and pr - 3 : pr - 4 (imaginary part) read as a signed integer, 01 -> 1, 11 -> -1,
+// 00 -> 0.
+__device__ __forceinline__ float2 code_pair(unsigned w, int pr)
+{
+    // the builtin's result is typed unsigned: the sign-extended field is read back as int
+    const int re = (int)__builtin_amdgcn_sbfe(w, (unsigned)pr, 2u), im = (int)__builtin_amdgcn_sbfe(w, (unsigned)(pr - 4), 2u);
+    return make_float2((float)re, (float)im);
+}
+
 // Grid: x strides over the delays. Dynamic LDS: the two-level table of W_N.
 template <int SRC>
 __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
 {
+    static_assert(SRC == DFT_LAG || SRC == DFT_CODES, "lag products or their sign codes");
     __shared__ float2 X[kD5X];
     __shared__ float2 w512[512];
     extern __shared__ float2 tab[];
@@ -138,6 +152,9 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
         __builtin_amdgcn_make_buffer_rsrc((void *)P.s4, (short)0, n * 16, 0x00020000);
     const __amdgpu_buffer_rsrc_t rrs =
         __builtin_amdgcn_make_buffer_rsrc((void *)P.r4, (short)0, 2 * n * 16, 0x00020000);
+    // and of the sign codes (DFT_CODES)
+    const __amdgpu_buffer_rsrc_t crs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)P.codes, (short)0, (int)P.code_bytes, 0x00020000);
     // this thread's bins: q = tid + 256 u
     int bq[4], bp[4];
     float2 bstep[4];
@@ -162,10 +179,41 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
         }
         for (int m0 = 0; m0 < M; m0 += kD5Group) {
             const int mb = min(kD5Group, M - m0);
-            // ---- pass 1: lag products of transform j, residue hb; 32-point DFT; W_512^{b c} ----
+            // ---- pass 1: the 32 samples a of transform j, residue hb; 32-point DFT; W_512^{b c} ----
             float2 x[32];
-            float flag = 0.0f;
-            if (j < mb) {
+            if (j >= mb) {
+#pragma unroll
+                for (int a = 0; a < 32; ++a) x[a] = make_float2(0.0f, 0.0f);
+            } else if constexpr (SRC == DFT_CODES) {
+                // sample idx = base + 16 M a: its word ((idx / 32) code_cols + l) 8 + 4 h + q
+                // (h = bit 2, q = bits 4:3 of idx), real sign at bit pr of the word, imaginary
+                // at pr - 4 (pr = 14, 30, 12, 28 for idx mod 4 = 0 .. 3)
+                const int base = m0 + j + M * hb;
+                if ((M & 31) == 0) {
+                    // 16 M a is a whole number of stages: word position and field stay put,
+                    // the stage step goes in the scalar offset
+                    const unsigned vo =
+                        (((unsigned)(base >> 5) * (unsigned)P.code_cols + (unsigned)l) * 8u +
+                         (unsigned)(((base >> 2) & 1) * 4 + ((base >> 3) & 3))) * 4u;
+                    const unsigned step = (unsigned)(M >> 1) * (unsigned)P.code_cols * 32u;
+                    const int pr = ((base & 1) ? 30 : 14) - 2 * ((base >> 1) & 1);
+#pragma unroll
+                    for (int a = 0; a < 32; ++a) {
+                        const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(crs, vo, step * (unsigned)a, 0);
+                        x[a] = code_pair(w, pr);
+                    }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 32; ++a) {
+                        const int idx = base + 16 * M * a;
+                        const unsigned vo =
+                            (((unsigned)(idx >> 5) * (unsigned)P.code_cols + (unsigned)l) * 8u +
+                             (unsigned)(((idx >> 2) & 1) * 4 + ((idx >> 3) & 3))) * 4u;
+                        const int pr = ((idx & 1) ? 30 : 14) - 2 * ((idx >> 1) & 1);
+                        x[a] = code_pair(__builtin_amdgcn_raw_buffer_load_b32(crs, vo, 0, 0), pr);
+                    }
+                }
+            } else {
                 // sample idx = m0 + j + M (16 a + hb): one vector offset per lane, the step
                 // of a (16 M samples) in the scalar offset of each load
                 const unsigned vs = (unsigned)(m0 + j + M * hb) * 16u;
@@ -177,25 +225,7 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
                         float4, __builtin_amdgcn_raw_buffer_load_b128(srs, vs, step * (unsigned)a, 0));
                     const float4 rv = __builtin_bit_cast(
                         float4, __builtin_amdgcn_raw_buffer_load_b128(rrs, vr, step * (unsigned)a, 0));
-                    x[a] = dft_source_signed<SRC>(sv, rv, flag);
-                }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 32; ++a) x[a] = make_float2(0.0f, 0.0f);
-            }
-            // exact signs the FP32 values cannot give (zero or cancelling lag components):
-            // the lane's samples again through the exact path, rolled (rare)
-            if (SRC != DFT_LAG && __builtin_amdgcn_ballot_w64(flag > 0.0f)) {
-                if (flag > 0.0f) {
-#pragma unroll 1
-                    for (int a = 0; a < 32; ++a) {
-                        const int idx = m0 + j + M * (16 * a + hb);
-                        const float2 rv = idx >= d ? P.r[idx - d] : make_float2(0.0f, 0.0f);
-                        const float2 v = dft_source<SRC>(P.s[idx], rv);
-#pragma unroll
-                        for (int t = 0; t < 32; ++t)
-                            if (t == a) x[t] = v;
-                    }
+                    x[a] = lag_value_signed(sv, rv);
                 }
             }
             reg_dft32(x);
@@ -219,20 +249,20 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
                 for (int e = 0; e < 16; ++e) X[j * kD5YS + hb + 16 * h + 32 * e] = y[h][e];
             }
             __syncthreads();
-            // ---- bins: sum_j W^{(m0 + j) p} Y_j[p mod 512] ----
+            // ---- bins: sum_j W^{(m0 + j) p} Y_j[p mod 512] = W^{m0 p} sum_j (W^p)^j Y_j, the
+            // inner sum by Horner's rule from the group's last phase down ----
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (bq[u] < 0) continue;
                 const int k = bp[u] & 511;
-                float2 w = table_twiddle(coarse, fine, bv[u], P.tb);
-                float2 a = acc[u];
-                for (int jj = 0; jj < mb; ++jj) {
+                const float2 w = bstep[u];
+                float2 h = X[(mb - 1) * kD5YS + k];
+                for (int jj = mb - 2; jj >= 0; --jj) {
                     const float2 yv = X[jj * kD5YS + k];
-                    a.x = fmaf(w.x, yv.x, fmaf(-w.y, yv.y, a.x));
-                    a.y = fmaf(w.x, yv.y, fmaf(w.y, yv.x, a.y));
-                    w = cmulf(w, bstep[u]);
+                    h = make_float2(fmaf(h.x, w.x, fmaf(-h.y, w.y, yv.x)), fmaf(h.x, w.y, fmaf(h.y, w.x, yv.y)));
                 }
-                acc[u] = a;
+                const float2 g = table_twiddle(coarse, fine, bv[u], P.tb);
+                acc[u] = make_float2(fmaf(g.x, h.x, fmaf(-g.y, h.y, acc[u].x)), fmaf(g.x, h.y, fmaf(g.y, h.x, acc[u].y)));
                 bv[u] = (int)(((long long)bv[u] + (long long)kD5Group * bp[u]) % n);
             }
         }
@@ -241,7 +271,7 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
         for (int u = 0; u < 4; ++u) {
             if (bq[u] < 0) continue;
             float2 a = acc[u];
-            if (SRC != DFT_LAG && bp[u] == 0) a = make_float2(0.0f, 0.0f);
+            if (SRC == DFT_CODES && bp[u] == 0) a = make_float2(0.0f, 0.0f);
             if (P.accumulate) a = caddf(a, dst[bq[u]]);
             dst[bq[u]] = a;
         }

@@ -12,8 +12,8 @@
 // are W_n^m = e^{-j 2 pi m / n} rounded once from FP64, exact at the quadrant points.
 //
 // Rows of up to 8192 samples are transformed in LDS by one work-group (8192 / L rows at a
-// time): log2 L radix-2 Stockham passes, each lane holding its butterflies' outputs between
-// the two barriers of a pass. Longer rows (n = 2^s L, L = 8192) take the recursion's lower
+// time): the log2 L radix-2 levels go up to three per Stockham pass (nfft_group_pass: the
+// same butterflies, run in registers between the pass's two LDS barriers). Longer rows (n = 2^s L, L = 8192) take the recursion's lower
 // levels in LDS, as the transforms of the 2^s decimated sequences x[j + 2^s t], and its top
 // s levels as passes over global memory (nfft_combine_kernel): at stride S the transform of
 // x[j::S] is the combination of those of x[j::2S] and x[j + S::2S].
@@ -67,6 +67,66 @@ __device__ __forceinline__ float2 nfft_odd(float2 o, float2 w)
     return OUTER ? cmul_rn(o, w) : cop32(o, w);
 }
 
+__device__ __forceinline__ int bitrev_bits(int q, int bits)
+{
+    return (int)(__brev((unsigned)q) >> (32 - bits)) & ((1 << bits) - 1);
+}
+
+// LR consecutive radix-2 levels of the recursion, sub-length p -> 2^LR p, in one LDS round
+// trip (Stockham order). Group (row, i), i < n / R: k = i mod p; the thread loads the R
+// entries i + q n / R, which the LR levels combine among themselves only, and runs their
+// butterflies in registers with the operations of the radix-2 passes: at level l (sub-length
+// P = 2^l p) pair m < R / 2 takes (v[m], v[m + R/2]) with twiddle W_{2P}^{k + rev_l(m mod 2^l) p}
+// and gives v'[2m] = v[m] + t, v'[2m + 1] = v[m] - t; value q then belongs at
+// (i - k) R + k + rev_LR(q) p (rev_b: the b-bit reversal). The same butterflies on the same
+// operands as log2 R radix-2 passes, so the result is unchanged bit for bit.
+template <bool OUTER, int LR>
+__device__ __forceinline__ void nfft_group_pass(float2 *buf, int rows, int n, int lg, int p, const float2 *tw,
+                                                int tid)
+{
+    constexpr int R = 1 << LR, H = R / 2;
+    constexpr int CNT = kNfftMaxN / R / kNfftThreads;
+    const int lnr = lg - LR; // log2 of the groups per row
+    const int nr = 1 << lnr;
+    float2 v[CNT][R];
+    int base[CNT];
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        const int w = tid + c * kNfftThreads;
+        const int r = w >> lnr, i = w & (nr - 1);
+        base[c] = -1;
+        if (r < rows) {
+            const int k = i & (p - 1);
+            const float2 *row = buf + r * n;
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[c][q] = row[i + q * nr];
+#pragma unroll
+            for (int l = 0; l < LR; ++l) {
+                const int tstep = n >> (l + 1) >> (31 - __builtin_clz(p)); // n / (2 P), P = 2^l p
+                float2 nv[R];
+#pragma unroll
+                for (int m = 0; m < H; ++m) {
+                    const int t_idx = (k + (l ? bitrev_bits(m & ((1 << l) - 1), l) : 0) * p) * tstep;
+                    const float2 t = nfft_odd<OUTER>(v[c][m + H], tw[t_idx]);
+                    nv[2 * m] = make_float2(v[c][m].x + t.x, v[c][m].y + t.y);
+                    nv[2 * m + 1] = make_float2(v[c][m].x - t.x, v[c][m].y - t.y);
+                }
+#pragma unroll
+                for (int q = 0; q < R; ++q) v[c][q] = nv[q];
+            }
+            base[c] = r * n + (i - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CNT; ++c)
+        if (base[c] >= 0) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[base[c] + bitrev_bits(q, LR) * p] = v[c][q];
+        }
+    __syncthreads();
+}
+
 // Dynamic LDS: rpb rows of n entries, then n / 2 twiddles. Row groups g = blockIdx.x,
 // + gridDim.x, ... of rpb = 8192 / n rows each (n a power of two). Row r (of `rows`) is
 // read from x + (r / sub) * in_row + (r % sub) with element stride `sub` (sub = 1: plain
@@ -81,7 +141,7 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
     float2 *buf = nfft_lds, *tw = nfft_lds + (size_t)rpb * n;
     constexpr int CNT = kNfftMaxN / 2 / kNfftThreads;
     const int tid = threadIdx.x, h = n >> 1;
-    const int lh = 31 - __builtin_clz(max(h, 1)); // log2 of h (h >= 1 when n >= 2)
+    const int lg = 31 - __builtin_clz(n); // log2 n
     for (int m = tid; m < h; m += kNfftThreads) tw[m] = nfft_twiddle(m, n);
     for (long long b0 = (long long)blockIdx.x * rpb; b0 < rows_total; b0 += (long long)gridDim.x * rpb) {
         const int rows = (int)min((long long)rpb, rows_total - b0);
@@ -91,32 +151,19 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
             buf[i] = OUTER ? cop32(v, make_float2(1.0f, 0.0f)) : v; // the length-1 transforms
         }
         __syncthreads(); // also orders the table before its first use
-        for (int p = 1; p < n; p <<= 1) {
-            float2 y0[CNT], y1[CNT];
-            int dst[CNT];
-            const int tstep = n / (2 * p); // W_{2p}^k = W_n^{k n / 2p}
-#pragma unroll
-            for (int c = 0; c < CNT; ++c) {
-                const int w = tid + c * kNfftThreads; // butterfly i of row r
-                const int r = w >> lh, i = w & (h - 1);
-                dst[c] = -1;
-                if (r < rows) {
-                    const int k = i & (p - 1);
-                    const float2 *row = buf + r * n;
-                    const float2 u0 = row[i], t = nfft_odd<OUTER>(row[i + h], tw[k * tstep]);
-                    y0[c] = make_float2(u0.x + t.x, u0.y + t.y);
-                    y1[c] = make_float2(u0.x - t.x, u0.y - t.y);
-                    dst[c] = r * n + (i - k) * 2 + k;
-                }
+        // log2 n radix-2 levels, up to three of them per LDS round trip
+        for (int p = 1; p < n;) {
+            const int left = lg - (31 - __builtin_clz(p)); // levels still to do
+            if (left >= 3) {
+                nfft_group_pass<OUTER, 3>(buf, rows, n, lg, p, tw, tid);
+                p <<= 3;
+            } else if (left == 2) {
+                nfft_group_pass<OUTER, 2>(buf, rows, n, lg, p, tw, tid);
+                p <<= 2;
+            } else {
+                nfft_group_pass<OUTER, 1>(buf, rows, n, lg, p, tw, tid);
+                p <<= 1;
             }
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < CNT; ++c)
-                if (dst[c] >= 0) {
-                    buf[dst[c]] = y0[c];
-                    buf[dst[c] + p] = y1[c];
-                }
-            __syncthreads();
         }
         float2 *Xr = X + b0 * n;
         for (int i = tid; i < rows * n; i += kNfftThreads) Xr[i] = buf[i];

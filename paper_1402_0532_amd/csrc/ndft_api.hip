@@ -877,7 +877,8 @@ hipError_t g_dft_attr_err = hipSuccess;
 // code_bytes in all) that the twiddle-sign kernel wrote earlier on the same stream.
 ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t tau0,
                        int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, int src, bool accumulate,
-                       hipStream_t s, const uint32_t *codes = nullptr, int code_cols = 0, size_t code_bytes = 0)
+                       hipStream_t s, const uint32_t *codes = nullptr, int code_cols = 0, size_t code_bytes = 0,
+                       const TsumParams *tsum = nullptr)
 {
     std::call_once(g_dft_attr_once, [] {
         for (int lb = 0; lb <= kDftMaxLog; ++lb)
@@ -908,7 +909,10 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
     P.n_coarse = L.n_coarse;
     P.out = L.n_mg > 1 ? static_cast<float2 *>(ws) : A;
     P.accumulate = L.n_mg > 1 ? 0 : (accumulate ? 1 : 0);
+    TsumParams T;
+    std::memset(&T, 0, sizeof(T));
     void *args[] = {&P};
+    void *args5[] = {&P, &T};
     if (L.fast) {
         // two work-groups per compute unit, each taking whole delay rows in turn
         if (src == DFT_LAG) {
@@ -926,11 +930,12 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
             P.codes = codes;
             P.code_cols = code_cols;
             P.code_bytes = (unsigned)code_bytes;
+            if (tsum) T = *tsum; // the other half's planes, added here instead of by a reduction
         }
         const dim3 grid((unsigned)std::min<int64_t>(n_tau, 2LL * device_cu_count()));
         const void *fn = src == DFT_LAG ? dft512_fn<DFT_LAG>() : dft512_fn<DFT_CODES>();
         ProfScope prof(s);
-        hipError_t e = hipLaunchKernel(fn, grid, dim3(kD5Threads), args, L.dyn_bytes, s);
+        hipError_t e = hipLaunchKernel(fn, grid, dim3(kD5Threads), args5, L.dyn_bytes, s);
         prof.stop();
         if (e != hipSuccess) return NDFT_E_HIP;
         return check_launch();
@@ -1199,6 +1204,33 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     return launch_reduce(L, part, n, batch, k0, k_count, reinterpret_cast<float2 *>(X), s);
 }
 
+// The FP32 sign-split plans after lsum_kernel: the twiddle half as an FFT of the exact lag
+// signs (src DFT_SIGNS / DFT_LIN_SIGNS). The whole-row kernel reads the sign codes and adds
+// the twiddle-sign half's planes to its bins, writing A once; otherwise the reduction writes
+// that half into A and the FFT adds to it.
+ndft_status launch_fft_half(const Launch &L, const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0,
+                            int64_t n_tau, int64_t p0, int64_t n_dop, ndft_c64 *A, void *ws, int src, hipStream_t s)
+{
+    const float4 *part = reinterpret_cast<const float4 *>(ws);
+    const uint32_t *codes = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off);
+    const size_t code_bytes = (size_t)(L.k_codes / 32) * L.n_cols_pad * 32;
+    TsumParams T;
+    std::memset(&T, 0, sizeof(T));
+    if (L.dft.fast) {
+        T.part = part; // the fft_d plans have no matrix planes: lsum_kernel's come first
+        T.ksplit = L.ksplit + L.ksT;
+        T.cols_pad = L.n_cols_pad;
+        T.bases_pad = L.n_bases_pad;
+        T.bm = L.bm;
+    } else {
+        ndft_status st = launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
+        if (st != NDFT_OK) return st;
+    }
+    return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
+                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), static_cast<char *>(ws) + L.dft_off, src, true,
+                      s, codes, L.n_cols_pad, code_bytes, L.dft.fast ? &T : nullptr);
+}
+
 size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
 {
     if (!prec_ok(prec) || !caf_args_ok(n, tau0, n_tau, n_dop)) return 0;
@@ -1230,16 +1262,8 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     if (L.plan->lag_kfn) {
         st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
                           tau0, part, ws, s);
-        if (st == NDFT_OK && L.plan->fft_d) {
-            // the twiddle-sign half (and base 0) into A, then the twiddle half added by FFT
-            st = launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
-            if (st != NDFT_OK) return st;
-            return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n,
-                              tau0, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A),
-                              static_cast<char *>(ws) + L.dft_off, DFT_SIGNS, true, s,
-                              reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off),
-                              L.n_cols_pad, (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
-        }
+        if (st == NDFT_OK && L.plan->fft_d) return launch_fft_half(L, surv, ref, n, tau0, n_tau, p0, n_dop, A, ws,
+                                                                   DFT_SIGNS, s);
     } else {
         uint4 *planes =
             L.plan->planes_kfn ? reinterpret_cast<uint4 *>(static_cast<char *>(ws) + L.plane_off) : nullptr;
@@ -1299,14 +1323,9 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
                       tau0, part, ws, s);
     if (st != NDFT_OK) return st;
-    st = launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
-    if (st != NDFT_OK || !L.plan->fft_d) return st;
     // FP32: the twiddle half by FFT of the exact signs of the ordinary lag products
-    return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
-                      n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), static_cast<char *>(ws) + L.dft_off,
-                      DFT_LIN_SIGNS, true, s,
-                      reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off), L.n_cols_pad,
-                      (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
+    if (L.plan->fft_d) return launch_fft_half(L, surv, ref, n, tau0, n_tau, p0, n_dop, A, ws, DFT_LIN_SIGNS, s);
+    return launch_reduce(L, part, n, n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), s);
 }
 
 size_t ndft_caf12b_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)

@@ -28,9 +28,32 @@
 // table is the two-level one of ndft_device.hpp; W_512^k is a table of its own.
 #pragma once
 
+#include "ndft_contract.hpp"
 #include "ndft_dft12b.hpp"
 
 namespace ndft {
+
+// The twiddle-sign half's partial planes (DFT_CODES): [ksplit][cols_pad][bases_pad] float4
+// (U, V, X, Y) sums over sample ranges, rows in the order of bm. The whole-row kernel adds
+// them to its bins itself (the ordered sum and +b / -b assembly of reduce_element), so the
+// surface is written once. part == nullptr: no planes (the surface is written or added to
+// as P.accumulate says).
+struct TsumParams {
+    const float4 *part;
+    int ksplit, cols_pad, bases_pad;
+    BaseMap bm;
+};
+
+// Row of base b in a base map (b is one of its bases).
+__device__ __forceinline__ int row_of_base(const BaseMap &bm, int b)
+{
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < bm.nseg && b >= bm.start[k] && b - bm.start[k] < bm.off[k + 1] - bm.off[k])
+            r = bm.off[k] + (b - bm.start[k]);
+    return r;
+}
 
 constexpr int kD5Threads = 256;
 constexpr int kD5Group = 16;      // transforms per group
@@ -132,7 +155,7 @@ __device__ __forceinline__ float2 code_pair(unsigned w, int pr)
 
 // Grid: x strides over the delays. Dynamic LDS: the two-level table of W_N.
 template <int SRC>
-__global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
+__global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, TsumParams T)
 {
     static_assert(SRC == DFT_LAG || SRC == DFT_CODES, "lag products or their sign codes");
     __shared__ float2 X[kD5X];
@@ -167,18 +190,37 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
         bp[u] = p;
         bstep[u] = table_twiddle(coarse, fine, p, P.tb);
     }
+    // twiddle-sign planes: the row of each bin's base (bin p: base min(p, n - p)), and the
+    // planes' stride
+    int trow[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) trow[u] = row_of_base(T.bm, bp[u] <= (n >> 1) ? bp[u] : n - bp[u]);
+    const long long tplane = (long long)T.cols_pad * T.bases_pad;
+    const bool tsum = SRC == DFT_CODES && T.part != nullptr;
 
     for (int l = blockIdx.x; l < P.n_tau; l += gridDim.x) {
         const int d = P.tau0 + l;
         float2 acc[4];
         int bv[4]; // (m0 p) mod n of the current group
+        // the twiddle-sign half of the bins: plane g is read during group g (its load in
+        // flight through the group's transforms) and the planes are added in order
+        float4 tacc[4], tv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             acc[u] = make_float2(0.0f, 0.0f);
             bv[u] = 0;
+            tacc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        const float4 *trow_l = tsum ? T.part + (long long)l * T.bases_pad : nullptr;
         for (int m0 = 0; m0 < M; m0 += kD5Group) {
             const int mb = min(kD5Group, M - m0);
+            const int tg = m0 / kD5Group; // the plane this group reads
+            const bool tload = tsum && tg < T.ksplit;
+            if (tload) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (bq[u] >= 0) tv[u] = trow_l[tg * tplane + trow[u]];
+            }
             // ---- pass 1: the 32 samples a of transform j, residue hb; 32-point DFT; W_512^{b c} ----
             float2 x[32];
             if (j >= mb) {
@@ -265,6 +307,16 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
                 acc[u] = make_float2(fmaf(g.x, h.x, fmaf(-g.y, h.y, acc[u].x)), fmaf(g.x, h.y, fmaf(g.y, h.x, acc[u].y)));
                 bv[u] = (int)(((long long)bv[u] + (long long)kD5Group * bp[u]) % n);
             }
+            if (tload) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (bq[u] >= 0) {
+                        tacc[u].x += tv[u].x;
+                        tacc[u].y += tv[u].y;
+                        tacc[u].z += tv[u].z;
+                        tacc[u].w += tv[u].w;
+                    }
+            }
         }
         float2 *dst = P.out + (size_t)l * P.n_dop;
 #pragma unroll
@@ -272,7 +324,21 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P)
             if (bq[u] < 0) continue;
             float2 a = acc[u];
             if (SRC == DFT_CODES && bp[u] == 0) a = make_float2(0.0f, 0.0f);
-            if (P.accumulate) a = caddf(a, dst[bq[u]]);
+            if (tsum) {
+                // planes past the row's groups, then the +b (p <= n / 2) or -b assembly
+                float4 t = tacc[u];
+                for (int k = (M + kD5Group - 1) / kD5Group; k < T.ksplit; ++k) {
+                    const float4 v = trow_l[k * tplane + trow[u]];
+                    t.x += v.x;
+                    t.y += v.y;
+                    t.z += v.z;
+                    t.w += v.w;
+                }
+                a = caddf(a, bp[u] <= (n >> 1) ? make_float2(t.x - t.y, t.z + t.w)
+                                                : make_float2(t.x + t.y, t.z - t.w));
+            } else if (P.accumulate) {
+                a = caddf(a, dst[bq[u]]);
+            }
             dst[bq[u]] = a;
         }
     }

@@ -29,8 +29,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "fp8": 5000.0}  # dense MFMA peaks, MI355X
-VALU_FP32_TFLOPS = 157.3  # FP32 vector peak (256 CUs at 2.4 GHz, packed FMA counted)
+# Vector-unit peaks from the unit counts and the clock: 256 CUs x 4 SIMDs x 16 lanes at
+# 2.4 GHz issue 39.3 T lane operations/s; an FP32 FMA is 2 flops, so 78.6 TFLOP/s for
+# unpacked FP32 (the library is built without packed FP32 instructions; the published
+# 157.3 TFLOP/s counts packed FMAs).
+VALU_LANE_TOPS = 39.3216
+VALU_FP32_TFLOPS = 2.0 * VALU_LANE_TOPS
 KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_api.hip",
+                  "paper_1402_0532_amd/csrc/ndft_dft512.hpp",
                   "paper_1402_0532_amd/csrc/ndft_contract.hpp",
                   "paper_1402_0532_amd/csrc/ndft_device.hpp",
                   "paper_1402_0532_amd/csrc/ndft_dft12b.hpp",
@@ -48,7 +54,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(form: str):
+def load_traffic(form: str, half: str = "d_half"):
     """HBM bytes per contraction launch measured with rocprofv3 counters (FETCH_SIZE,
     WRITE_SIZE, calibrated on a copy kernel), if recorded for the current kernel source."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
@@ -62,7 +68,7 @@ def load_traffic(form: str):
                 rec[k.strip()] = v.strip()
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    key = "traffic_bytes_per_launch_" + form
+    key = "traffic_bytes_per_launch_" + form + ("_t_half" if half == "t_half" else "")
     return float(rec[key]) if key in rec else None
 
 
@@ -82,6 +88,17 @@ def fft_flops_per_row(n: int, n_dop: int) -> float:
     return 5.0 * L * math.log2(L) * M + 8.0 * M * n_dop if L > 1 else 8.0 * n * n_dop
 
 
+def tsum_ops(n: int, n_tau: int, p0: int, n_dop: int) -> float:
+    """Operations of the twiddle-sign half (lsum_kernel) for one surface: per delay and
+    sample the Eq. (6) lag product at the paper's count for one complex operator (4 sign,
+    8 abs, 6 add: 18) and 2 adds of the prefix sums; per delay, base b and part (real,
+    imaginary) 2 b sign changes of csgn(W^{bk}) over the n samples, each a +-2 P term
+    (2 ops: real and imaginary)."""
+    bases = {min((p0 + q) % n, n - (p0 + q) % n) for q in range(n_dop)}
+    crossings = sum(4 * b for b in bases)  # both parts
+    return float(n_tau) * (20.0 * n + 2.0 * crossings)
+
+
 def time_caf(nd, torch, s, r, geo, prec, steps, warmup, event_kernel=True):
     """(ms per call, event-timed main-kernel ms per launch) of ndft_caf on one stream."""
     n, tau0, n_tau, p0, n_dop = geo
@@ -92,6 +109,7 @@ def time_caf(nd, torch, s, r, geo, prec, steps, warmup, event_kernel=True):
         nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
     torch.cuda.synchronize()
     nd.prof_read()
+    nd.prof_read(1)
     nd.prof_enable(event_kernel)
     e0, e1 = _events(torch)
     e0.record()
@@ -101,6 +119,7 @@ def time_caf(nd, torch, s, r, geo, prec, steps, warmup, event_kernel=True):
     torch.cuda.synchronize()
     nd.prof_enable(False)
     k_ms, k_cnt = nd.prof_read()
+    nd.prof_read(1)
     return e0.elapsed_time(e1) / steps, (k_ms / k_cnt if k_cnt else None), out
 
 
@@ -262,6 +281,7 @@ def bench_adjoint(nd, synth, torch, args):
         torch.cuda.synchronize()
         reps = max(5, args.steps)
         nd.prof_read()
+        nd.prof_read(1)
         nd.prof_enable(True)
         e0, e1 = _events(torch)
         e0.record()
@@ -271,6 +291,7 @@ def bench_adjoint(nd, synth, torch, args):
         torch.cuda.synchronize()
         nd.prof_enable(False)
         kb_ms, kb_n = nd.prof_read()
+        nd.prof_read(1)
         ms_b = e0.elapsed_time(e1) / reps
         ms_f, kf_ms, _ = time_caf(nd, torch, s, r, (n,) + a, prec, reps, 3)
         kb = kb_ms / max(kb_n, 1)
@@ -416,7 +437,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=100)  # clocks settle after ~100 calls
-    ap.add_argument("--form", default="bf16x2", choices=["fp32", "bf16x2", "fp8"])
+    ap.add_argument("--form", default="fp32", choices=["fp32", "bf16x2", "fp8"],
+                    help="the reported form (default: FP32, the fastest and most accurate)")
     ap.add_argument("--forms", default="fp32,bf16x2,fp8", help="forms to time (comma list)")
     ap.add_argument("--autotune", action="store_true",
                     help="time every plan and split of the single-surface forms first and use the fastest "
@@ -486,6 +508,7 @@ def main():
             nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
         torch.cuda.synchronize()
         nd.prof_read()  # drop anything recorded before
+        nd.prof_read(1)
         nd.prof_enable(True)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -505,8 +528,10 @@ def main():
         wall = time.perf_counter() - t0
         nd.prof_enable(False)
         k_ms, k_cnt = nd.prof_read()
+        t_ms, t_cnt = nd.prof_read(1)
         ms = ev0.elapsed_time(ev1) / args.steps
         kern_ms = k_ms / max(k_cnt, 1)
+        tsum_ms = t_ms / t_cnt if t_cnt else None
         plan, ks = nd.get_plan(prec, n, n_tau, p0, n_dop)
         pname = nd.plan_name(prec, plan)
         # sign-split plans: the timed kernel is dsum_kernel, the twiddle x lag-sign half of
@@ -517,26 +542,39 @@ def main():
         fft = pname.startswith("fp32s_")
         if fft:
             kernel_flops = fft_flops_per_row(n, n_dop) * n_tau
-            bound, peak, kname = "alu", VALU_FP32_TFLOPS, (
-                "dft12b_kernel (twiddle half as a decimated FFT of the exact lag signs; 5 L log2 L flops per "
-                "length-L FFT plus 8 flops per phase term and bin)")
+            bound, peak, unit, kname = "alu", VALU_FP32_TFLOPS, "TFLOP/s", (
+                "dft512_kernel (twiddle half as a decimated FFT of the exact lag signs; 5 L log2 L flops per "
+                "length-L FFT plus 8 flops per phase term and bin; unpacked FP32 FMA peak)")
         else:
             kernel_flops = flops_per_call / 2 if split else flops_per_call
-            bound, peak = "mfma", PEAK_TFLOPS[form]
+            bound, peak, unit = "mfma", PEAK_TFLOPS[form], "TFLOP/s"
             kname = "dsum_kernel (8 N flops per cell)" if split else "contraction (16 N flops per cell)"
         achieved = kernel_flops / (kern_ms * 1e-3) / 1e12
+        kernels = {"d_half": {"kernel": kname, "ms": kern_ms, "bound": bound, "achieved": achieved,
+                              "peak": peak, "unit": unit, "frac": achieved / peak}}
+        if split and tsum_ms:
+            t_achieved = tsum_ops(n, n_tau, p0, n_dop) / (tsum_ms * 1e-3) / 1e12
+            kernels["t_half"] = {
+                "kernel": "lsum_kernel (twiddle-sign half: 18 ops per Eq. (6) lag product, 2 prefix adds per "
+                          "sample, 2 ops per sign change of csgn(W^{bk}); vector-lane operation peak)",
+                "ms": tsum_ms, "bound": "alu", "achieved": t_achieved, "peak": VALU_LANE_TOPS,
+                "unit": "Top/s", "frac": t_achieved / VALU_LANE_TOPS}
+        dom = max(kernels, key=lambda k: kernels[k]["ms"])  # the kernel that takes longest
         results[form] = {
             "cells_per_s": cells / (ms * 1e-3),
             "ms_per_step": ms,
             "wall_ms_per_step": wall * 1e3 / args.steps,
-            "timed_kernel_ms": kern_ms,
-            "timed_kernel_tflops": achieved,
-            "bound": bound,
-            "peak_tflops": peak,
-            "frac_of_peak": achieved / peak,
+            "timed_kernel_ms": kernels[dom]["ms"],
+            "timed_kernel_tflops": kernels[dom]["achieved"],
+            "bound": kernels[dom]["bound"],
+            "peak_tflops": kernels[dom]["peak"],
+            "unit": kernels[dom]["unit"],
+            "frac_of_peak": kernels[dom]["frac"],
             "plan": pname,
             "ksplit": ks,
-            "timed_kernel": kname,
+            "timed_kernel": kernels[dom]["kernel"],
+            "dominant": dom,
+            "kernels": kernels,
             "algorithmic_tflops_whole_call": flops_per_call / (ms * 1e-3) / 1e12,
         }
         if form in tuned:
@@ -638,9 +676,9 @@ def main():
             "bound": main_res["bound"],
             "achieved": main_res["timed_kernel_tflops"],
             "peak": main_res["peak_tflops"],
-            "unit": "TFLOP/s",
+            "unit": main_res["unit"],
             "frac": main_res["frac_of_peak"],
-            "traffic": load_traffic(args.form),
+            "traffic": load_traffic(args.form, main_res["dominant"]),
             "kernel": main_res["timed_kernel"],
         },
         "speedup_vs_plain_fp32": main_res["speedup_vs_plain_fp32"],

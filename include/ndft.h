@@ -305,12 +305,17 @@ ndft_status ndft_get_plan(ndft_prec prec, int64_t n, int64_t n_cols, int64_t p0,
 
 /* ---------------------------------------------------------------------------------
  * Timing of the contraction kernel: when enabled, every call records a pair of
- * hipEvents around its contraction launch on the call's stream. ndft_prof_read()
- * waits for the recorded events, returns the summed milliseconds and the number of
- * launches since the last read, and resets both. Process-wide, mutex-guarded.
+ * hipEvents around its contraction launch on the call's stream (the matrix-core kernel,
+ * or the FFT of the twiddle half for the FP32 sign-split plan), and the sign-split
+ * surfaces another pair around the twiddle-sign kernel. ndft_prof_read() waits for the
+ * contraction events, returns the summed milliseconds and the number of launches since
+ * the last read, and resets both; ndft_prof_read_slot(0, ...) is the same and slot 1 reads
+ * the twiddle-sign kernel's events (other slots: NDFT_E_INVAL). Process-wide,
+ * mutex-guarded.
  * ------------------------------------------------------------------------------- */
 ndft_status ndft_prof_enable(int32_t on);
 ndft_status ndft_prof_read(double *contract_ms, int64_t *launches);
+ndft_status ndft_prof_read_slot(int32_t slot, double *ms_sum, int64_t *launches);
 
 const char *ndft_status_string(ndft_status st);
 const char *ndft_version(void);

@@ -424,8 +424,12 @@ def prof_enable(on: bool = True) -> None:
     _lib.check(_lib.load().ndft_prof_enable(1 if on else 0), "ndft_prof_enable")
 
 
-def prof_read():
+def prof_read(slot: int = 0):
+    """Summed milliseconds and launch count of the timed kernel since the last read:
+    slot 0 the contraction (or the FP32 sign-split plan's FFT), slot 1 the twiddle-sign
+    kernel of the sign-split plans."""
     ms = ctypes.c_double()
     cnt = ctypes.c_int64()
-    _lib.check(_lib.load().ndft_prof_read(ctypes.byref(ms), ctypes.byref(cnt)), "ndft_prof_read")
+    _lib.check(_lib.load().ndft_prof_read_slot(int(slot), ctypes.byref(ms), ctypes.byref(cnt)),
+               "ndft_prof_read_slot")
     return ms.value, cnt.value

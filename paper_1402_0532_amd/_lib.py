@@ -45,6 +45,7 @@ SIGNATURES = {
     "ndft_get_plan": (_ST, [_I32, _I64, _I64, _I64, _I64, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "ndft_prof_enable": (_ST, [_I32]),
     "ndft_prof_read": (_ST, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "ndft_prof_read_slot": (_ST, [_I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "ndft_status_string": (ctypes.c_char_p, [_ST]),
     "ndft_version": (ctypes.c_char_p, []),
 }

@@ -588,7 +588,9 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 // set for the duration of an ndft_caf_noalloc call on this thread: no event records
 thread_local bool t_no_prof = false;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pending;
+// slot 0: the contraction (or its FFT) kernel; slot 1: the twiddle-sign kernel
+constexpr int kProfSlots = 2;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pending[kProfSlots];
 std::vector<hipEvent_t> g_event_pool;
 
 hipEvent_t take_event()
@@ -598,15 +600,18 @@ hipEvent_t take_event()
         g_event_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache write-back) when the event completes, so
+    // the records do not slow the kernels between them
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
 struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;
-    explicit ProfScope(hipStream_t st) : s(st)
+    int slot;
+    explicit ProfScope(hipStream_t st, int sl = 0) : s(st), slot(sl)
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on || t_no_prof) return;
@@ -619,7 +624,7 @@ struct ProfScope {
         if (!(a && b)) return;
         (void)hipEventRecord(b, s);
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof_pending.push_back({a, b});
+        g_prof_pending[slot].push_back({a, b});
         a = b = nullptr;
     }
 };
@@ -767,7 +772,10 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         void *targs[] = {&T};
         dim3 tgrid((unsigned)cdiv(n_cols, kLsumDelays), (unsigned)L.ksT, (unsigned)lsum_groups(L));
         const void *tfn = L.lin ? L.plan->lag_kfn_lin : L.plan->lag_kfn;
-        if (hipLaunchKernel(tfn, tgrid, dim3(256), targs, 0, stream) != hipSuccess) return NDFT_E_HIP;
+        ProfScope tprof(stream, 1);
+        const hipError_t te = hipLaunchKernel(tfn, tgrid, dim3(256), targs, 0, stream);
+        tprof.stop();
+        if (te != hipSuccess) return NDFT_E_HIP;
     }
     ndft_status st = check_launch();
     if (st != NDFT_OK || lsum_only || L.tiles_b == 0 || L.plan->fft_d) return st; // fft_d: the FFT runs after the reduction
@@ -1773,10 +1781,16 @@ ndft_status ndft_prof_enable(int32_t on)
 
 ndft_status ndft_prof_read(double *contract_ms, int64_t *launches)
 {
+    return ndft_prof_read_slot(0, contract_ms, launches);
+}
+
+ndft_status ndft_prof_read_slot(int32_t slot, double *ms_sum, int64_t *launches)
+{
+    if (slot < 0 || slot >= kProfSlots) return NDFT_E_INVAL;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pend;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        pend.swap(g_prof_pending);
+        pend.swap(g_prof_pending[slot]);
     }
     double total = 0.0;
     ndft_status st = NDFT_OK;
@@ -1793,7 +1807,7 @@ ndft_status ndft_prof_read(double *contract_ms, int64_t *launches)
             g_event_pool.push_back(ev.second);
         }
     }
-    if (contract_ms) *contract_ms = total;
+    if (ms_sum) *ms_sum = total;
     if (launches) *launches = (int64_t)pend.size();
     return st;
 }

@@ -198,7 +198,12 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
     const long long tplane = (long long)T.cols_pad * T.bases_pad;
     const bool tsum = SRC == DFT_CODES && T.part != nullptr;
 
-    for (int l = blockIdx.x; l < P.n_tau; l += gridDim.x) {
+    // Rows in an XCD-aware order: work-groups are dealt to the 8 XCDs in turn, so with a
+    // grid that is a multiple of 8 the work-groups of one XCD take consecutive rows (a
+    // 128-byte line of sign codes holds 4 neighbouring delays: read into one L2, not four).
+    const int G = (int)gridDim.x;
+    const int v = (G & 7) == 0 ? (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+    for (int l = v; l < P.n_tau; l += G) {
         const int d = P.tau0 + l;
         float2 acc[4];
         int bv[4]; // (m0 p) mod n of the current group

@@ -24,7 +24,8 @@
 // Two LDS exchanges and four barriers per 8192 samples, no inner-twiddle passes over LDS.
 //
 // LDS: pass-1 buffer at (c 16 + b) 17 + j (the 16 lanes of a row j are consecutive, the
-// four b of a wave 17 apart); pass-2 buffer at j 516 + k (rows 4 banks apart). The W_N
+// four b of a wave 17 apart); pass-2 buffer at j 513 + k (the 16 lanes of one column c
+// write rows j 2 banks apart: 513 float2 is 1026 words, 2 more than a multiple of 32). The W_N
 // table is the two-level one of ndft_device.hpp; W_512^k is a table of its own.
 #pragma once
 
@@ -59,7 +60,7 @@ constexpr int kD5Threads = 256;
 constexpr int kD5Group = 16;      // transforms per group
 constexpr int kD5MaxBins = 1024;  // requested bins (4 per thread)
 constexpr int kD5X = 32 * 16 * 17;
-constexpr int kD5YS = 516;
+constexpr int kD5YS = 513;
 
 // o times W_32^e = e^{-2 pi j e / 32} (e a constant after unrolling; 0 <= e < 32).
 __device__ __forceinline__ float2 mul_w32(float2 o, int e)

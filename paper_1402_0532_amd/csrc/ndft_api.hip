@@ -1383,7 +1383,7 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
         for (const void *fn : {reinterpret_cast<const void *>(&nfft_kernel<false>),
                                reinterpret_cast<const void *>(&nfft_kernel<true>)}) {
             const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)(kNfftMaxN + kNfftMaxN / 2) * (int)sizeof(float2));
+                                                     (int)(kNfftMaxN + kNfftMaxN / 8 + kNfftMaxN) * (int)sizeof(float2));
             if (e != hipSuccess && attr == hipSuccess) attr = e;
         }
     });
@@ -1405,8 +1405,12 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
     // the last top level writes X: the LDS stage writes X after an even number of levels
     float2 *first = (lev % 2 == 0) ? Xo : buf;
     const int rpb = kNfftMaxN / L;
-    const size_t shmem = ((size_t)rpb * L + L / 2) * sizeof(float2);
-    const int64_t grid = std::min<int64_t>(cdiv(rows, rpb), 8LL * device_cu_count());
+    // padded rows (one entry per 8 more), then the per-level twiddle table (L - 1 entries)
+    const size_t shmem = ((size_t)rpb * L + (size_t)rpb * L / 8 + L) * sizeof(float2);
+    // as many work-groups as fit on the device at once (160 KB of LDS per compute unit),
+    // each looping over row groups: the twiddle table is built once per work-group
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)shmem);
+    const int64_t grid = std::min<int64_t>(cdiv(rows, rpb), per_cu * device_cu_count());
     ProfScope prof(s);
     if (outer)
         hipLaunchKernelGGL(nfft_kernel<true>, dim3((unsigned)grid), dim3(kNfftThreads), shmem, s, xin, first, rows, L,

@@ -13,7 +13,11 @@
 //
 // Rows of up to 8192 samples are transformed in LDS by one work-group (8192 / L rows at a
 // time): the log2 L radix-2 levels go up to three per Stockham pass (nfft_group_pass: the
-// same butterflies, run in registers between the pass's two LDS barriers). Longer rows (n = 2^s L, L = 8192) take the recursion's lower
+// same butterflies, run in registers between the pass's two LDS barriers). LDS entry e of
+// the rows sits at e + e / 8 (a pad after every 8: the first pass writes each lane's 8
+// outputs side by side, which would put 16 lanes on 2 bank pairs), and the twiddles of
+// level P (sub-length P, W_{2P}^k for k < P) are stored contiguously at P - 1 + k, so the
+// lanes of a butterfly level read consecutive entries. Longer rows (n = 2^s L, L = 8192) take the recursion's lower
 // levels in LDS, as the transforms of the 2^s decimated sequences x[j + 2^s t], and its top
 // s levels as passes over global memory (nfft_combine_kernel): at stride S the transform of
 // x[j::S] is the combination of those of x[j::2S] and x[j + S::2S].
@@ -72,6 +76,24 @@ __device__ __forceinline__ int bitrev_bits(int q, int bits)
     return (int)(__brev((unsigned)q) >> (32 - bits)) & ((1 << bits) - 1);
 }
 
+// LDS slot of row entry e (one pad entry after every 8)
+__device__ __forceinline__ int nfft_pad(int e) { return e + (e >> 3); }
+
+// The per-level twiddle table of length-n rows in LDS: entry j < n - 1 holds, for level
+// P = the largest power of two <= j + 1 and k = j + 1 - P, W_{2P}^k = W_n^{k n / (2P)}. The
+// top level (P = n / 2: W_n^k) is evaluated, the lower levels are copied from it.
+__device__ __forceinline__ void nfft_level_table(float2 *tw, int n, int tid)
+{
+    const int h = n >> 1;
+    float2 *top = tw + h - 1;
+    for (int k = tid; k < h; k += kNfftThreads) top[k] = nfft_twiddle(k, n);
+    __syncthreads();
+    for (int j = tid; j < h - 1; j += kNfftThreads) {
+        const int P = 1 << (31 - __builtin_clz(j + 1));
+        tw[j] = top[(j + 1 - P) * (h / P)];
+    }
+}
+
 // LR consecutive radix-2 levels of the recursion, sub-length p -> 2^LR p, in one LDS round
 // trip (Stockham order). Group (row, i), i < n / R: k = i mod p; the thread loads the R
 // entries i + q n / R, which the LR levels combine among themselves only, and runs their
@@ -97,17 +119,17 @@ __device__ __forceinline__ void nfft_group_pass(float2 *buf, int rows, int n, in
         base[c] = -1;
         if (r < rows) {
             const int k = i & (p - 1);
-            const float2 *row = buf + r * n;
+            const int row = r * n;
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[c][q] = row[i + q * nr];
+            for (int q = 0; q < R; ++q) v[c][q] = buf[nfft_pad(row + i + q * nr)];
 #pragma unroll
             for (int l = 0; l < LR; ++l) {
-                const int tstep = n >> (l + 1) >> (31 - __builtin_clz(p)); // n / (2 P), P = 2^l p
+                const float2 *twl = tw + (p << l) - 1; // level P = 2^l p: W_{2P}^j at j
                 float2 nv[R];
 #pragma unroll
                 for (int m = 0; m < H; ++m) {
-                    const int t_idx = (k + (l ? bitrev_bits(m & ((1 << l) - 1), l) : 0) * p) * tstep;
-                    const float2 t = nfft_odd<OUTER>(v[c][m + H], tw[t_idx]);
+                    const float2 t =
+                        nfft_odd<OUTER>(v[c][m + H], twl[k + (l ? bitrev_bits(m & ((1 << l) - 1), l) : 0) * p]);
                     nv[2 * m] = make_float2(v[c][m].x + t.x, v[c][m].y + t.y);
                     nv[2 * m + 1] = make_float2(v[c][m].x - t.x, v[c][m].y - t.y);
                 }
@@ -122,12 +144,13 @@ __device__ __forceinline__ void nfft_group_pass(float2 *buf, int rows, int n, in
     for (int c = 0; c < CNT; ++c)
         if (base[c] >= 0) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) buf[base[c] + bitrev_bits(q, LR) * p] = v[c][q];
+            for (int q = 0; q < R; ++q) buf[nfft_pad(base[c] + bitrev_bits(q, LR) * p)] = v[c][q];
         }
     __syncthreads();
 }
 
-// Dynamic LDS: rpb rows of n entries, then n / 2 twiddles. Row groups g = blockIdx.x,
+// Dynamic LDS: rpb rows of n entries (padded: 9/8 of that), then the n - 1 entries of the
+// per-level twiddle table. Row groups g = blockIdx.x,
 // + gridDim.x, ... of rpb = 8192 / n rows each (n a power of two). Row r (of `rows`) is
 // read from x + (r / sub) * in_row + (r % sub) with element stride `sub` (sub = 1: plain
 // rows; sub = 2^s: the decimated sequences of a long row of in_row = n sub samples) and
@@ -138,17 +161,16 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
                                                            long long in_row)
 {
     extern __shared__ float2 nfft_lds[];
-    float2 *buf = nfft_lds, *tw = nfft_lds + (size_t)rpb * n;
-    constexpr int CNT = kNfftMaxN / 2 / kNfftThreads;
-    const int tid = threadIdx.x, h = n >> 1;
+    float2 *buf = nfft_lds, *tw = nfft_lds + nfft_pad(rpb * n);
+    const int tid = threadIdx.x;
     const int lg = 31 - __builtin_clz(n); // log2 n
-    for (int m = tid; m < h; m += kNfftThreads) tw[m] = nfft_twiddle(m, n);
+    nfft_level_table(tw, n, tid);
     for (long long b0 = (long long)blockIdx.x * rpb; b0 < rows_total; b0 += (long long)gridDim.x * rpb) {
         const int rows = (int)min((long long)rpb, rows_total - b0);
         for (int i = tid; i < rows * n; i += kNfftThreads) {
             const long long r = b0 + i / n;
             const float2 v = x[(r / sub) * in_row + (r % sub) + (long long)sub * (i % n)];
-            buf[i] = OUTER ? cop32(v, make_float2(1.0f, 0.0f)) : v; // the length-1 transforms
+            buf[nfft_pad(i)] = OUTER ? cop32(v, make_float2(1.0f, 0.0f)) : v; // the length-1 transforms
         }
         __syncthreads(); // also orders the table before its first use
         // log2 n radix-2 levels, up to three of them per LDS round trip
@@ -166,7 +188,7 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
             }
         }
         float2 *Xr = X + b0 * n;
-        for (int i = tid; i < rows * n; i += kNfftThreads) Xr[i] = buf[i];
+        for (int i = tid; i < rows * n; i += kNfftThreads) Xr[i] = buf[nfft_pad(i)];
         __syncthreads(); // buf is refilled for the next row
     }
 }

@@ -507,9 +507,7 @@ def main():
         for _ in range(args.warmup):
             nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
         torch.cuda.synchronize()
-        nd.prof_read()  # drop anything recorded before
-        nd.prof_read(1)
-        nd.prof_enable(True)
+        # the timed steps: nothing but the calls
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -518,6 +516,21 @@ def main():
         for _ in range(args.steps):
             nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
         ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1) / args.steps
+        # the same steps again with the library's kernel events on (each call then records
+        # two event pairs on its stream, which costs the call a few microseconds): the
+        # duration of each half's kernel
+        nd.prof_read()  # drop anything recorded before
+        nd.prof_read(1)
+        nd.prof_enable(True)
+        ev2 = torch.cuda.Event(enable_timing=True)
+        ev3 = torch.cuda.Event(enable_timing=True)
+        ev2.record()
+        for _ in range(args.steps):
+            nd.caf(s, r, tau0, n_tau, p0, n_dop, prec, out=out, ws=ws)
+        ev3.record()
         if args.calib_copy_mib:
             src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
             dst = torch.empty_like(src)
@@ -525,19 +538,19 @@ def main():
                 dst.copy_(src)
             del src, dst
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         nd.prof_enable(False)
         k_ms, k_cnt = nd.prof_read()
         t_ms, t_cnt = nd.prof_read(1)
-        ms = ev0.elapsed_time(ev1) / args.steps
+        ms_instr = ev2.elapsed_time(ev3) / args.steps
         kern_ms = k_ms / max(k_cnt, 1)
         tsum_ms = t_ms / t_cnt if t_cnt else None
         plan, ks = nd.get_plan(prec, n, n_tau, p0, n_dop)
         pname = nd.plan_name(prec, plan)
-        # sign-split plans: the timed kernel is dsum_kernel, the twiddle x lag-sign half of
-        # the algorithmic work; the twiddle-sign half runs in lsum_kernel (vector units).
-        # The FP32 sign-split plan takes that half as a decimated FFT (dft12b_kernel): its
-        # bound is the vector units, its work the FFT's flops, not 8 N per cell.
+        # sign-split plans: the D half (twiddle x lag signs) is dsum_kernel on the matrix
+        # cores (8 N flops per cell), or for the FP32 plan a decimated FFT of the exact lag
+        # signs (dft512_kernel: the FFT's flops on the vector units); the T half (twiddle
+        # signs x lag values) is lsum_kernel on the vector units. The roofline is the half
+        # whose kernel takes longer.
         split = pname.startswith(SPLIT_PLAN_PREFIXES)
         fft = pname.startswith("fp32s_")
         if fft:
@@ -564,6 +577,7 @@ def main():
             "cells_per_s": cells / (ms * 1e-3),
             "ms_per_step": ms,
             "wall_ms_per_step": wall * 1e3 / args.steps,
+            "ms_per_step_with_kernel_events": ms_instr,
             "timed_kernel_ms": kernels[dom]["ms"],
             "timed_kernel_tflops": kernels[dom]["achieved"],
             "bound": kernels[dom]["bound"],

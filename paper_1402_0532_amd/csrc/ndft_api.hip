@@ -644,6 +644,26 @@ ndft_status launch_prep(const float2 *x, float4 *out, int64_t n, int64_t rows, i
     return check_launch();
 }
 
+// The surveillance and the reference rows with their signs in one launch: s -> s4 (s_len
+// entries, s from 0), r -> r4 (r_len entries, r from r_lead).
+ndft_status launch_prep_pair(const float2 *s, float4 *s4, int64_t s_len, const float2 *r, float4 *r4, int64_t r_len,
+                             int64_t r_lead, int64_t n, float g, hipStream_t stream)
+{
+    PrepPair Q;
+    Q.x[0] = s;
+    Q.x[1] = r;
+    Q.out[0] = s4;
+    Q.out[1] = r4;
+    Q.ostride[0] = s_len;
+    Q.ostride[1] = r_len;
+    Q.lead[0] = 0;
+    Q.lead[1] = (int)r_lead;
+    const int64_t len = std::max(s_len, r_len);
+    if (len == 0) return NDFT_OK;
+    hipLaunchKernelGGL(sign_prep_pair_kernel, dim3((unsigned)cdiv(len, 256), 2), dim3(256), 0, stream, Q, (int)n, g);
+    return check_launch();
+}
+
 // FP8 combined kernel: the largest |re| + |im| of each input (one word each) into the
 // workspace slot, cleared first by a kernel of its own (no memset in the stream).
 ndft_status launch_absmax(unsigned *w, const float2 *a, int64_t na, const float2 *b, int64_t nb, hipStream_t s)
@@ -927,8 +947,7 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
             // the inputs with their exact signs (the reference after n zeros)
             float4 *s4 = static_cast<float4 *>(ws);
             float4 *r4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + align256((size_t)n * sizeof(float4)));
-            ndft_status st = launch_prep(surv, s4, n, 1, n, 0, 1.0f, s);
-            if (st == NDFT_OK) st = launch_prep(ref, r4, n, 1, 2 * n, n, 1.0f, s);
+            ndft_status st = launch_prep_pair(surv, s4, n, ref, r4, 2 * n, n, n, 1.0f, s);
             if (st != NDFT_OK) return st;
             P.s4 = s4;
             P.r4 = r4;
@@ -1263,8 +1282,8 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     float4 *r4 = s4 + n + kTailPad; // n zeros, then the reference, then a zero tail
     if (!L.plan->raw_inputs) {
         const float g = L.plan->sign_scale;
-        st = launch_prep(reinterpret_cast<const float2 *>(surv), s4, n, 1, n + kTailPad, 0, g, s);
-        if (st == NDFT_OK) st = launch_prep(reinterpret_cast<const float2 *>(ref), r4, n, 1, 2 * n + kTailPad, n, g, s);
+        st = launch_prep_pair(reinterpret_cast<const float2 *>(surv), s4, n + kTailPad,
+                              reinterpret_cast<const float2 *>(ref), r4, 2 * n + kTailPad, n, n, g, s);
         if (st != NDFT_OK) return st;
     }
     if (L.plan->lag_kfn) {

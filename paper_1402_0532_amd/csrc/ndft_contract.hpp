@@ -108,6 +108,24 @@ __global__ __launch_bounds__(256) void sign_prep_kernel(const float2 *__restrict
     out[k] = (j >= 0 && j < n) ? with_signs(x[row * n + j], g) : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Two single-row sign preps in one launch (blockIdx.y 0: x0 -> out0, 1: x1 -> out1), each as
+// sign_prep_kernel with rows = 1: out[k] = x[k - lead] with its signs, zero outside [0, n).
+struct PrepPair {
+    const float2 *x[2];
+    float4 *out[2];
+    long long ostride[2];
+    int lead[2];
+};
+
+__global__ __launch_bounds__(256) void sign_prep_pair_kernel(PrepPair Q, int n, float g)
+{
+    const int y = blockIdx.y;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= Q.ostride[y]) return;
+    const long long j = k - Q.lead[y];
+    Q.out[y][k] = (j >= 0 && j < n) ? with_signs(Q.x[y][j], g) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
 {
     bf16x2v v = {(__bf16)lo, (__bf16)hi};

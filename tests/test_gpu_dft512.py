@@ -4,7 +4,9 @@ sign-split form of Eq. (12a) (its twiddle half: the exact lag signs) and the FP3
 Eq. (12c) (signs of the ordinary lag product), each against the FP64 oracle on sampled
 delay rows. The shapes cover a ragged last group of transforms (M not a multiple of 16),
 a single group, the largest bin window, one bin, bins starting at 0 and wrapping past N,
-and delay rows near the end of the record (mostly zero lag products).
+delay rows near the end of the record (mostly zero lag products), and more rows than the
+work-groups (taken in XCD order) cover in one pass. The sign halves read the sign codes of
+the twiddle-sign kernel and add its partial planes themselves.
 Tolerance: l1-relative per output <= 1e-5 (FP32)."""
 import numpy as np
 import pytest
@@ -45,6 +47,7 @@ SHAPES = [
     (8192, 7990, 192, 4000, 1, "gauss"),      # delays up to N - 10, one bin near N/2
     (4096, 3, 300, -200, 400, "int_zeros"),   # M = 8: a single partial group
     (16384, 1, 256, 16000, 700, "gauss"),     # bins wrapping past N
+    (12288, 0, 520, -100, 200, "int_zeros"),  # 520 rows over 512 work-groups in XCD order
 ]
 
 
@@ -85,6 +88,7 @@ SPLIT_SHAPES = [
     (8704, 0, 130, 0, 34, "int_zeros"),       # M = 17, bins from 0 (bin 0 summed apart)
     (8192, 7990, 192, -16, 32, "gauss"),      # delays near the end of the record
     (16384, 1, 256, 16320, 128, "gauss"),     # bins wrapping past N
+    (10240, 0, 600, -40, 80, "gauss"),        # M = 20; 600 rows over 512 work-groups in XCD order
 ]
 
 

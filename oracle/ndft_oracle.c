@@ -516,8 +516,14 @@ int oracle_caf_loss_fd(const double *s, const double *r, int64_t n, int64_t tau0
 {
     if (n < 1 || tau0 < 0 || n_tau < 0 || tau0 + n_tau > n || n_dop < 0) return 1;
     double *A = (double *)malloc(sizeof(double) * 2 * (size_t)(n_tau * n_dop));
-    if (!A) return 2;
+    double *tw = (double *)malloc(sizeof(double) * 2 * (size_t)n); /* W^v, v < n, as oracle_twiddle gives it */
+    if (!A || !tw) {
+        free(A);
+        free(tw);
+        return 2;
+    }
     oracle_caf(s, r, n, tau0, n_tau, p0, n_dop, NULL, 0, A, NULL);
+    for (int64_t v = 0; v < n; ++v) oracle_twiddle(v, n, tw + 2 * v);
 #pragma omp parallel for schedule(dynamic)
     for (int64_t k = 0; k < n_coords; ++k) {
         int64_t m = coords[k] / 2;
@@ -541,8 +547,7 @@ int oracle_caf_loss_fd(const double *s, const double *r, int64_t n, int64_t tau0
                     double re = A[2 * (l * n_dop + q)], im = A[2 * (l * n_dop + q) + 1];
                     if (touched) {
                         int64_t p = mod_n(p0 + q, n);
-                        double wv[2];
-                        oracle_twiddle(mod_n(i * p, n), n, wv);
+                        const double *wv = tw + 2 * mod_n(i * p, n);
                         re += (rop_x(zn_r, wv[0]) - rop_x(zn_i, wv[1])) -
                               (rop_x(zo_r, wv[0]) - rop_x(zo_i, wv[1]));
                         im += (rop_x(zn_i, wv[0]) + rop_x(zn_r, wv[1])) -
@@ -556,6 +561,7 @@ int oracle_caf_loss_fd(const double *s, const double *r, int64_t n, int64_t tau0
         out[k] = (Lside[0] - Lside[1]) / (2.0 * h);
     }
     free(A);
+    free(tw);
     return 0;
 }
 

@@ -96,40 +96,35 @@ def test_config5_gradient_vs_oracle(nd, cfg5, prec):
 
 
 def test_config5_gradient_vs_finite_differences(nd, orc, cfg5):
-    # central differences (h = 1e-4, FP64) of the literal loss at sampled coordinates,
-    # skipping those whose +-h step crosses a lag-product sign change
+    # central differences (h = 1e-4, FP64) of the literal loss at every real coordinate of
+    # r (2N of them), skipping those whose +-h step can move a lag-product component across
+    # zero (the loss jumps there: Eq. (6) applied to the lag product and the twiddle)
     c, A, G, gro, gso = cfg5
-    n = c["n"]
-    rng = np.random.default_rng(55)
-    coords = np.sort(rng.choice(2 * n, 48, replace=False))
-    fd = orc.caf_loss_fd(c["s"], c["r"], c["tau0"], c["n_tau"], c["p0"], c["n_dop"], c["w"], coords, 1e-4)
+    n, h = c["n"], 1e-4
+    coords = np.arange(2 * n)
+    fd = orc.caf_loss_fd(c["s"], c["r"], c["tau0"], c["n_tau"], c["p0"], c["n_dop"], c["w"], coords, h)
     args = (c["tau0"], c["n_tau"], c["p0"], c["n_dop"])
     gr, _ = nd.caf_backward(dev(c["s"]), dev(c["r"]), *args, dev((2.0 * c["w"] * A).astype(np.complex64)),
                             prec=0, need_grad_s=False)
     gr = gr.cpu().numpy().astype(np.complex128)
     ana = np.where(coords % 2 == 0, gr[coords // 2].real, gr[coords // 2].imag)
-    keep = []
-    s64 = c["s"].astype(np.complex128)
+    # r[m] moves the lag products z_l[m + d] of every delay d; a step of h in one part of
+    # r[m] moves each component of s (x) conj(r) by at most h (the operator's slope is +-1
+    # in each operand away from 0), so a component within 2h of zero may change sign
+    near = np.zeros(n, bool)
+    for l in range(c["n_tau"]):
+        d = c["tau0"] + l
+        z, _ = orc.lag_row(c["s"], c["r"], d)
+        zz = z[d:]
+        near[: n - d] |= (np.abs(zz.real) <= 2 * h) | (np.abs(zz.imag) <= 2 * h)
     r64 = c["r"].astype(np.complex128)
-    for k, cc in enumerate(coords):
-        m, part = cc // 2, cc % 2
-        ok = True
-        for l in range(c["n_tau"]):
-            i = m + c["tau0"] + l
-            if i >= n:
-                break
-            for dlt in (-1e-4, 1e-4):
-                rp = r64[m] + (dlt if part == 0 else 1j * dlt)
-                z0, sg0 = orc.lag_row(s64[i:i + 1], np.array([r64[m]]), 0)
-                z1, sg1 = orc.lag_row(s64[i:i + 1], np.array([rp]), 0)
-                if np.any(sg0 != sg1):
-                    ok = False
-        keep.append(ok)
-    keep = np.array(keep)
-    assert keep.sum() >= 40
+    near |= (np.abs(r64.real) <= 2 * h) | (np.abs(r64.imag) <= 2 * h)  # an operand crossing 0
+    keep = ~near[coords // 2]
+    assert keep.mean() >= 0.9, keep.mean()
     sr, _ = grad_scales(G, n, c["tau0"])
     err = np.abs(ana - fd) / sr[coords // 2]
-    print("config5 GPU gradient vs FD, max l1-relative error", float(err[keep].max()), flush=True)
+    print("config5 GPU gradient vs FD on %d of %d coordinates, max l1-relative error %.3g"
+          % (keep.sum(), 2 * n, float(err[keep].max())), flush=True)
     assert np.all(err[keep] <= 1e-5)
 
 

@@ -507,10 +507,13 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         pi = lin ? -1 : 0;
         for (int k = 0; k < (int)ps.size(); ++k) {
             if (!usable(k)) continue;
-            // sign-split: the twiddle-sign part walks ~4 b C / N sign runs per base b and
-            // chunk of C samples; taken only while that stays about one per chunk (the
-            // Eq. (12c) surface has no other form: the walk is exact for any base)
-            if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * kLsumChunk > n) continue;
+            // sign-split: the twiddle-sign part walks 2 b C / N sign changes per base b, part
+            // and chunk of C samples; taken while that stays at most 2 (b C <= N) for the
+            // matrix-core plans, whose twiddle half is dense in the bases anyway, and at most
+            // 8 (b C / 4 <= N) for the FP32 plan, whose FFT half costs the same for any
+            // window (the Eq. (12c) surface has no other form: the walk is exact for any base)
+            const int64_t runs_c = ps[k].fft_d ? kLsumChunk / 4 : kLsumChunk;
+            if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * runs_c > n) continue;
             // the FFT of the twiddle half wants a power-of-two factor of at least 64 in n
             if (!lin && ps[k].fft_d && n % 64 != 0) continue;
             const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);

@@ -393,6 +393,33 @@ def dc65536(orc):
     return (s, r, n, tau0, n_tau, p0, n_dop, rows), T, A, sc
 
 
+@pytest.fixture(scope="module")
+def dc16384(orc):
+    # bins -256..255 at N = 16384: 64 b = N, the limit where the built-in choice still takes
+    # the FP32 sign-split plan (8 sign changes per part and 256-sample chunk at b = 256)
+    n, tau0, n_tau, p0, n_dop = 16384, 0, 128, -256, 512
+    s, r = dc_pair(n, 62)
+    rows = np.array([0, 1, 33, 90, 127])
+    z, sg = oracle_lag_rows(orc, s, r, tau0 + rows)
+    T = oracle_T(orc, z, sg, n, p0, n_dop)
+    A, sc = orc.caf(s, r, tau0, n_tau, p0, n_dop, rows=rows)
+    return (s, r, n, tau0, n_tau, p0, n_dop, rows), T, A, sc
+
+
+def test_twiddle_sign_half_rounding_dc_rows_fp32_limit(nd, dc16384):
+    (s, r, n, tau0, n_tau, p0, n_dop, rows), Tref, Aref, sc = dc16384
+    plan, _ = nd.get_plan(0, n, n_tau, p0, n_dop)
+    name = nd.plan_name(0, plan)
+    assert name.startswith("fp32s_"), name
+    _, T = nd.dbg_split(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=0, lag=False)
+    eT = rel_err(T.cpu().numpy()[rows], Tref, sc)
+    A = nd.caf(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=0).cpu().numpy()
+    eA = rel_err(A[rows], Aref, sc)
+    log("DC rows at the FP32 plan's limit, plan", name, "T half l1-relative error", eT, "whole cell", eA)
+    assert eT <= 5e-6
+    assert eA <= TOL[0]
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_twiddle_sign_half_rounding_dc_rows(nd, dc65536, prec):
     (s, r, n, tau0, n_tau, p0, n_dop, rows), Tref, Aref, sc = dc65536

@@ -207,8 +207,8 @@ Plan make_split_plan(const char *name, double rel_cost)
     p.sign_scale = 0.5f;
     p.planes_kfn = GEN ? nullptr : reinterpret_cast<const void *>(&dplane_build_kernel<Cfg::BT, KS>);
     p.raw_inputs = true;
-    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel<false>);
-    p.lag_kfn_lin = reinterpret_cast<const void *>(&lsum_kernel<true>);
+    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel<false, false>);
+    p.lag_kfn_lin = reinterpret_cast<const void *>(&lsum_kernel<true, false>);
     p.fft_d = false;
     p.stage_a = Cfg::STAGE_A;
     return p;
@@ -222,6 +222,9 @@ Plan make_fftd_plan(const char *name)
     Plan p = make_split_plan<8, 2, 128, true>(name, 1.0);
     p.kfn[0] = nullptr;
     p.fft_d = true; // lag_kfn_lin kept: the Eq. (12c) surface in FP32 the same way
+    // the sign codes in the packed layout the FFT kernel reads (half the bytes)
+    p.lag_kfn = reinterpret_cast<const void *>(&lsum_kernel<false, true>);
+    p.lag_kfn_lin = reinterpret_cast<const void *>(&lsum_kernel<true, true>);
     p.cost_scale = 0.05; // far below the FP32 contraction wherever it is eligible
     return p;
 }
@@ -329,6 +332,7 @@ struct Launch {
     long long kchunkT; // sign-split: samples per lsum_kernel chunk
     long long k_codes; // sign-split: samples covered by the sign codes (n rounded up)
     size_t code_off;   // sign-split: offset of the sign codes in the workspace
+    size_t code_bytes; // sign-split: their bytes (the packed layout for fft_d plans)
     size_t part_bytes; // split-K partials
     size_t ws_bytes;   // partials + signed copies of the inputs (+ twiddle planes)
     long long plane_stages; // planes: stage blocks per base tile
@@ -570,10 +574,12 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     if (L.plan->lag_kfn) {
         L.grp_stride = (int)(cdiv((int64_t)L.tiles_b * L.ksplit, 8) * 8);
         L.code_off = L.ws_bytes;
-        L.ws_bytes += align256((size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
+        // one byte per delay and sample in the matrix kernels' layout, half a byte packed
+        L.code_bytes = (size_t)L.k_codes * L.n_cols_pad / (L.plan->fft_d ? 2 : 1);
+        L.ws_bytes += align256(L.code_bytes);
     }
     if (L.plan->fft_d) {
-        L.dft = plan_dft12b(n, n_cols, n_bins, (size_t)(L.k_codes / 32) * L.n_cols_pad * 32);
+        L.dft = plan_dft12b(n, n_cols, n_bins, L.code_bytes);
         L.dft_off = L.ws_bytes;
         L.ws_bytes += L.dft.ws_bytes;
     }
@@ -791,6 +797,7 @@ ndft_status launch_split(const Launch &L, const float2 *surv, const float2 *ref,
         T.kchunk = L.kchunkT;
         T.k_end = L.k_codes;
         T.codes = codes;
+        T.code_wpc = L.k_codes / 8;
         T.part = partial + (size_t)L.ksplit * L.n_cols_pad * L.n_bases_pad;
         void *targs[] = {&T};
         dim3 tgrid((unsigned)cdiv(n_cols, kLsumDelays), (unsigned)L.ksT, (unsigned)lsum_groups(L));
@@ -904,11 +911,11 @@ hipError_t g_dft_attr_err = hipSuccess;
 // exact signs (DFT_SIGNS / DFT_LIN_SIGNS: the twiddle half of the Eq. (12a) / Eq. (12c)
 // sign-split forms, bin 0 left out), written to A or, with accumulate, added to it. ws
 // holds the partial surfaces.
-// The fast kernel on a sign half reads the sign codes at `codes` (code_cols columns,
-// code_bytes in all) that the twiddle-sign kernel wrote earlier on the same stream.
+// The fast kernel on a sign half reads the packed sign codes at `codes` (code_wpc words per
+// delay row, code_bytes in all) that the twiddle-sign kernel wrote earlier on the stream.
 ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *ref, int64_t n, int64_t tau0,
                        int64_t n_tau, int64_t p0, int64_t n_dop, float2 *A, void *ws, int src, bool accumulate,
-                       hipStream_t s, const uint32_t *codes = nullptr, int code_cols = 0, size_t code_bytes = 0,
+                       hipStream_t s, const uint32_t *codes = nullptr, int64_t code_wpc = 0, size_t code_bytes = 0,
                        const TsumParams *tsum = nullptr)
 {
     std::call_once(g_dft_attr_once, [] {
@@ -956,9 +963,11 @@ ndft_status launch_dft(const Dft12bLaunch &L, const float2 *surv, const float2 *
             P.r4 = r4;
         } else {
             // a sign half: the codes of the call's twiddle-sign kernel
-            if (!L.codes || !codes || code_cols < n_tau || code_bytes >= (size_t(1) << 31)) return NDFT_E_INVAL;
+            if (!L.codes || !codes || code_bytes >= (size_t(1) << 31) || code_wpc * 8 < n ||
+                (size_t)(code_wpc * 4) * (size_t)n_tau > code_bytes)
+                return NDFT_E_INVAL;
             P.codes = codes;
-            P.code_cols = code_cols;
+            P.code_wpc = (int)code_wpc;
             P.code_bytes = (unsigned)code_bytes;
             if (tsum) T = *tsum; // the other half's planes, added here instead of by a reduction
         }
@@ -1243,7 +1252,6 @@ ndft_status launch_fft_half(const Launch &L, const ndft_c64 *surv, const ndft_c6
 {
     const float4 *part = reinterpret_cast<const float4 *>(ws);
     const uint32_t *codes = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off);
-    const size_t code_bytes = (size_t)(L.k_codes / 32) * L.n_cols_pad * 32;
     TsumParams T;
     std::memset(&T, 0, sizeof(T));
     if (L.dft.fast) {
@@ -1258,7 +1266,7 @@ ndft_status launch_fft_half(const Launch &L, const ndft_c64 *surv, const ndft_c6
     }
     return launch_dft(L.dft, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, tau0,
                       n_tau, p0, n_dop, reinterpret_cast<float2 *>(A), static_cast<char *>(ws) + L.dft_off, src, true,
-                      s, codes, L.n_cols_pad, code_bytes, L.dft.fast ? &T : nullptr);
+                      s, codes, L.k_codes / 8, L.code_bytes, L.dft.fast ? &T : nullptr);
 }
 
 size_t ndft_caf_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop, ndft_prec prec)
@@ -1500,7 +1508,7 @@ ndft_status ndft_dbg_split(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
         const uint32_t *codes = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.code_off);
         const long long total = (long long)n_tau * n;
         hipLaunchKernelGGL(dbg_decode_codes_kernel, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, codes,
-                           L.n_cols_pad, (int)n, total, lag_sign);
+                           L.n_cols_pad, (int)n, total, lag_sign, L.plan->fft_d ? 1 : 0, L.k_codes / 8);
         if ((st = check_launch()) != NDFT_OK) return st;
     }
     if (!T) return NDFT_OK;

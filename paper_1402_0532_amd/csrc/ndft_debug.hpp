@@ -42,17 +42,21 @@ __global__ __launch_bounds__(256) void dbg_signs_kernel(const float2 *s, const f
 // bits 15:14, 31:30, 13:12, 29:28 for e = 0..3 and its imaginary-part field four bits
 // lower. A field decodes to 0 (00), +1 (01) or -1 (11); the unused pattern 10 is passed
 // on as 2 so that a test sees it.
+// packed != 0: the packed layout (wpc words per delay row; the fields of samples 0..3 of a
+// word 8 bits lower).
 __global__ __launch_bounds__(256) void dbg_decode_codes_kernel(const uint32_t *codes, int n_cols_pad, int n,
-                                                               long long total, int8_t *lag)
+                                                               long long total, int8_t *lag, int packed,
+                                                               long long wpc)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     const long long l = idx / n;
     const long long k = idx % n;
-    const long long word = (((k >> 5) * n_cols_pad + l) * 2 + ((k >> 2) & 1)) * 4 + ((k >> 3) & 3);
+    const long long word = packed ? l * wpc + (k >> 3)
+                                  : (((k >> 5) * n_cols_pad + l) * 2 + ((k >> 2) & 1)) * 4 + ((k >> 3) & 3);
     const uint32_t c = codes[word];
     const int e = (int)(k & 3);
-    const int pos = (e & 1) ? 30 - 2 * (e >> 1) : 14 - 2 * (e >> 1);
+    const int pos = ((e & 1) ? 30 - 2 * (e >> 1) : 14 - 2 * (e >> 1)) - (packed && !(k & 4) ? 8 : 0);
     const uint32_t fr = (c >> pos) & 3u, fi = (c >> (pos - 4)) & 3u;
     auto dec = [](uint32_t f) -> int8_t { return f == 0u ? 0 : (f == 1u ? 1 : (f == 3u ? -1 : 2)); };
     lag[2 * idx] = dec(fr);

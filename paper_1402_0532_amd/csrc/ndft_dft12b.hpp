@@ -45,10 +45,10 @@ struct Dft12bParams {
     // the whole-row kernel (L = 512): the inputs with their exact signs, (re, im, sign re,
     // sign im): s4[n] and r4[2 n] (n zeros, then the reference, so r[m < 0] reads 0)
     const float4 *s4, *r4;
-    // DFT_CODES: the sign codes, [32-sample stage][code_cols][8] words (see ndft_signsplit.hpp),
-    // column l for delay row l; code_bytes of them (< 2^31)
+    // DFT_CODES: the sign codes in the packed layout (see ndft_signsplit.hpp), code_wpc
+    // words per delay row, row l for delay row l; code_bytes of them (< 2^31)
     const uint32_t *codes;
-    int code_cols;
+    int code_wpc;
     unsigned code_bytes;
     int n, tau0, n_tau;
     int p0n, n_dop;       // first bin (reduced mod n) and bin count

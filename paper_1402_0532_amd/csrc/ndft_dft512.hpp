@@ -9,7 +9,8 @@
 // registers, so no partial surfaces are written. DFT_LAG reads the inputs with their exact
 // signs (a sign-prep pass: s4[n], and r4[2 n] with n zeros in front, so a delayed reference
 // needs no bounds test); DFT_CODES reads the 2-bit sign codes the twiddle-sign kernel wrote
-// for the same call (4 bits a sample instead of 32 bytes, and no lag arithmetic). Both go
+// for the same call in the packed layout (half a byte a sample instead of 32 bytes, a delay
+// row contiguous, and no lag arithmetic). Both go
 // through buffer loads whose scalar offset carries the stride of the samples a lane takes.
 // The phases go in groups of 16; each 512-point transform is done as 32 x 16 (t = 16 a + b,
 // k = c + 32 e):
@@ -199,11 +200,13 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
     const long long tplane = (long long)T.cols_pad * T.bases_pad;
     const bool tsum = SRC == DFT_CODES && T.part != nullptr;
 
-    // Rows in an XCD-aware order: work-groups are dealt to the 8 XCDs in turn, so with a
-    // grid that is a multiple of 8 the work-groups of one XCD take consecutive rows (a
-    // 128-byte line of sign codes holds 4 neighbouring delays: read into one L2, not four).
+    // DFT_LAG: rows in an XCD-aware order (work-groups are dealt to the 8 XCDs in turn; with
+    // a grid that is a multiple of 8 the work-groups of one XCD take consecutive delays,
+    // whose reference windows nearly coincide: measured 2% faster). DFT_CODES: rows in grid
+    // order (each row's packed codes are contiguous; the XCD order measured 2% slower).
     const int G = (int)gridDim.x;
-    const int v = (G & 7) == 0 ? (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+    const int v = SRC == DFT_LAG && (G & 7) == 0 ? (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3)
+                                                 : (int)blockIdx.x;
     for (int l = v; l < P.n_tau; l += G) {
         const int d = P.tau0 + l;
         float2 acc[4];
@@ -233,33 +236,18 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
 #pragma unroll
                 for (int a = 0; a < 32; ++a) x[a] = make_float2(0.0f, 0.0f);
             } else if constexpr (SRC == DFT_CODES) {
-                // sample idx = base + 16 M a: its word ((idx / 32) code_cols + l) 8 + 4 h + q
-                // (h = bit 2, q = bits 4:3 of idx), real sign at bit pr of the word, imaginary
-                // at pr - 4 (pr = 14, 30, 12, 28 for idx mod 4 = 0 .. 3)
+                // sample idx = base + 16 M a is field idx mod 8 of packed word idx / 8 of row
+                // l: the field stays put for all a (16 M a is a multiple of 8) and the word
+                // steps by 2 M, which goes in the scalar offset
                 const int base = m0 + j + M * hb;
-                if ((M & 31) == 0) {
-                    // 16 M a is a whole number of stages: word position and field stay put,
-                    // the stage step goes in the scalar offset
-                    const unsigned vo =
-                        (((unsigned)(base >> 5) * (unsigned)P.code_cols + (unsigned)l) * 8u +
-                         (unsigned)(((base >> 2) & 1) * 4 + ((base >> 3) & 3))) * 4u;
-                    const unsigned step = (unsigned)(M >> 1) * (unsigned)P.code_cols * 32u;
-                    const int pr = ((base & 1) ? 30 : 14) - 2 * ((base >> 1) & 1);
+                const unsigned vo = ((unsigned)l * (unsigned)P.code_wpc + (unsigned)(base >> 3)) * 4u;
+                const unsigned step = 8u * (unsigned)M;
+                const int e = base & 7;
+                const int pr = ((e & 1) ? 30 : 14) - 2 * ((e >> 1) & 1) - ((e & 4) ? 0 : 8);
 #pragma unroll
-                    for (int a = 0; a < 32; ++a) {
-                        const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(crs, vo, step * (unsigned)a, 0);
-                        x[a] = code_pair(w, pr);
-                    }
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 32; ++a) {
-                        const int idx = base + 16 * M * a;
-                        const unsigned vo =
-                            (((unsigned)(idx >> 5) * (unsigned)P.code_cols + (unsigned)l) * 8u +
-                             (unsigned)(((idx >> 2) & 1) * 4 + ((idx >> 3) & 3))) * 4u;
-                        const int pr = ((idx & 1) ? 30 : 14) - 2 * ((idx >> 1) & 1);
-                        x[a] = code_pair(__builtin_amdgcn_raw_buffer_load_b32(crs, vo, 0, 0), pr);
-                    }
+                for (int a = 0; a < 32; ++a) {
+                    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(crs, vo, step * (unsigned)a, 0);
+                    x[a] = code_pair(w, pr);
                 }
             } else {
                 // sample idx = m0 + j + M (16 a + hb): one vector offset per lane, the step

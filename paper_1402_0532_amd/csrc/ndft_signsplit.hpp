@@ -41,6 +41,13 @@ namespace ndft {
 // Layout: [32-sample stage][delay column (padded)][half h][step q] words, where the word
 // (h, q) covers samples stage*32 + 8q + 4h + 0..3 (the samples lane half h of a matrix
 // step q consumes).
+// Packed layout (the FP32 plan, whose FFT kernel reads the codes of one delay row at a
+// time): [delay column (padded)][k / 8] words, one per delay and 8 consecutive samples: the
+// used bytes of the two 4-sample words side by side (byte 1 of the word of samples 0..3,
+// byte 1 of that of 4..7, byte 3 of the first, byte 3 of the second), so sample e's real
+// field sits at bit 14, 30, 12, 28 (e mod 4 = 0 .. 3) less 8 for e < 4, its imaginary one
+// 4 bits lower: half the bytes, and a delay row is contiguous.
+constexpr unsigned kPackSel = 0x07030501u; // v_perm selector (w1, w0): w0.b1, w1.b1, w0.b3, w1.b3
 __device__ __forceinline__ uint32_t sign_field(float s)
 {
     return s == 0.0f ? 0u : (s < 0.0f ? 3u : 1u);
@@ -120,6 +127,7 @@ struct LsumParams {
     long long kchunk;         // samples per block (multiple of the chunk), k range of blockIdx.y
     long long k_end;          // samples covered by the codes (n rounded up to the chunk)
     uint32_t *codes;          // sign codes, see above
+    long long code_wpc;       // packed layout: words per delay column (k_end / 8)
     float4 *part;             // this kernel's partial planes: [blockIdx.y][n_cols_pad][n_bases_pad]
 };
 
@@ -179,7 +187,8 @@ __device__ __forceinline__ uint32_t sign_pair(float hi, float lo)
 // prefix sum grows (DC-heavy rows), instead of a few ulp of the block's prefix sum.
 //
 // LIN: the lag product of the Eq. (12c) surface (linear_lag64) instead of Eq. (6).
-template <bool LIN>
+// PACK: the codes in the packed layout.
+template <bool LIN, bool PACK>
 __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
 {
     constexpr int DT = kLsumDelays, C = kLsumChunk;
@@ -368,7 +377,15 @@ __global__ __launch_bounds__(256, 2) void lsum_kernel(LsumParams L)
             }
         }
         nfield += SPT;
-        {
+        if constexpr (PACK) {
+            // the thread's 8 samples are one packed word per delay
+            const long long wi = (k0 + o0) >> 3;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (col0 + h < L.n_cols_pad)
+                    L.codes[(long long)(col0 + h) * L.code_wpc + wi] =
+                        __builtin_amdgcn_perm(code[h][1], code[h][0], kPackSel);
+        } else {
             // the thread's 8 samples are one step q of a 32-sample stage: word (w, q) holds
             // samples 8 q + 4 w .. + 3
             const long long k = k0 + o0;

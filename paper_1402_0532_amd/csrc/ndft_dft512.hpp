@@ -155,6 +155,27 @@ __device__ __forceinline__ float2 code_pair(unsigned w, int pr)
     return make_float2((float)re, (float)im);
 }
 
+// Inner phase sums of a whole group (kD5Group phases) for a thread's first NU bins,
+// sum_j (W^p)^j Y_j[p mod 512] by Horner's rule from the last phase down: the NU chains side
+// by side and unrolled, so the reads are issued ahead of the multiply-adds. A bin of the
+// last NU past the window runs on a valid column and is dropped by the caller.
+template <int NU>
+__device__ __forceinline__ void group_horner(const float2 *X, const int (&bp)[4], const float2 (&bstep)[4],
+                                             float2 (&hs)[4])
+{
+#pragma unroll
+    for (int u = 0; u < NU; ++u) hs[u] = X[(kD5Group - 1) * kD5YS + (bp[u] & 511)];
+#pragma unroll
+    for (int jj = kD5Group - 2; jj >= 0; --jj) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const float2 yv = X[jj * kD5YS + (bp[u] & 511)], w = bstep[u];
+            hs[u] = make_float2(fmaf(hs[u].x, w.x, fmaf(-hs[u].y, w.y, yv.x)),
+                                fmaf(hs[u].x, w.y, fmaf(hs[u].y, w.x, yv.y)));
+        }
+    }
+}
+
 // Grid: x strides over the delays. Dynamic LDS: the two-level table of W_N.
 template <int SRC>
 __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, TsumParams T)
@@ -181,7 +202,7 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
     const __amdgpu_buffer_rsrc_t crs =
         __builtin_amdgcn_make_buffer_rsrc((void *)P.codes, (short)0, (int)P.code_bytes, 0x00020000);
     // this thread's bins: q = tid + 256 u
-    int bq[4], bp[4];
+    int bq[4], bp[4], bjump[4];
     float2 bstep[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -191,9 +212,12 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
         p = p >= n ? p - n : p;
         bp[u] = p;
         bstep[u] = table_twiddle(coarse, fine, p, P.tb);
+        bjump[u] = (int)(((long long)kD5Group * p) % n); // the group factor's step: W^{16 p}
     }
     // twiddle-sign planes: the row of each bin's base (bin p: base min(p, n - p)), and the
     // planes' stride
+    // bins in use per thread (the same for the whole work-group)
+    const int nu = min(4, (P.n_dop + kD5Threads - 1) / kD5Threads);
     int trow[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) trow[u] = row_of_base(T.bm, bp[u] <= (n >> 1) ? bp[u] : n - bp[u]);
@@ -231,15 +255,15 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
                     if (bq[u] >= 0) tv[u] = trow_l[tg * tplane + trow[u]];
             }
             // ---- pass 1: the 32 samples a of transform j, residue hb; 32-point DFT; W_512^{b c} ----
+            // lanes past the group's last phase (a short last group) repeat that phase's
+            // loads: their transforms are never read
+            const int jl = min(j, mb - 1);
             float2 x[32];
-            if (j >= mb) {
-#pragma unroll
-                for (int a = 0; a < 32; ++a) x[a] = make_float2(0.0f, 0.0f);
-            } else if constexpr (SRC == DFT_CODES) {
+            if constexpr (SRC == DFT_CODES) {
                 // sample idx = base + 16 M a is field idx mod 8 of packed word idx / 8 of row
                 // l: the field stays put for all a (16 M a is a multiple of 8) and the word
                 // steps by 2 M, which goes in the scalar offset
-                const int base = m0 + j + M * hb;
+                const int base = m0 + jl + M * hb;
                 const unsigned vo = ((unsigned)l * (unsigned)P.code_wpc + (unsigned)(base >> 3)) * 4u;
                 const unsigned step = 8u * (unsigned)M;
                 const int e = base & 7;
@@ -252,8 +276,8 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
             } else {
                 // sample idx = m0 + j + M (16 a + hb): one vector offset per lane, the step
                 // of a (16 M samples) in the scalar offset of each load
-                const unsigned vs = (unsigned)(m0 + j + M * hb) * 16u;
-                const unsigned vr = (unsigned)(n + m0 + j + M * hb - d) * 16u;
+                const unsigned vs = (unsigned)(m0 + jl + M * hb) * 16u;
+                const unsigned vr = (unsigned)(n + m0 + jl + M * hb - d) * 16u;
                 const unsigned step = 256u * (unsigned)M;
 #pragma unroll
                 for (int a = 0; a < 32; ++a) {
@@ -287,19 +311,37 @@ __global__ __launch_bounds__(kD5Threads, 2) void dft512_kernel(Dft12bParams P, T
             __syncthreads();
             // ---- bins: sum_j W^{(m0 + j) p} Y_j[p mod 512] = W^{m0 p} sum_j (W^p)^j Y_j, the
             // inner sum by Horner's rule from the group's last phase down ----
+            float2 hs[4] = {};
+            if (mb == kD5Group) {
+                if (nu == 1)
+                    group_horner<1>(X, bp, bstep, hs);
+                else if (nu == 2)
+                    group_horner<2>(X, bp, bstep, hs);
+                else if (nu == 3)
+                    group_horner<3>(X, bp, bstep, hs);
+                else
+                    group_horner<4>(X, bp, bstep, hs);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u >= nu) break;
+                    const int k = bp[u] & 511;
+                    const float2 w = bstep[u];
+                    float2 h = X[(mb - 1) * kD5YS + k];
+                    for (int jj = mb - 2; jj >= 0; --jj) {
+                        const float2 yv = X[jj * kD5YS + k];
+                        h = make_float2(fmaf(h.x, w.x, fmaf(-h.y, w.y, yv.x)), fmaf(h.x, w.y, fmaf(h.y, w.x, yv.y)));
+                    }
+                    hs[u] = h;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (bq[u] < 0) continue;
-                const int k = bp[u] & 511;
-                const float2 w = bstep[u];
-                float2 h = X[(mb - 1) * kD5YS + k];
-                for (int jj = mb - 2; jj >= 0; --jj) {
-                    const float2 yv = X[jj * kD5YS + k];
-                    h = make_float2(fmaf(h.x, w.x, fmaf(-h.y, w.y, yv.x)), fmaf(h.x, w.y, fmaf(h.y, w.x, yv.y)));
-                }
-                const float2 g = table_twiddle(coarse, fine, bv[u], P.tb);
+                if (u >= nu) break;
+                const float2 g = table_twiddle(coarse, fine, bv[u], P.tb), h = hs[u];
                 acc[u] = make_float2(fmaf(g.x, h.x, fmaf(-g.y, h.y, acc[u].x)), fmaf(g.x, h.y, fmaf(g.y, h.x, acc[u].y)));
-                bv[u] = (int)(((long long)bv[u] + (long long)kD5Group * bp[u]) % n);
+                bv[u] += bjump[u]; // both below n
+                bv[u] = bv[u] >= n ? bv[u] - n : bv[u];
             }
             if (tload) {
 #pragma unroll

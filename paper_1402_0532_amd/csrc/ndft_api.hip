@@ -1432,8 +1432,10 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
     float2 *buf = need ? static_cast<float2 *>(ws) : nullptr;
     float2 *tw = need ? reinterpret_cast<float2 *>(static_cast<char *>(ws) + align256((size_t)batch * n * sizeof(float2)))
                       : nullptr;
-    // the last top level writes X: the LDS stage writes X after an even number of levels
-    float2 *first = (lev % 2 == 0) ? Xo : buf;
+    // the top levels go two per pass over global memory (one more for an odd count); the
+    // last pass writes X: the LDS stage writes X after an even number of passes
+    const int passes = (lev + 1) / 2;
+    float2 *first = (passes % 2 == 0) ? Xo : buf;
     const int rpb = kNfftMaxN / L;
     // padded rows (one entry per 8 more), then the per-level twiddle table (L - 1 entries)
     const size_t shmem = ((size_t)rpb * L + (size_t)rpb * L / 8 + L) * sizeof(float2);
@@ -1452,15 +1454,27 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
     if (lev > 0) {
         hipLaunchKernelGGL(nfft_table_kernel, dim3((unsigned)cdiv(n / 2, 256)), dim3(256), 0, s, tw, (int)n);
         const unsigned cgrid = (unsigned)std::min<int64_t>(cdiv(batch * (n / 2), 256), 8LL * device_cu_count());
+        const unsigned cgrid2 = (unsigned)std::min<int64_t>(cdiv(batch * (n / 4), 256), 8LL * device_cu_count());
         float2 *src = first;
-        for (int S = sub / 2; S >= 1; S /= 2) {
+        for (int S = sub / 2; S >= 1;) { // the level of stride S, inputs at stride 2 S
             float2 *dst = src == Xo ? buf : Xo;
-            if (outer)
-                hipLaunchKernelGGL(nfft_combine_kernel<true>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
-                                   (long long)batch, (int)n, S);
-            else
-                hipLaunchKernelGGL(nfft_combine_kernel<false>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
-                                   (long long)batch, (int)n, S);
+            if (S >= 2) { // levels S and S / 2 in one pass
+                if (outer)
+                    hipLaunchKernelGGL(nfft_combine2_kernel<true>, dim3(cgrid2), dim3(256), 0, s, src, dst, tw,
+                                       (long long)batch, (int)n, S / 2);
+                else
+                    hipLaunchKernelGGL(nfft_combine2_kernel<false>, dim3(cgrid2), dim3(256), 0, s, src, dst, tw,
+                                       (long long)batch, (int)n, S / 2);
+                S /= 4;
+            } else {
+                if (outer)
+                    hipLaunchKernelGGL(nfft_combine_kernel<true>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
+                                       (long long)batch, (int)n, S);
+                else
+                    hipLaunchKernelGGL(nfft_combine_kernel<false>, dim3(cgrid), dim3(256), 0, s, src, dst, tw,
+                                       (long long)batch, (int)n, S);
+                S /= 2;
+            }
             src = dst;
         }
     }

@@ -32,12 +32,13 @@ constexpr int kNfftMaxLong = 1 << 24;      // longest row
 constexpr int kNfftThreads = 1024;
 
 // Eq. (1) with the sign table of Eq. (2), FP32: one rounding
+// (|a| + |b| with the sign of a b, 0 when an operand is zero of either sign: the sign bit of
+// the non-zero sum is the exclusive or of the operands' sign bits)
 __device__ __forceinline__ float rop32(float a, float b)
 {
     const float m = fabsf(a) + fabsf(b);
-    const bool pos = (a > 0.0f && b > 0.0f) || (a < 0.0f && b < 0.0f);
-    const bool neg = (a > 0.0f && b < 0.0f) || (a < 0.0f && b > 0.0f);
-    return pos ? m : (neg ? -m : 0.0f);
+    const unsigned sg = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
+    return (a == 0.0f || b == 0.0f) ? 0.0f : __uint_as_float(__float_as_uint(m) | sg);
 }
 
 // Eq. (6): o (x) w
@@ -150,29 +151,54 @@ __device__ __forceinline__ void nfft_group_pass(float2 *buf, int rows, int n, in
 }
 
 // Dynamic LDS: rpb rows of n entries (padded: 9/8 of that), then the n - 1 entries of the
-// per-level twiddle table. Row groups g = blockIdx.x,
-// + gridDim.x, ... of rpb = 8192 / n rows each (n a power of two). Row r (of `rows`) is
-// read from x + (r / sub) * in_row + (r % sub) with element stride `sub` (sub = 1: plain
-// rows; sub = 2^s: the decimated sequences of a long row of in_row = n sub samples) and
-// written contiguously to X + r n.
+// per-level twiddle table. Row groups g = blockIdx.x, + gridDim.x, ... of rpb = 8192 / n rows
+// each (n a power of two, rpb n = 8192: eight entries a thread). Row r (of `rows`) is read
+// from x + (r / sub) * in_row + (r % sub) with element stride `sub` (sub = 1: plain rows;
+// sub = 2^s: the decimated sequences of a long row of in_row = n sub samples) and written
+// contiguously to X + r n. The next row group's entries are loaded into registers while the
+// current one is transformed.
 template <bool OUTER>
 __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__restrict__ x, float2 *__restrict__ X,
                                                            long long rows_total, int n, int rpb, int sub,
                                                            long long in_row)
 {
+    constexpr int EPT = kNfftMaxN / kNfftThreads; // entries a thread loads and stores
     extern __shared__ float2 nfft_lds[];
     float2 *buf = nfft_lds, *tw = nfft_lds + nfft_pad(rpb * n);
     const int tid = threadIdx.x;
-    const int lg = 31 - __builtin_clz(n); // log2 n
+    const int lg = 31 - __builtin_clz(n);   // log2 n
+    const int ls = 31 - __builtin_clz(sub); // log2 sub
+    const long long gstep = (long long)gridDim.x * rpb;
+    // entry i = tid + c 1024 of a row group: row i >> lg, column i mod n; with sub = 1 the
+    // group's rows are contiguous (entry i at i), with sub > 1 a group is one row (rpb = 1,
+    // entry i at i sub): either way i << ls from the group's first entry
+    auto load_group = [&](long long b0, float2(&v)[EPT]) {
+        const long long rows = min((long long)rpb, rows_total - b0);
+        // the group's first entry and each c's part of the offset are uniform; the thread's
+        // part, tid sub 8 bytes, is below 2^24
+        const char *src = reinterpret_cast<const char *>(x + (b0 >> ls) * in_row + (b0 & (sub - 1)));
+        const unsigned voff = (unsigned)tid << (ls + 3);
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int i = tid + c * kNfftThreads;
+            const char *srcc = src + ((size_t)(c * kNfftThreads) << (ls + 3));
+            v[c] = (i >> lg) < rows ? *reinterpret_cast<const float2 *>(srcc + voff) : make_float2(0.0f, 0.0f);
+        }
+    };
+    float2 pv[EPT];
+    long long b0 = (long long)blockIdx.x * rpb;
+    if (b0 < rows_total) load_group(b0, pv); // in flight while the table is built
     nfft_level_table(tw, n, tid);
-    for (long long b0 = (long long)blockIdx.x * rpb; b0 < rows_total; b0 += (long long)gridDim.x * rpb) {
+    for (; b0 < rows_total; b0 += gstep) {
         const int rows = (int)min((long long)rpb, rows_total - b0);
-        for (int i = tid; i < rows * n; i += kNfftThreads) {
-            const long long r = b0 + i / n;
-            const float2 v = x[(r / sub) * in_row + (r % sub) + (long long)sub * (i % n)];
-            buf[nfft_pad(i)] = OUTER ? cop32(v, make_float2(1.0f, 0.0f)) : v; // the length-1 transforms
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int i = tid + c * kNfftThreads;
+            if ((i >> lg) < rows)
+                buf[nfft_pad(i)] = OUTER ? cop32(pv[c], make_float2(1.0f, 0.0f)) : pv[c]; // the length-1 transforms
         }
         __syncthreads(); // also orders the table before its first use
+        if (b0 + gstep < rows_total) load_group(b0 + gstep, pv);
         // log2 n radix-2 levels, up to three of them per LDS round trip
         for (int p = 1; p < n;) {
             const int left = lg - (31 - __builtin_clz(p)); // levels still to do
@@ -188,8 +214,15 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
             }
         }
         float2 *Xr = X + b0 * n;
-        for (int i = tid; i < rows * n; i += kNfftThreads) Xr[i] = buf[nfft_pad(i)];
-        __syncthreads(); // buf is refilled for the next row
+        float2 ov[EPT];
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) ov[c] = buf[nfft_pad(tid + c * kNfftThreads)];
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int i = tid + c * kNfftThreads;
+            if ((i >> lg) < rows) Xr[i] = ov[c];
+        }
+        __syncthreads(); // buf is refilled for the next row group
     }
 }
 
@@ -211,17 +244,59 @@ __global__ __launch_bounds__(256) void nfft_combine_kernel(const float2 *__restr
 {
     const long long half = (long long)n / 2;
     const int h = n / (2 * S);
+    const int lhalf = 30 - __builtin_clz(n), lh = 31 - __builtin_clz(h); // n, S powers of two
     const long long total = batch * half;
     for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < total; w += (long long)gridDim.x * 256) {
-        const long long row = w / half;
-        const int b = (int)(w - row * half); // butterfly of the row: j = b / h, k = b % h
-        const int j = b / h, k = b - (b / h) * h;
+        const long long row = w >> lhalf;
+        const int b = (int)(w & (half - 1)); // butterfly of the row: j = b / h, k = b % h
+        const int j = b >> lh, k = b & (h - 1);
         const float2 *s = src + row * n;
         const float2 e = s[(long long)j * h + k];
         const float2 t = nfft_odd<OUTER>(s[(long long)(j + S) * h + k], tw[(long long)k * S]);
         float2 *d = dst + row * n + (long long)j * 2 * h;
         d[k] = make_float2(e.x + t.x, e.y + t.y);
         d[k + h] = make_float2(e.x - t.x, e.y - t.y);
+    }
+}
+
+// Two top levels of a long row in one pass: strides 2S, then S. The transforms of length h4 =
+// n / (4 S) of x[j::4S] (A), x[j + 2S::4S] (B), x[j + S::4S] (C) and x[j + 3S::4S] (D) give
+// those of x[j::2S] (A, B) and x[j + S::2S] (C, D) at level 2S, and those the transform of
+// x[j::S] at level S: thread (j, k), k < h4, takes both level-2S butterflies at k and the two
+// level-S butterflies at k and k + h4 whose operands they produce. The butterflies and their
+// operations are those of two single-level passes, so the result is the same bit for bit,
+// with half the passes over global memory. src holds 4S sequences of length h4, dst S of
+// length 4 h4.
+template <bool OUTER>
+__global__ __launch_bounds__(256) void nfft_combine2_kernel(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                                            const float2 *__restrict__ tw, long long batch, int n,
+                                                            int S)
+{
+    const long long quarter = (long long)n / 4;
+    const int h4 = n / (4 * S);
+    const int lq = 29 - __builtin_clz(n), lh4 = 31 - __builtin_clz(h4); // n, S powers of two
+    const long long total = batch * quarter;
+    for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < total; w += (long long)gridDim.x * 256) {
+        const long long row = w >> lq;
+        const int b = (int)(w & (quarter - 1));
+        const int j = b >> lh4, k = b & (h4 - 1);
+        const float2 *s = src + row * n;
+        const float2 a = s[(long long)j * h4 + k], bv = s[(long long)(j + 2 * S) * h4 + k];
+        const float2 c = s[(long long)(j + S) * h4 + k], d = s[(long long)(j + 3 * S) * h4 + k];
+        const float2 w1 = tw[(long long)k * 2 * S];          // W_{2 h4}^k
+        const float2 w2a = tw[(long long)k * S];             // W_{4 h4}^k
+        const float2 w2b = tw[(long long)(k + h4) * S];      // W_{4 h4}^{k + h4}
+        // level 2S: x[j::2S] at k and k + h4 (P), x[j + S::2S] likewise (Q)
+        const float2 t1 = nfft_odd<OUTER>(bv, w1), t2 = nfft_odd<OUTER>(d, w1);
+        const float2 pp = make_float2(a.x + t1.x, a.y + t1.y), pm = make_float2(a.x - t1.x, a.y - t1.y);
+        const float2 qp = make_float2(c.x + t2.x, c.y + t2.y), qm = make_float2(c.x - t2.x, c.y - t2.y);
+        // level S: butterflies k and k + h4 of x[j::S]
+        const float2 u = nfft_odd<OUTER>(qp, w2a), v = nfft_odd<OUTER>(qm, w2b);
+        float2 *o = dst + row * n + (long long)j * 4 * h4;
+        o[k] = make_float2(pp.x + u.x, pp.y + u.y);
+        o[k + 2 * h4] = make_float2(pp.x - u.x, pp.y - u.y);
+        o[k + h4] = make_float2(pm.x + v.x, pm.y + v.y);
+        o[k + 3 * h4] = make_float2(pm.x - v.x, pm.y - v.y);
     }
 }
 

@@ -87,7 +87,7 @@ def test_nfft_printed_reading_bit_exact(nd, orc, n, kind):
 
 
 @pytest.mark.parametrize("reading", [0, 1])
-@pytest.mark.parametrize("n,batch", [(1 << 14, 3), (1 << 15, 2), (1 << 17, 2), (1 << 20, 1)])
+@pytest.mark.parametrize("n,batch", [(1 << 14, 3), (1 << 15, 2), (1 << 16, 2), (1 << 17, 2), (1 << 20, 1)])
 def test_nfft_long_rows_bit_exact(nd, orc, reading, n, batch):
     rng = np.random.default_rng(n + reading)
     x = (rng.standard_normal((batch, n)) + 1j * rng.standard_normal((batch, n))).astype(np.complex64)

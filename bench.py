@@ -88,6 +88,25 @@ def fft_flops_per_row(n: int, n_dop: int) -> float:
     return 5.0 * L * math.log2(L) * M + 8.0 * M * n_dop if L > 1 else 8.0 * n * n_dop
 
 
+def fast_flops_per_row(n: int) -> float:
+    """Flops of the fast exact transform of one length-n row (n a power of two, every bin):
+    per correlation length L = 2^l >= 64 its lg - l + 1 pairs of two length-L/4 sequences,
+    each transformed forward and back (5 Q log2 Q flops a complex FFT) and multiplied by the
+    spectra (two complex products and a sum: 14 flops an entry); the direct correlations of
+    lengths 2 .. 32 (8 flops a term); the FFT of the signs (5 n log2 n); the folds and the
+    sums into T (2 flops an entry and level)."""
+    lg = int(round(math.log2(n)))
+    f = 5.0 * n * lg + 2.0 * n * lg * 2
+    for l in range(1, lg + 1):
+        b, half = lg - l + 1, 2 ** (l - 1)
+        if l <= 5:
+            f += 8.0 * b * half * half
+        else:
+            q = half // 2
+            f += 2 * (2 * b) * 5.0 * q * math.log2(q) + 14.0 * b * half
+    return f
+
+
 def tsum_ops(n: int, n_tau: int, p0: int, n_dop: int) -> float:
     """Operations of the twiddle-sign half (lsum_kernel) for one surface: per delay and
     sample the Eq. (6) lag product at the paper's count for one complex operator (4 sign,
@@ -222,8 +241,10 @@ def bench_batched(nd, tune, synth, torch, args):
 def bench_config2(nd, synth, torch, args):
     """The plain-FP32 workload of the radar model at N = 4096: 256 delays x all 4096 Doppler
     bins (1048576 cells). Every base bin up to N / 2 is needed, so the library takes its
-    wide-window kernels; each form's main kernel is event-timed against its dense peak
-    (16 N algorithmic flops per cell; 8 N for a sign-split matrix half)."""
+    wide-window kernels (in FP32 the fast exact transform, N being a power of two); each
+    form's main kernel is event-timed against its dense peak (16 N algorithmic flops per
+    cell; 8 N for a sign-split matrix half), the fast transform against the vector units'
+    FP32 peak with its own flop count."""
     import numpy as np
 
     c = synth.config2()
@@ -244,11 +265,16 @@ def bench_config2(nd, synth, torch, args):
         ms, kern, out = time_caf(nd, torch, s, r, geo, prec, max(5, args.steps), max(3, args.warmup // 10))
         plan, ks = nd.get_plan(prec, c["n"], c["n_tau"], c["p0"], c["n_dop"])
         pname = nd.plan_name(prec, plan)
-        kflops = flops / 2 if pname.startswith(SPLIT_PLAN_PREFIXES) else flops
+        if pname.startswith("fp32x_fast"):
+            # the fast exact transform: its own flops against the vector units' FP32 peak
+            kflops, peak, bound = fast_flops_per_row(c["n"]) * c["n_tau"], VALU_FP32_TFLOPS, "alu"
+        else:
+            kflops = flops / 2 if pname.startswith(SPLIT_PLAN_PREFIXES) else flops
+            peak, bound = PEAK_TFLOPS[form], "mfma"
         tf = kflops / (kern * 1e-3) / 1e12
         res[form] = {"ms_per_surface": ms, "cells_per_s": cells / (ms * 1e-3), "plan": pname, "ksplit": ks,
-                     "main_kernel_ms": kern, "main_kernel_tflops": tf,
-                     "frac_of_peak": tf / PEAK_TFLOPS[form],
+                     "main_kernel_ms": kern, "main_kernel_tflops": tf, "bound": bound,
+                     "frac_of_peak": tf / peak,
                      "algorithmic_tflops_whole_call": flops / (ms * 1e-3) / 1e12}
         if ref is not None:
             g = out.cpu().numpy()[rows].astype(np.complex128)

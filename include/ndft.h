@@ -53,14 +53,22 @@ typedef enum {
 } ndft_status;
 
 /* Arithmetic of the dense contraction (sign operands are exact in every form):
- *   NDFT_FP32   FP32 operands on FP32 matrix cores, FP32 accumulation.
+ *   NDFT_FP32   FP32 operands on FP32 matrix cores, FP32 accumulation. For n a power of
+ *               two from 8 to 4096 and wide bin windows the built-in choice is the fast
+ *               exact transform (plan "fp32x_fast_exact": every bin of a row from FFTs
+ *               and cyclic correlations over the odd residues mod n, the same terms as
+ *               Eq. (7) regrouped, FP32 arithmetic).
  *   NDFT_BF16X2 data split into BF16 hi + lo (|v - hi - lo| <= 2^-18 |v|), exact BF16
  *               signs, FP32 accumulation.
  *   NDFT_FP8    data split into four e4m3 terms (v = t0 + t1/16 + t2/256 + t3/4096 up to
  *               ~2^-16 |v|), exact e4m3 signs, block-scaled FP8 matrix cores, FP32
- *               accumulation. Input components must stay below 64 in magnitude; n is
- *               limited by LDS (NDFT_E_UNSUPPORTED above 2^20 for some plans). The
- *               adjoint has no FP8 form (NDFT_E_UNSUPPORTED).                         */
+ *               accumulation. The data are carried scaled by a power of two taken from
+ *               the inputs' largest |re| + |im| (one extra pass); at or above
+ *               M = max(|s_r|+|s_i|) + max(|r_r|+|r_i|) = 2^29 (the forward NDFT:
+ *               max(|x_r|+|x_i|)) the combined kernel returns NaN outputs, the FP8
+ *               sign-split plans have no input limit. n is limited by LDS
+ *               (NDFT_E_UNSUPPORTED above 2^20 for some plans). The adjoint has no FP8
+ *               form (NDFT_E_UNSUPPORTED).                                            */
 typedef enum { NDFT_FP32 = 0, NDFT_BF16X2 = 1, NDFT_FP8 = 2 } ndft_prec;
 
 /* Maximum transform length. */

@@ -21,6 +21,7 @@
 #include "ndft_debug.hpp"
 #include "ndft_dft12b.hpp"
 #include "ndft_dft512.hpp"
+#include "ndft_fast.hpp"
 #include "ndft_nfft.hpp"
 #include "ndft_signsplit.hpp"
 #include "ndft_surface_bf16.hpp"
@@ -116,6 +117,7 @@ struct Plan {
     const void *lag_kfn_lin; // the same for the Eq. (12c) surface (ordinary lag product)
     int stage_a;             // plane uint4 per stage (plane plans)
     bool fft_d;              // sign-split with the twiddle half as a decimated FFT (no matrix kernel)
+    bool fastx = false;      // the fast exact transform (every bin; N a power of two, ndft_fast.hpp)
 };
 
 template <int PREC, int WAVES_B, int WAVES_L, int WB, int WL, int KS>
@@ -240,6 +242,37 @@ Plan make_split8_plan(const char *name, double rel_cost)
     return p;
 }
 
+// FP32 fast exact transform (ndft_fast.hpp): every bin of a row from FFTs and cyclic
+// correlations over the odd residues, N a power of two in [kFastMinN, kFastMaxN]; no matrix
+// kernel. In the built-in choice its cost is a per-row count independent of the window.
+Plan make_fast_plan(const char *name)
+{
+    Plan p;
+    std::memset(&p, 0, sizeof(p));
+    p.name = name;
+    p.bt = 1;
+    p.lt = 1;
+    p.ks = 1;
+    p.nt = kFastThreads;
+    p.kgran = 1;
+    p.cost_scale = 1.0;
+    p.sign_scale = 1.0f;
+    p.fastx = true;
+    return p;
+}
+
+bool fast_ok(int64_t n) { return n >= kFastMinN && n <= kFastMaxN && (n & (n - 1)) == 0; }
+
+// Built-in cost of the fast transform per row, in the contraction's units (padded cell x
+// cost_scale): ~2 log2(N)^2 cells (its work is O(N log N) a row against O(N) a cell, and
+// its ~log2(N)^2 barrier-separated steps bound it at these lengths).
+double fast_row_cost(int64_t n)
+{
+    int lg = 0;
+    while ((1LL << lg) < n) ++lg;
+    return 2.0 * lg * lg;
+}
+
 const std::vector<Plan> &plans(int prec)
 {
     // name: bases x delays per work-group, waves, samples per stage
@@ -249,6 +282,7 @@ const std::vector<Plan> &plans(int prec)
         make_plan<PREC_FP32, 4, 2, 2, 1, 8>("fp32_b256_l64_w8_ks8"),
         make_plan<PREC_FP32, 3, 4, 1, 1, 8>("fp32_b96_l128_w12_ks8"),
         make_fftd_plan("fp32s_fftd_b64_l256"),
+        make_fast_plan("fp32x_fast_exact"),
     };
     static const std::vector<Plan> fp8 = {
         make_plan<PREC_FP8, 2, 4, 2, 1, 16>("fp8_b128_l128_w8_ks16"),
@@ -300,6 +334,12 @@ hipError_t g_attr_err = hipSuccess;
 
 void set_kernel_attributes()
 {
+    for (const void *fn : {reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_X>),
+                           reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_LAG>)}) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           fast_lds_bytes(kFastMaxN, 2 * 64));
+        if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
+    }
     for (int prec = 0; prec < 3; ++prec)
         for (const Plan &p : plans(prec))
             for (int k = 0; k < 4; ++k) {
@@ -501,6 +541,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     }
     const std::vector<Plan> &ps = plans(prec);
     auto usable = [&](int k) {
+        if (ps[k].fastx) return !lin && fast_ok(n);
         if (lin) return ps[k].lag_kfn_lin != nullptr;
         return ps[k].kfn[prod] != nullptr || (prod == PROD_LAG && ps[k].fft_d);
     };
@@ -520,10 +561,11 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
             if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * runs_c > n) continue;
             // the FFT of the twiddle half wants a power-of-two factor of at least 64 in n
             if (!lin && ps[k].fft_d && n % 64 != 0) continue;
-            const int r0 = zero_row(ps[k], prod, L.bm, L.n_bases);
+            const int r0 = ps[k].fastx ? 0 : zero_row(ps[k], prod, L.bm, L.n_bases);
             double rows = (double)(cdiv(L.n_bases - r0, ps[k].bt) * ps[k].bt);
             double cols = (double)(cdiv(n_cols, ps[k].lt) * ps[k].lt);
-            double cost = rows * (cols + ps[k].row_cost_cols) * ps[k].cost_scale;
+            double cost = ps[k].fastx ? cols * fast_row_cost(n)
+                                      : rows * (cols + ps[k].row_cost_cols) * ps[k].cost_scale;
             if (best < 0 || cost < best * 0.999) {
                 best = cost;
                 pi = k;
@@ -532,6 +574,14 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
     }
     if (pi < 0) return L; // L.plan stays nullptr
     L.plan = &ps[pi];
+    if (L.plan->fastx) {
+        // tables of the call: the group order, its inverse, the correlation spectra
+        choose_table(n, kMaxTableBytes, &L.tb, &L.n_coarse, &L.tw_exact);
+        L.fits = 1;
+        L.ws_bytes = 2 * align256((size_t)(n / 2) * sizeof(int)) +
+                     align256((size_t)std::max(1, fast_spec_entries((int)n)) * sizeof(float2));
+        return L;
+    }
     L.row0 = zero_row(*L.plan, prod, L.bm, L.n_bases);
     L.bm_tile = L.row0 ? drop_first_base(L.bm) : L.bm;
     L.tiles_b = (int)cdiv(L.n_bases - L.row0, L.plan->bt);
@@ -1209,6 +1259,53 @@ const char *ndft_status_string(ndft_status st)
 
 const char *ndft_version(void) { return "ndft-mi355x 0.1 (gfx950)"; }
 
+// The fast exact transform: the call's tables (group order, its inverse, the correlation
+// spectra), then one work-group per row at a time, every bin of the row in LDS and the
+// requested ones written out.
+ndft_status launch_fast(const Launch &L, int mode, const float2 *x, const float2 *surv, const float2 *ref,
+                        int64_t n, int64_t rows, int64_t tau0, int64_t p0, int64_t n_bins, float2 *out, void *ws,
+                        hipStream_t s)
+{
+    std::call_once(g_attr_once, set_kernel_attributes);
+    if (g_attr_err != hipSuccess) return NDFT_E_HIP;
+    int lg = 0;
+    while ((1LL << lg) < n) ++lg;
+    int *gtab = static_cast<int *>(ws);
+    int *dlog = reinterpret_cast<int *>(static_cast<char *>(ws) + align256((size_t)(n / 2) * sizeof(int)));
+    float2 *spec = reinterpret_cast<float2 *>(static_cast<char *>(ws) + 2 * align256((size_t)(n / 2) * sizeof(int)));
+    const int nspec = lg >= 6 ? 2 * (lg - 5) : 0;
+    hipLaunchKernelGGL(fast_tables_kernel, dim3((unsigned)(nspec + 1)), dim3(256), 0, s, (int)n, lg, gtab, dlog, spec);
+    ndft_status st = check_launch();
+    if (st != NDFT_OK) return st;
+    FastParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.n = (int)n;
+    P.lg = lg;
+    P.rows = (int)rows;
+    P.x = x;
+    P.s = surv;
+    P.r = ref;
+    P.tau0 = (int)tau0;
+    P.gtab = gtab;
+    P.dlog = dlog;
+    P.spec = spec;
+    P.tb = L.tb;
+    P.n_coarse = L.n_coarse;
+    P.p0n = (int)mod_n(p0, n);
+    P.n_dop = (int)n_bins;
+    P.out = out;
+    const int lds = fast_lds_bytes((int)n, L.n_coarse + (1 << L.tb));
+    const int64_t per_cu = std::max(1, (160 * 1024) / lds);
+    const unsigned grid = (unsigned)std::min<int64_t>(rows, per_cu * device_cu_count());
+    ProfScope prof(s);
+    if (mode == FAST_X)
+        hipLaunchKernelGGL(fast_ndft_kernel<FAST_X>, dim3(grid), dim3(kFastThreads), (size_t)lds, s, P);
+    else
+        hipLaunchKernelGGL(fast_ndft_kernel<FAST_LAG>, dim3(grid), dim3(kFastThreads), (size_t)lds, s, P);
+    prof.stop();
+    return check_launch();
+}
+
 size_t ndft_forward_workspace(int64_t batch, int64_t n, int64_t k0, int64_t k_count, ndft_prec prec)
 {
     if (!prec_ok(prec) || n < 1 || n > NDFT_MAX_N || batch < 1 || k_count < 1 || k_count > n) return 0;
@@ -1230,6 +1327,9 @@ ndft_status ndft_forward(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t 
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (L.plan->fastx)
+        return launch_fast(L, FAST_X, reinterpret_cast<const float2 *>(x), nullptr, nullptr, n, batch, 0, k0, k_count,
+                           reinterpret_cast<float2 *>(X), ws, s);
     float4 *part = reinterpret_cast<float4 *>(ws);
     float4 *x4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
     st = launch_prep(reinterpret_cast<const float2 *>(x), x4, n, batch, n + kTailPad, 0, L.plan->sign_scale, s);
@@ -1288,6 +1388,10 @@ ndft_status ndft_caf(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (L.plan->fastx)
+        return launch_fast(L, FAST_LAG, nullptr, reinterpret_cast<const float2 *>(surv),
+                           reinterpret_cast<const float2 *>(ref), n, n_tau, tau0, p0, n_dop,
+                           reinterpret_cast<float2 *>(A), ws, s);
     float4 *part = reinterpret_cast<float4 *>(ws);
     float4 *s4 = reinterpret_cast<float4 *>(static_cast<char *>(ws) + L.part_bytes);
     float4 *r4 = s4 + n + kTailPad; // n zeros, then the reference, then a zero tail

@@ -200,7 +200,9 @@ def test_fp32_plan_choice_rules():
 
     assert name(65536, 1024, -256, 512).startswith("fp32s_") and ks.value == 0
     assert name(16384, 100, -64, 128).startswith("fp32s_")
-    assert not name(4096, 256, 0, 4096).startswith("fp32s_")   # bases up to N / 2
+    assert name(4096, 256, 0, 4096) == "fp32x_fast_exact"      # bases up to N / 2, N = 2^12
+    assert name(1024, 64, -500, 1000) == "fp32x_fast_exact"
+    assert not name(8192, 256, 0, 8192).startswith("fp32s_")   # beyond the fast transform's rows
     assert not name(65540, 3, -2, 5).startswith("fp32s_")      # N = 4 x odd
     assert not name(1000, 64, -3, 7).startswith("fp32s_")      # N = 8 x 125
 

@@ -427,6 +427,55 @@ def bench_nfft(nd, torch, args):
     return res
 
 
+def bench_forward(nd, torch, args):
+    """The NDFT of Eq. (7) on a batch (1024 rows of N = 4096, every bin) in FP32: the
+    built-in choice (the fast exact transform) against the FP32 contraction forced through
+    the plan table, and both against the oracle on two rows."""
+    import numpy as np
+
+    rows, n = 1024, 4096
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.complex(torch.randn(rows, n, device="cuda", generator=g),
+                      torch.randn(rows, n, device="cuda", generator=g))
+    res = {"workload": "forward_b1024_n4096_all_bins", "outputs": rows * n,
+           "algorithmic_flops": 16.0 * n * rows * n}
+    names = [nd.plan_name(0, k) for k in range(nd.plan_count(0))]
+    pick = [0, rows - 1]
+    ref = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ref = oracle.ndft(x[pick].cpu().numpy().astype(np.complex128))
+    for label, plan in (("fast", -1), ("contraction", names.index("fp32_b96_l128_w12_ks8"))):
+        nd.set_plan(0, plan, 0)
+        try:
+            out = nd.forward(x, prec=0)
+            for _ in range(max(3, args.warmup // 10)):
+                out = nd.forward(x, prec=0)
+            torch.cuda.synchronize()
+            reps = max(5, args.steps) if label == "fast" else 3
+            e0, e1 = _events(torch)
+            e0.record()
+            for _ in range(reps):
+                out = nd.forward(x, prec=0)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            p, _ = nd.get_plan(0, n, rows, 0, n)
+            res[label] = {"ms": ms, "outputs_per_s": rows * n / (ms * 1e-3), "plan": nd.plan_name(0, p)}
+            if ref is not None:
+                got = out[pick].cpu().numpy().astype(np.complex128)
+                Xo, sc = ref
+                err = (np.abs(got.real - Xo.real) + np.abs(got.imag - Xo.imag)) / np.where(sc > 0, sc, 1)
+                res[label]["max_l1_rel_err_vs_oracle"] = float(err.max())
+        finally:
+            nd.set_plan(0, -1, 0)
+    res["fast"]["flops_own"] = fast_flops_per_row(n) * rows
+    res["fast"]["frac_of_fp32_vector_peak"] = res["fast"]["flops_own"] / (res["fast"]["ms"] * 1e-3) / 1e12 / VALU_FP32_TFLOPS
+    res["speedup_fast_vs_contraction"] = res["contraction"]["ms"] / res["fast"]["ms"]
+    return res
+
+
 def bench_robustness(nd, synth, torch, args):
     """Targets and clutter under AWGN and eps-contaminated Gaussian noise (noise-free
     reference): the Eq. (12a) and (12b) surfaces (this library) against the ordinary
@@ -481,9 +530,9 @@ def main():
                     help="force a tile plan and split count for a form (no autotuning for it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip every extra section (same as --extras '')")
-    ap.add_argument("--extras", default="config2,batched,adjoint,surfaces,robustness,nfft",
-                    help="extra sections to run (comma list of config2, batched, adjoint, surfaces, "
-                         "robustness, nfft)")
+    ap.add_argument("--extras", default="config2,forward,batched,adjoint,surfaces,robustness,nfft",
+                    help="extra sections to run (comma list of config2, forward, batched, adjoint, "
+                         "surfaces, robustness, nfft)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -691,6 +740,8 @@ def main():
     want = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
     if "config2" in want:
         extras["config2"] = bench_config2(nd, synth, torch, args)
+    if "forward" in want:
+        extras["forward"] = bench_forward(nd, torch, args)
     if "batched" in want:
         extras["batched"] = bench_batched(nd, tune, synth, torch, args)
     if "adjoint" in want:

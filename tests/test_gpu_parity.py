@@ -267,17 +267,25 @@ def test_invalid_arguments_raise(nd):
         nd.caf(s.real.contiguous(), s, 0, 4, 0, 4)
 
 
-@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft", "nfft_long"])
+@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft", "nfft_long", "fast"])
 def test_fft_paths_graph_replay(nd, which):
     """The FFT-based paths (the FP32 sign-split surfaces of Eq. (12a) and (12c):
     twiddle-sign kernel, reduction, then the FFT of the exact lag signs added on top; the
-    Eq. (12b) surface: FFT kernel and the reduction of its partial surfaces; the NFFT)
-    captured into a graph: every replay, with unrelated eager work and a scrambled
-    workspace between, equals the eager call."""
+    Eq. (12b) surface: FFT kernel and the reduction of its partial surfaces; the NFFT; the
+    fast exact transform: its tables kernel, then the row kernel) captured into a graph:
+    every replay, with unrelated eager work and a scrambled workspace between, equals the
+    eager call."""
     n, tau0, n_tau, p0, n_dop = 16384, 3, 100, -64, 128
+    if which == "fast":
+        n, tau0, n_tau, p0, n_dop = 4096, 3, 300, -2048, 4096
     s, r = synth.random_pair(n, seed=22, zeros=0.02)
     S, R = dev(s), dev(r)
-    if which == "fp32_fft_half":
+    if which == "fast":
+        plan, _ = nd.get_plan(0, n, n_tau, p0, n_dop)
+        assert nd.plan_name(0, plan) == "fp32x_fast_exact"
+        nbytes = nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
+        call = lambda out, ws: nd.caf(S, R, tau0, n_tau, p0, n_dop, prec=0, out=out, ws=ws)
+    elif which == "fp32_fft_half":
         plan, _ = nd.get_plan(0, n, n_tau, p0, n_dop)
         assert nd.plan_name(0, plan).startswith("fp32s_")
         nbytes = nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)

@@ -21,7 +21,7 @@
 // definition, regrouped, so the result is Eq. (7)'s up to FP32 rounding (a few ulp times
 // log2 N of the l1 mass of the terms; the DFTs of phi_L are made in FP64 and rounded once).
 //
-// One 512-thread work-group per row (rows looped over the grid), everything in LDS:
+// One 1024-thread work-group per row (rows looped over the grid), everything in LDS:
 // the folds y_0 .. y_n (2N entries, up to four levels a step), two correlation buffers
 // (N/2 each, at least 48), T (N), the signs (N char2), the group order and its inverse
 // (N/2 ints each) and the two-level W_N table: 153 KB at N = 4096.
@@ -32,7 +32,7 @@
 
 namespace ndft {
 
-constexpr int kFastThreads = 512;
+constexpr int kFastThreads = 1024;
 constexpr int kFastMinN = 8;
 constexpr int kFastMaxN = 4096;
 constexpr int kFastDirectL = 32; // correlation lengths summed directly
@@ -231,7 +231,7 @@ __device__ __forceinline__ FastStage fast_stage_of(int lq, int S, int st)
     return {1, lq};
 }
 
-// Global item g of a step over all lengths goes to thread g mod 512: a length's items
+// Global item g of a step over all lengths goes to thread g mod 1024: a length's items
 // o .. o + items - 1 are taken by the loop below without decoding the length per item.
 #define FAST_FOR_ITEMS(x, o, items)                                                                         \
     for (int x = (tid - (o)) & (kFastThreads - 1); x < (items); x += kFastThreads)
@@ -265,12 +265,13 @@ __device__ __forceinline__ void fast_multi_stage(const float2 *src, float2 *dst,
                 float2 a[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a[q] = sp[q << lqr];
-#pragma unroll
-                for (int q = 1; q < 4; ++q) {
-                    float2 w = table_twiddle(coarse, fine, (q * k) << lstep, tb);
-                    if (INV) w.y = -w.y;
-                    a[q] = cmulf(w, a[q]);
-                }
+                // W, W^2, W^3 from one table read and two products
+                float2 w = table_twiddle(coarse, fine, k << lstep, tb);
+                if (INV) w.y = -w.y;
+                const float2 w2 = cmulf(w, w);
+                a[1] = cmulf(w, a[1]);
+                a[2] = cmulf(w2, a[2]);
+                a[3] = cmulf(cmulf(w, w2), a[3]);
                 const float2 t0 = caddf(a[0], a[2]), t1 = csubf(a[0], a[2]);
                 const float2 t2 = caddf(a[1], a[3]);
                 float2 t3 = csubf(a[1], a[3]);
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
         G[i] = P.gtab[i];
         DL[i] = P.dlog[i];
     }
-    // a thread's samples k = tid + 512 e, e < EPT (n <= 4096): the row's inputs are loaded a
+    // a thread's samples k = tid + 1024 e, e < EPT (n <= 4096): the row's inputs are loaded a
     // row ahead into registers (FAST_LAG: the surveillance samples are the same every row)
     constexpr int EPT = kFastMaxN / kFastThreads;
     float2 pa[EPT], pb[EPT];

@@ -171,10 +171,12 @@ ndft_status ndft_caf12b(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
  * with d, p, the zero reference before the record, the layout and the limits of
  * ndft_caf. The lag product's component signs are exact (FP64 from the complex64
  * inputs); its value enters in FP32.
- * Only the sign-split plans compute it (the only candidates, for any Doppler window):
- * NDFT_BF16X2 / NDFT_FP8 with the twiddle half on the matrix cores, NDFT_FP32 with it as
- * an FFT of the exact lag signs. ndft_set_plan overrides apply when they name a
- * sign-split plan. Errors, workspace and stream as for ndft_caf.
+ * The sign-split plans compute it (for any Doppler window): NDFT_BF16X2 / NDFT_FP8 with
+ * the twiddle half on the matrix cores, NDFT_FP32 with it as an FFT of the exact lag
+ * signs; in NDFT_FP32 the fast exact transform ("fp32x_fast_exact") too, the built-in
+ * choice for n a power of two up to 4096 where the sign-split walk would be long (the
+ * largest base b with 64 b > n). ndft_set_plan overrides apply when they name one of
+ * these plans. Errors, workspace and stream as for ndft_caf.
  * ------------------------------------------------------------------------------- */
 size_t ndft_caf12c_workspace(int64_t n, int64_t tau0, int64_t n_tau, int64_t p0, int64_t n_dop,
                              ndft_prec prec);

@@ -176,8 +176,9 @@ def caf12b_workspace_bytes(n: int, tau0: int, n_tau: int, p0: int, n_dop: int, p
 def caf12c(s: torch.Tensor, r: torch.Tensor, tau0: int, n_tau: int, p0: int, n_dop: int,
            prec=BF16X2, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
     """Eq. (12c) surface A[n_tau, n_dop] (ordinary lag product, then the Eq. (6) operator
-    with the twiddle). Every precision runs a sign-split plan: BF16X2 and FP8 take the
-    twiddle half on the matrix cores, FP32 as an FFT of the exact lag signs."""
+    with the twiddle). BF16X2 and FP8 run a sign-split plan with the twiddle half on the
+    matrix cores; FP32 takes the twiddle half as an FFT of the exact lag signs, or the fast
+    exact transform for n a power of two up to 4096 and wide windows."""
     lib = _lib.load()
     _check_c64(s, "surv", 1)
     _check_c64(r, "ref", 1)

@@ -335,7 +335,8 @@ hipError_t g_attr_err = hipSuccess;
 void set_kernel_attributes()
 {
     for (const void *fn : {reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_X>),
-                           reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_LAG>)}) {
+                           reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_LAG>),
+                           reinterpret_cast<const void *>(&fast_ndft_kernel<FAST_LIN>)}) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            fast_lds_bytes(kFastMaxN, 2 * 64));
         if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
@@ -540,8 +541,12 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
         ko = g_ksplit_override[prec];
     }
     const std::vector<Plan> &ps = plans(prec);
+    // the fast exact transform takes either lag product; where it can, the sign-split plans
+    // keep the walk short for the Eq. (12c) surface too
+    bool fast_here = false;
+    for (const Plan &q : ps) fast_here = fast_here || (q.fastx && fast_ok(n));
     auto usable = [&](int k) {
-        if (ps[k].fastx) return !lin && fast_ok(n);
+        if (ps[k].fastx) return fast_ok(n);
         if (lin) return ps[k].lag_kfn_lin != nullptr;
         return ps[k].kfn[prod] != nullptr || (prod == PROD_LAG && ps[k].fft_d);
     };
@@ -558,7 +563,7 @@ Launch plan_launch(int prec, int prod, int64_t n, int64_t n_cols, int64_t p0, in
             // 8 (b C / 4 <= N) for the FP32 plan, whose FFT half costs the same for any
             // window (the Eq. (12c) surface has no other form: the walk is exact for any base)
             const int64_t runs_c = ps[k].fft_d ? kLsumChunk / 4 : kLsumChunk;
-            if (!lin && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * runs_c > n) continue;
+            if ((!lin || fast_here) && ps[k].lag_kfn && (int64_t)max_base(L.bm, L.n_bases) * runs_c > n) continue;
             // the FFT of the twiddle half wants a power-of-two factor of at least 64 in n
             if (!lin && ps[k].fft_d && n % 64 != 0) continue;
             const int r0 = ps[k].fastx ? 0 : zero_row(ps[k], prod, L.bm, L.n_bases);
@@ -1300,8 +1305,10 @@ ndft_status launch_fast(const Launch &L, int mode, const float2 *x, const float2
     ProfScope prof(s);
     if (mode == FAST_X)
         hipLaunchKernelGGL(fast_ndft_kernel<FAST_X>, dim3(grid), dim3(kFastThreads), (size_t)lds, s, P);
-    else
+    else if (mode == FAST_LAG)
         hipLaunchKernelGGL(fast_ndft_kernel<FAST_LAG>, dim3(grid), dim3(kFastThreads), (size_t)lds, s, P);
+    else
+        hipLaunchKernelGGL(fast_ndft_kernel<FAST_LIN>, dim3(grid), dim3(kFastThreads), (size_t)lds, s, P);
     prof.stop();
     return check_launch();
 }
@@ -1461,6 +1468,10 @@ ndft_status ndft_caf12c(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, in
     ndft_status st = ws_ok(ws, ws_bytes, L.ws_bytes);
     if (st != NDFT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (L.plan->fastx)
+        return launch_fast(L, FAST_LIN, nullptr, reinterpret_cast<const float2 *>(surv),
+                           reinterpret_cast<const float2 *>(ref), n, n_tau, tau0, p0, n_dop,
+                           reinterpret_cast<float2 *>(A), ws, s);
     float4 *part = reinterpret_cast<float4 *>(ws);
     st = launch_split(L, reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), n, n_tau,
                       tau0, part, ws, s);

@@ -43,12 +43,13 @@ constexpr int kFastDirectEntries = 288; // sum_{l <= 5} (lg - l + 1) 2^(l-1) <= 
 // sources of the rows
 constexpr int FAST_X = 0;   // rows of x (Eq. (7))
 constexpr int FAST_LAG = 1; // lag products of Eq. (6) at the delays tau0 + row (Eq. (12a))
+constexpr int FAST_LIN = 2; // ordinary lag products s conj(r) at those delays (Eq. (12c))
 
 struct FastParams {
     int n, lg;                 // N = 2^lg
     int rows;
     const float2 *x;           // FAST_X: rows of x, stride n
-    const float2 *s, *r;       // FAST_LAG: surveillance and reference records
+    const float2 *s, *r;       // FAST_LAG, FAST_LIN: surveillance and reference records
     int tau0;
     const int *gtab;           // the group order of the odd residues mod N: N / 2 entries
     const int *dlog;           // its inverse: index of odd u at (u - 1) / 2
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
             }
         }
     };
-    if constexpr (MODE == FAST_LAG) {
+    if constexpr (MODE != FAST_X) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int k = tid + e * kFastThreads;
@@ -373,12 +374,21 @@ __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
                 zi = pa[e].y;
                 sr = sgnf(pa[e].x);
                 si = sgnf(pa[e].y);
-            } else {
+            } else if constexpr (MODE == FAST_LAG) {
                 const Lag z = lag_product(pa[e], pb[e]);
                 zr = z.zr;
                 zi = z.zi;
                 sr = z.sr;
                 si = z.si;
+            } else {
+                // s conj(r) in FP64: the products of FP32 values are exact, one rounding of
+                // each sum keeps its sign (the FP32 value can underflow, the sign cannot)
+                const double sx = pa[e].x, sy = pa[e].y, rx = pb[e].x, ry = pb[e].y;
+                const double zr64 = fma(sx, rx, sy * ry), zi64 = fma(sy, rx, -(sx * ry));
+                zr = (float)zr64;
+                zi = (float)zi64;
+                sr = zr64 > 0.0 ? 1.0f : (zr64 < 0.0 ? -1.0f : 0.0f);
+                si = zi64 > 0.0 ? 1.0f : (zi64 < 0.0 ? -1.0f : 0.0f);
             }
             Y[k] = make_float2(zr, zi);
             sig[k] = make_char2((signed char)sr, (signed char)si);

@@ -1,5 +1,5 @@
 """The fast exact transform (plan fp32x_fast_exact, N a power of two from 8 to 4096) against
-the FP64 oracle: Eq. (7) rows (ndft_forward) and Eq. (12a) surfaces (ndft_caf), every bin
+the FP64 oracle: Eq. (7) rows (ndft_forward), Eq. (12a) and Eq. (12c) surfaces, every bin
 and bin windows, Gaussian and integer data with exact zeros, more rows than work-groups.
 
 The transform regroups the terms of Eq. (7) (folds over the power-of-two divisors of the
@@ -128,3 +128,35 @@ def test_caf_fast_zero_and_negation(nd, fast):
     An = nd.caf(dev(-s), dev(r), 0, 30, -100, 300, prec=0).cpu().numpy()
     # every step is odd in z (sums, products with fixed tables, FFTs): exactly -A
     np.testing.assert_array_equal(An, -A)
+
+
+@pytest.mark.parametrize("shape", [(64, 0, 64, 0, 64), (1024, 5, 60, -512, 1024), (4096, 100, 40, 0, 4096)])
+@pytest.mark.parametrize("kind", ["gauss", "int_zeros"])
+def test_caf12c_fast(nd, orc, fast, shape, kind):
+    # Eq. (12c): the ordinary lag product s conj(r) (FP64, exact signs), then the operator
+    # of Eq. (6) with the twiddles: the same transform on those rows
+    n, tau0, n_tau, p0, n_dop = shape
+    if kind == "gauss":
+        s, r = synth.random_pair(n, seed=n + 15, zeros=0.02)
+    else:
+        s, r = synth.random_pair(n, seed=n + 16, zeros=0.2, integer=True)
+    log("fast caf12c", shape, kind)
+    A = nd.caf12c(dev(s), dev(r), tau0, n_tau, p0, n_dop, prec=0).cpu().numpy()
+    Ao, sc = orc.caf12c(s, r, tau0, n_tau, p0, n_dop)
+    e = rel_err(A, Ao, sc)
+    log("max l1-relative error", e)
+    assert e <= TOL
+
+
+def test_caf12c_fast_is_built_in_for_wide_windows(nd):
+    # the Eq. (12c) surface takes the fast transform where the sign-split walk would be
+    # long: the built-in call equals the forced one bit for bit
+    s, r = synth.random_pair(4096, seed=77, zeros=0.02)
+    A = nd.caf12c(dev(s), dev(r), 0, 64, 0, 4096, prec=0).cpu().numpy()
+    names = [nd.plan_name(0, k) for k in range(nd.plan_count(0))]
+    nd.set_plan(0, names.index(NAME), 0)
+    try:
+        Af = nd.caf12c(dev(s), dev(r), 0, 64, 0, 4096, prec=0).cpu().numpy()
+    finally:
+        nd.set_plan(0, -1, 0)
+    np.testing.assert_array_equal(A, Af)

@@ -1507,8 +1507,8 @@ size_t ndft_nfft_workspace(int64_t batch, int64_t n)
 {
     if (n < 1 || n > kNfftMaxLong || (n & (n - 1)) != 0 || batch < 0) return 0;
     if (n <= kNfftMaxN || batch == 0) return 0;
-    // ping-pong rows for the top levels, then the twiddle table W_n^m, m < n / 2
-    return align256((size_t)batch * n * sizeof(float2)) + align256((size_t)(n / 2) * sizeof(float2));
+    // ping-pong rows for the top levels, then their twiddles, a table per level (n - 8192)
+    return align256((size_t)batch * n * sizeof(float2)) + align256((size_t)(n - kNfftMaxN) * sizeof(float2));
 }
 
 ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, int32_t reading, void *ws,
@@ -1567,7 +1567,7 @@ ndft_status ndft_nfft(const ndft_c64 *x, ndft_c64 *X, int64_t batch, int64_t n, 
                            L, rpb, sub, (long long)n);
     if ((st = check_launch()) != NDFT_OK) return st;
     if (lev > 0) {
-        hipLaunchKernelGGL(nfft_table_kernel, dim3((unsigned)cdiv(n / 2, 256)), dim3(256), 0, s, tw, (int)n);
+        hipLaunchKernelGGL(nfft_table_kernel, dim3((unsigned)cdiv(n - kNfftMaxN, 256)), dim3(256), 0, s, tw, (int)n);
         const unsigned cgrid = (unsigned)std::min<int64_t>(cdiv(batch * (n / 2), 256), 8LL * device_cu_count());
         const unsigned cgrid2 = (unsigned)std::min<int64_t>(cdiv(batch * (n / 4), 256), 8LL * device_cu_count());
         float2 *src = first;

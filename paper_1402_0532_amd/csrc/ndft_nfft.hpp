@@ -226,11 +226,18 @@ __global__ __launch_bounds__(kNfftThreads) void nfft_kernel(const float2 *__rest
     }
 }
 
-// W_n^m for m < n / 2 into a table (long rows).
+// The top levels' twiddles of long rows (n > 8192), one contiguous table per level: the level
+// whose halves have length h (8192 <= h <= n / 2) holds W_{2h}^k = W_n^{k n / (2h)}, k < h,
+// at h - 8192 + k (n - 8192 entries in all), so the lanes of a pass read consecutive entries.
+__device__ __forceinline__ int nfft_top_off(int h) { return h - kNfftMaxN; }
+
 __global__ __launch_bounds__(256) void nfft_table_kernel(float2 *tw, int n)
 {
-    const int m = blockIdx.x * 256 + threadIdx.x;
-    if (m < n / 2) tw[m] = nfft_twiddle(m, n);
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n - kNfftMaxN) return;
+    const int h = 1 << (31 - __builtin_clz(j + kNfftMaxN)); // the level: largest power of two <= j + 8192
+    const int k = j + kNfftMaxN - h;
+    tw[j] = nfft_twiddle((int)((long long)k * (n / (2 * h))), n);
 }
 
 // One top level of a long row (n samples per row): at stride S the transform of x[j::S]
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(256) void nfft_combine_kernel(const float2 *__restr
         const int j = b >> lh, k = b & (h - 1);
         const float2 *s = src + row * n;
         const float2 e = s[(long long)j * h + k];
-        const float2 t = nfft_odd<OUTER>(s[(long long)(j + S) * h + k], tw[(long long)k * S]);
+        const float2 t = nfft_odd<OUTER>(s[(long long)(j + S) * h + k], tw[nfft_top_off(h) + k]); // W_{2h}^k
         float2 *d = dst + row * n + (long long)j * 2 * h;
         d[k] = make_float2(e.x + t.x, e.y + t.y);
         d[k + h] = make_float2(e.x - t.x, e.y - t.y);
@@ -283,9 +290,9 @@ __global__ __launch_bounds__(256) void nfft_combine2_kernel(const float2 *__rest
         const float2 *s = src + row * n;
         const float2 a = s[(long long)j * h4 + k], bv = s[(long long)(j + 2 * S) * h4 + k];
         const float2 c = s[(long long)(j + S) * h4 + k], d = s[(long long)(j + 3 * S) * h4 + k];
-        const float2 w1 = tw[(long long)k * 2 * S];          // W_{2 h4}^k
-        const float2 w2a = tw[(long long)k * S];             // W_{4 h4}^k
-        const float2 w2b = tw[(long long)(k + h4) * S];      // W_{4 h4}^{k + h4}
+        const float2 w1 = tw[nfft_top_off(h4) + k];          // W_{2 h4}^k
+        const float2 w2a = tw[nfft_top_off(2 * h4) + k];     // W_{4 h4}^k
+        const float2 w2b = tw[nfft_top_off(2 * h4) + k + h4]; // W_{4 h4}^{k + h4}
         // level 2S: x[j::2S] at k and k + h4 (P), x[j + S::2S] likewise (Q)
         const float2 t1 = nfft_odd<OUTER>(bv, w1), t2 = nfft_odd<OUTER>(d, w1);
         const float2 pp = make_float2(a.x + t1.x, a.y + t1.y), pm = make_float2(a.x - t1.x, a.y - t1.y);

@@ -476,17 +476,19 @@ __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
             dst = tmp;
         }
         if (S == 0) __syncthreads(); // SV complete
-        // Chat[c][e1][om] = sum_e2 Fhat[e1 xor e2][om] Yhat[c][e2][-om]
-        for (int l = kFastFftL, o = 0; l <= lg; o += (lg - l + 1) << (l - 1), ++l) {
-            const int lh = l - 1, lq = l - 2, Q = 1 << lq;
+        // Chat[c][e1][om] = sum_e2 Fhat[e1 xor e2][om] Yhat[c][e2][-om], both e1 of an
+        // (c, om) from one read of its inputs
+        for (int l = kFastFftL, o = 0, oi = 0; l <= lg; o += (lg - l + 1) << (l - 1), oi += (lg - l + 1) << (l - 2), ++l) {
+            const int lq = l - 2, Q = 1 << lq;
             const float2 *F = P.spec + fast_spec_off(1 << l);
-            FAST_FOR_ITEMS(x, o, (lg - l + 1) << lh)
+            FAST_FOR_ITEMS(x, oi, (lg - l + 1) << lq)
             {
-                const int c = x >> lh, i = x & ((1 << lh) - 1), e1 = i >> lq, om = i & (Q - 1);
-                const int nom = (Q - om) & (Q - 1);
-                const float2 y0 = src[o + ((2 * c) << lq) + nom], y1 = src[o + ((2 * c + 1) << lq) + nom];
-                const float2 fa = F[(e1 << lq) + om], fb = F[((e1 ^ 1) << lq) + om];
-                dst[o + x] = caddf(cmulf(fa, y0), cmulf(fb, y1));
+                const int c = x >> lq, om = x & (Q - 1), nom = (Q - om) & (Q - 1);
+                const int b0 = o + ((2 * c) << lq), b1 = b0 + Q;
+                const float2 y0 = src[b0 + nom], y1 = src[b1 + nom];
+                const float2 f0 = F[om], f1 = F[Q + om];
+                dst[b0 + om] = caddf(cmulf(f0, y0), cmulf(f1, y1));
+                dst[b1 + om] = caddf(cmulf(f1, y0), cmulf(f0, y1));
             }
         }
         __syncthreads();

@@ -299,6 +299,17 @@ ndft_status ndft_dbg_split(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
                            int8_t *lag_sign, ndft_c64 *T, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
+ * Test hook: the lengths whose fast-exact-transform tables (group order of the odd
+ * residues, its inverse, the correlation spectra) the current device holds, as a bit mask
+ * (bit lg set: N = 2^lg cached). The library fills a length's slot on the first call of
+ * that length outside stream capture (that call waits for its stream once); under capture
+ * an uncached length makes its tables in the call's workspace. reset != 0 clears the
+ * mask after reading it, so the next call of each length fills its slot again (with the
+ * same values). Returns -1 when no device is current.
+ * ------------------------------------------------------------------------------- */
+int32_t ndft_dbg_fast_tables(int32_t reset);
+
+/* ---------------------------------------------------------------------------------
  * Tile plans (used by the autotuner). A plan is a tile shape of the contraction
  * kernel; ksplit is the number of sample chunks reduced in a fixed order (0 = pick
  * from the shape). Setting plan -1 restores the built-in choice. The setting is

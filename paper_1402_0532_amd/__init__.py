@@ -399,6 +399,15 @@ def dbg_split(s, r, tau0: int, n_tau: int, p0: int, n_dop: int, prec=BF16X2, lin
     return lg, tt
 
 
+def fast_tables_cached(reset: bool = False) -> int:
+    """Bit mask of the lengths (bit lg: N = 2^lg) whose fast-transform tables the current
+    device holds; reset clears it after reading."""
+    m = int(_lib.load().ndft_dbg_fast_tables(1 if reset else 0))
+    if m < 0:
+        raise RuntimeError("ndft_dbg_fast_tables: no current device")
+    return m
+
+
 def plan_count(prec=FP32) -> int:
     return int(_lib.load().ndft_plan_count(_prec(prec)))
 

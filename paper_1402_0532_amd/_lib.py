@@ -39,6 +39,7 @@ SIGNATURES = {
     "ndft_caf_backward": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P, _SZ, _P]),
     "ndft_dbg_signs": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _P, _P, _P]),
     "ndft_dbg_split": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _I64, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ndft_dbg_fast_tables": (_I32, [_I32]),
     "ndft_plan_count": (_I32, [_I32]),
     "ndft_plan_name": (ctypes.c_char_p, [_I32, _I32]),
     "ndft_set_plan": (_ST, [_I32, _I32, _I32]),

@@ -1243,6 +1243,85 @@ void *scratch_on(int dev)
     return ptr;
 }
 
+// ------------------------------------------------------------------------------------
+// tables of the fast exact transform, kept per device and length
+// ------------------------------------------------------------------------------------
+// The tables (group order, its inverse, the correlation spectra) depend on the length
+// alone. Each device holds one slot per length 2^lg (lg = 3 .. 12) in a file-scope array,
+// filled by the first call of that length outside stream capture, which waits for its
+// stream so that the slot is complete before any stream reads it; slots are never written
+// again. Under capture, a length not yet cached makes its tables in the call's workspace.
+constexpr size_t align256c(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t fast_slot_bytes(int lg)
+{
+    return 2 * align256c(((size_t)1 << lg) / 2 * sizeof(int)) +
+           align256c((size_t)std::max(1, fast_spec_entries(1 << lg)) * sizeof(float2));
+}
+constexpr size_t fast_slot_off(int lg)
+{
+    size_t o = 0;
+    for (int l = 3; l < lg; ++l) o += fast_slot_bytes(l);
+    return o;
+}
+constexpr size_t kFastCacheBytes = fast_slot_off(kFastLgMax + 1);
+static_assert((1 << 3) == kFastMinN, "the first slot is the shortest length");
+static __device__ __align__(256) char fast_cache[kFastCacheBytes];
+
+std::mutex g_fast_mu;
+void *g_fast_cache_ptr[kMaxDevices] = {};
+std::atomic<unsigned> g_fast_valid[kMaxDevices];
+
+void fast_tables_launch(char *base, int n, int lg, hipStream_t s)
+{
+    int *gtab = reinterpret_cast<int *>(base);
+    int *dlog = reinterpret_cast<int *>(base + align256((size_t)(n / 2) * sizeof(int)));
+    float2 *spec = reinterpret_cast<float2 *>(base + 2 * align256((size_t)(n / 2) * sizeof(int)));
+    const int nspec = lg >= 6 ? 2 * (lg - 5) : 0;
+    hipLaunchKernelGGL(fast_tables_kernel, dim3((unsigned)(nspec + 1)), dim3(kFastTabThreads), 0, s, n, lg, gtab,
+                       dlog, spec);
+}
+
+// the device's cached tables of length 2^lg (nullptr: not available, the call makes its own)
+char *fast_cached_tables(int lg, hipStream_t s)
+{
+    int dev = -1;
+    if (s ? hipStreamGetDevice(s, &dev) != hipSuccess : hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices || lg < 3 || lg > kFastLgMax) return nullptr;
+    const unsigned bit = 1u << lg;
+    if ((g_fast_valid[dev].load(std::memory_order_acquire) & bit) && g_fast_cache_ptr[dev])
+        return static_cast<char *>(g_fast_cache_ptr[dev]) + fast_slot_off(lg);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (cs != hipStreamCaptureStatusNone) return nullptr;
+    std::lock_guard<std::mutex> lk(g_fast_mu);
+    if (!g_fast_cache_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(fast_cache));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_fast_cache_ptr[dev] = ptr;
+    }
+    char *base = static_cast<char *>(g_fast_cache_ptr[dev]) + fast_slot_off(lg);
+    if (!(g_fast_valid[dev].load(std::memory_order_acquire) & bit)) {
+        fast_tables_launch(base, 1 << lg, lg, s);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return nullptr;
+        g_fast_valid[dev].fetch_or(bit, std::memory_order_release);
+    }
+    return base;
+}
+
 } // namespace
 
 // ======================================================================================
@@ -1275,13 +1354,16 @@ ndft_status launch_fast(const Launch &L, int mode, const float2 *x, const float2
     if (g_attr_err != hipSuccess) return NDFT_E_HIP;
     int lg = 0;
     while ((1LL << lg) < n) ++lg;
-    int *gtab = static_cast<int *>(ws);
-    int *dlog = reinterpret_cast<int *>(static_cast<char *>(ws) + align256((size_t)(n / 2) * sizeof(int)));
-    float2 *spec = reinterpret_cast<float2 *>(static_cast<char *>(ws) + 2 * align256((size_t)(n / 2) * sizeof(int)));
-    const int nspec = lg >= 6 ? 2 * (lg - 5) : 0;
-    hipLaunchKernelGGL(fast_tables_kernel, dim3((unsigned)(nspec + 1)), dim3(256), 0, s, (int)n, lg, gtab, dlog, spec);
-    ndft_status st = check_launch();
-    if (st != NDFT_OK) return st;
+    char *base = fast_cached_tables(lg, s);
+    if (!base) { // capture of a length not yet cached: the call's own tables in its workspace
+        base = static_cast<char *>(ws);
+        fast_tables_launch(base, (int)n, lg, s);
+        const ndft_status st = check_launch();
+        if (st != NDFT_OK) return st;
+    }
+    int *gtab = reinterpret_cast<int *>(base);
+    int *dlog = reinterpret_cast<int *>(base + align256((size_t)(n / 2) * sizeof(int)));
+    float2 *spec = reinterpret_cast<float2 *>(base + 2 * align256((size_t)(n / 2) * sizeof(int)));
     FastParams P;
     std::memset(&P, 0, sizeof(P));
     P.n = (int)n;
@@ -1611,6 +1693,19 @@ ndft_status ndft_dbg_signs(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n,
                        reinterpret_cast<const float2 *>(surv), reinterpret_cast<const float2 *>(ref), (int)n,
                        (int)tau0, (int)mod_n(p0, n), ntw, nlag, tw_sign, lag_sign);
     return check_launch();
+}
+
+int32_t ndft_dbg_fast_tables(int32_t reset)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    std::lock_guard<std::mutex> lk(g_fast_mu);
+    const unsigned m = g_fast_valid[dev].load(std::memory_order_acquire);
+    if (reset) g_fast_valid[dev].store(0, std::memory_order_release);
+    return (int32_t)m;
 }
 
 ndft_status ndft_dbg_split(const ndft_c64 *surv, const ndft_c64 *ref, int64_t n, int64_t tau0, int64_t n_tau,

@@ -87,14 +87,18 @@ __device__ __forceinline__ int pow5_signed(int e, int a, int L)
 // Tables of one call. Blocks 0 .. nspec - 1: the DFT (length Q = L/4, FP64 radix-2) of
 // phi_L in group order for the sign e, one block per (L, e), L = 2 kFastDirectL .. N; the
 // last block: the group order of the odd residues mod N and its inverse.
-__global__ __launch_bounds__(256) void fast_tables_kernel(int n, int lg, int *gtab, int *dlog, float2 *spec)
+constexpr int kFastTabThreads = 512;
+
+__global__ __launch_bounds__(kFastTabThreads) void fast_tables_kernel(int n, int lg, int *gtab, int *dlog,
+                                                                      float2 *spec)
 {
     __shared__ double2 buf[2][kFastMaxN / 4];
+    __shared__ double2 wq[kFastMaxN / 8]; // W_Q^m = (cos, sin) of -2 pi m / Q, m < Q / 2
     const int tid = threadIdx.x;
     const int nspec = lg >= 6 ? 2 * (lg - 5) : 0; // L = 64 .. n
     if ((int)blockIdx.x >= nspec) {
         const int qn = n / 4;
-        for (int i = tid; i < n / 2; i += 256) {
+        for (int i = tid; i < n / 2; i += kFastTabThreads) {
             const int g = pow5_signed(i / qn, i % qn, n);
             gtab[i] = g;
             dlog[(g - 1) >> 1] = i;
@@ -103,17 +107,22 @@ __global__ __launch_bounds__(256) void fast_tables_kernel(int n, int lg, int *gt
     }
     const int l = 6 + (int)blockIdx.x / 2, e = (int)blockIdx.x & 1;
     const int L = 1 << l, Q = L / 4;
-    for (int a = tid; a < Q; a += 256) {
+    for (int a = tid; a < Q; a += kFastTabThreads) {
         const TwSign sg = twiddle_sign(pow5_signed(e, a, L), L);
         buf[0][a] = make_double2((double)sg.c, (double)sg.t);
     }
+    for (int m = tid; m < Q / 2; m += kFastTabThreads) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)Q, &sn, &cs);
+        wq[m] = make_double2(cs, sn);
+    }
     __syncthreads();
     int src = 0;
-    for (int h = 1; h < Q; h <<= 1) {
-        for (int j = tid; j < Q / 2; j += 256) {
+    for (int h = 1, ls = l - 3; h < Q; h <<= 1, --ls) {
+        for (int j = tid; j < Q / 2; j += kFastTabThreads) {
             const int k = j & (h - 1);
-            double sn, cs;
-            sincospi(-(double)k / (double)h, &sn, &cs); // W_{2h}^k
+            const double2 w = wq[k << ls]; // W_{2h}^k = W_Q^{k Q / (2h)}
+            const double cs = w.x, sn = w.y;
             const double2 a = buf[src][j], b = buf[src][j + Q / 2];
             const double2 wb = make_double2(cs * b.x - sn * b.y, cs * b.y + sn * b.x);
             buf[src ^ 1][2 * j - k] = make_double2(a.x + wb.x, a.y + wb.y);
@@ -123,7 +132,7 @@ __global__ __launch_bounds__(256) void fast_tables_kernel(int n, int lg, int *gt
         src ^= 1;
     }
     float2 *dst = spec + fast_spec_off(L) + e * Q;
-    for (int w = tid; w < Q; w += 256) dst[w] = make_float2((float)buf[src][w].x, (float)buf[src][w].y);
+    for (int w = tid; w < Q; w += kFastTabThreads) dst[w] = make_float2((float)buf[src][w].x, (float)buf[src][w].y);
 }
 
 // Stockham stages over nseq sequences of length Q = 2^lq in LDS, src -> dst: radix 4 while

@@ -160,3 +160,20 @@ def test_caf12c_fast_is_built_in_for_wide_windows(nd):
     finally:
         nd.set_plan(0, -1, 0)
     np.testing.assert_array_equal(A, Af)
+
+
+def test_fast_tables_cache(nd, orc, fast):
+    # the first call of a length fills the device's slot and reads it, later calls read
+    # it; clearing and filling again gives the same bits (the capture of an uncached
+    # length, which makes the tables in the workspace, is checked with the graph replays)
+    x = rows(2048, 5, 91)
+    nd.fast_tables_cached(reset=True)
+    X1 = nd.forward(dev(x), prec=0).cpu().numpy()
+    assert nd.fast_tables_cached() >> 11 & 1
+    X2 = nd.forward(dev(x), prec=0).cpu().numpy()
+    np.testing.assert_array_equal(X1, X2)
+    nd.fast_tables_cached(reset=True)
+    X3 = nd.forward(dev(x), prec=0).cpu().numpy()
+    np.testing.assert_array_equal(X1, X3)
+    Xo, sc = orc.ndft(x.astype(np.complex128))
+    assert rel_err(X1, Xo, sc) <= TOL

@@ -267,20 +267,22 @@ def test_invalid_arguments_raise(nd):
         nd.caf(s.real.contiguous(), s, 0, 4, 0, 4)
 
 
-@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft", "nfft_long", "fast"])
+@pytest.mark.parametrize("which", ["fp32_fft_half", "caf12b", "caf12c_fp32", "nfft", "nfft_long", "fast",
+                                   "fast_uncached"])
 def test_fft_paths_graph_replay(nd, which):
     """The FFT-based paths (the FP32 sign-split surfaces of Eq. (12a) and (12c):
     twiddle-sign kernel, reduction, then the FFT of the exact lag signs added on top; the
     Eq. (12b) surface: FFT kernel and the reduction of its partial surfaces; the NFFT; the
-    fast exact transform: its tables kernel, then the row kernel) captured into a graph:
-    every replay, with unrelated eager work and a scrambled workspace between, equals the
-    eager call."""
+    fast exact transform: the row kernel on the device's cached tables, or, for a length
+    not cached when the capture starts, the tables kernel into the workspace first)
+    captured into a graph: every replay, with unrelated eager work and a scrambled
+    workspace between, equals the eager call."""
     n, tau0, n_tau, p0, n_dop = 16384, 3, 100, -64, 128
-    if which == "fast":
+    if which.startswith("fast"):
         n, tau0, n_tau, p0, n_dop = 4096, 3, 300, -2048, 4096
     s, r = synth.random_pair(n, seed=22, zeros=0.02)
     S, R = dev(s), dev(r)
-    if which == "fast":
+    if which.startswith("fast"):
         plan, _ = nd.get_plan(0, n, n_tau, p0, n_dop)
         assert nd.plan_name(0, plan) == "fp32x_fast_exact"
         nbytes = nd.caf_workspace_bytes(n, tau0, n_tau, p0, n_dop, 0)
@@ -328,8 +330,12 @@ def test_fft_paths_graph_replay(nd, which):
         call(out, ws)  # warm-up on the capture stream
     torch.cuda.current_stream().wait_stream(stream)
     torch.cuda.synchronize()
+    if which.startswith("fast"):
+        assert nd.fast_tables_cached(reset=which == "fast_uncached") >> 12 & 1  # the eager calls filled it
     with torch.cuda.graph(g, stream=stream):
         call(out, ws)
+    if which == "fast_uncached":
+        assert not nd.fast_tables_cached() >> 12 & 1  # nothing filled under capture
     for rep in range(3):
         out.fill_(1.0)
         ws.fill_(255)

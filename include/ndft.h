@@ -57,7 +57,11 @@ typedef enum {
  *               two from 8 to 4096 and wide bin windows the built-in choice is the fast
  *               exact transform (plan "fp32x_fast_exact": every bin of a row from FFTs
  *               and cyclic correlations over the odd residues mod n, the same terms as
- *               Eq. (7) regrouped, FP32 arithmetic).
+ *               Eq. (7) regrouped, FP32 arithmetic). Its tables depend on n alone and
+ *               are kept per device and length in a library-held array (98 KB, no
+ *               allocation): the first call of a length outside stream capture fills
+ *               them and waits for its stream once; under capture an uncached length
+ *               makes them in the call's workspace.
  *   NDFT_BF16X2 data split into BF16 hi + lo (|v - hi - lo| <= 2^-18 |v|), exact BF16
  *               signs, FP32 accumulation.
  *   NDFT_FP8    data split into four e4m3 terms (v = t0 + t1/16 + t2/256 + t3/4096 up to

@@ -251,7 +251,9 @@ __device__ __forceinline__ void fast_multi_stage(const float2 *src, float2 *dst,
                                                  const float2 *coarse, const float2 *fine, int tb, int tid)
 {
     int o = 0, off = 0;
-    for (int l = kFastFftL; l <= lg; ++l) {
+#pragma unroll
+    for (int l = kFastFftL; l <= kFastLgMax; ++l) { // unrolled: l is a constant in each copy
+        if (l > lg) break;
         const FastStage f = fast_stage_of(l - 2, S, st);
         const int lr = f.r == 4 ? 2 : (f.r == 2 ? 1 : 0), lq = l - 2;
         const int items = (2 * (lg - l + 1)) << (lq - lr);

@@ -35,13 +35,9 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "fp8": 5000.0}  # dense MFMA pea
 # 157.3 TFLOP/s counts packed FMAs).
 VALU_LANE_TOPS = 39.3216
 VALU_FP32_TFLOPS = 2.0 * VALU_LANE_TOPS
-KERNEL_SOURCES = ["paper_1402_0532_amd/csrc/ndft_api.hip",
-                  "paper_1402_0532_amd/csrc/ndft_dft512.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_contract.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_device.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_dft12b.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_surface_bf16.hpp",
-                  "paper_1402_0532_amd/csrc/ndft_signsplit.hpp"]
+# every source of the library: a recorded figure is tied to the exact build it came from
+KERNEL_SOURCES = sorted("paper_1402_0532_amd/csrc/" + f for f in os.listdir(os.path.join(ROOT, "paper_1402_0532_amd", "csrc"))
+                        if f.endswith((".hip", ".hpp")))
 TRAFFIC_FILE = "profiles/contract_traffic_caf_n65536.txt"
 SPLIT_PLAN_PREFIXES = ("bf16x2s_", "bf16x2g_", "fp8s_", "fp32s_")
 

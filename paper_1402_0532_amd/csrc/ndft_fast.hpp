@@ -246,55 +246,142 @@ __device__ __forceinline__ FastStage fast_stage_of(int lq, int S, int st)
 #define FAST_FOR_ITEMS(x, o, items)                                                                         \
     for (int x = (tid - (o)) & (kFastThreads - 1); x < (items); x += kFastThreads)
 
+// A stage's work on one length comes in items of four entries (one radix-4 butterfly, two
+// radix-2 butterflies of neighbouring j, or four copied entries), 64 items to a chunk, the
+// lengths' chunks one after another; chunk c goes to wave c mod 16, so a wave's parameters
+// are uniform and its lanes busy (at N = 4096: 32 chunks, two a wave).
+struct FastChunk {
+    int kind;  // 1: copy, 2: two radix-2 butterflies, 4: one radix-4 butterfly
+    int off;   // the length's first entry in the buffers
+    int lq;    // log2 Q (sequence length)
+    int lqr;   // log2 (Q / radix)
+    int lh;    // log2 of the sub-length h
+    int lstep; // twiddle W_{radix h}^m = W_N^{m 2^lstep}
+};
+
+// One lane's item: its four inputs and the raw table entries of its twiddles.
+struct FastItem {
+    float2 a[4];
+    float2 wc[2], wf[2];
+};
+
+__device__ __forceinline__ void fast_item_load(const FastChunk &f, const float2 *src, const float2 *coarse,
+                                               const float2 *fine, int tb, int x, FastItem &it)
+{
+    const int fm = (1 << tb) - 1;
+    if (f.kind == 4) {
+        const int j = x & ((1 << f.lqr) - 1), k = j & ((1 << f.lh) - 1);
+        const float2 *sp = src + f.off + ((x >> f.lqr) << f.lq) + j;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) it.a[q] = sp[q << f.lqr];
+        const int v = k << f.lstep;
+        it.wc[0] = coarse[v >> tb];
+        it.wf[0] = fine[v & fm];
+    } else if (f.kind == 2) {
+        // sub-items 2x and 2x + 1: the same sequence, j and j + 1 (j even)
+        const int x2 = 2 * x, j = x2 & ((1 << f.lqr) - 1), k = j & ((1 << f.lh) - 1);
+        const float2 *sp = src + f.off + ((x2 >> f.lqr) << f.lq) + j;
+        const float4 u0 = *reinterpret_cast<const float4 *>(sp);
+        const float4 u1 = *reinterpret_cast<const float4 *>(sp + (1 << f.lqr));
+        it.a[0] = make_float2(u0.x, u0.y);
+        it.a[2] = make_float2(u0.z, u0.w);
+        it.a[1] = make_float2(u1.x, u1.y);
+        it.a[3] = make_float2(u1.z, u1.w);
+        const int v0 = k << f.lstep, v1 = f.lh ? (k + 1) << f.lstep : 0;
+        it.wc[0] = coarse[v0 >> tb];
+        it.wf[0] = fine[v0 & fm];
+        it.wc[1] = coarse[v1 >> tb];
+        it.wf[1] = fine[v1 & fm];
+    } else {
+        const float4 *sp = reinterpret_cast<const float4 *>(src + f.off + 4 * x);
+        const float4 u0 = sp[0], u1 = sp[1];
+        it.a[0] = make_float2(u0.x, u0.y);
+        it.a[1] = make_float2(u0.z, u0.w);
+        it.a[2] = make_float2(u1.x, u1.y);
+        it.a[3] = make_float2(u1.z, u1.w);
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void fast_item_store(const FastChunk &f, float2 *dst, int x, FastItem &it)
+{
+    const int h = 1 << f.lh;
+    if (f.kind == 4) {
+        const int j = x & ((1 << f.lqr) - 1), k = j & (h - 1);
+        float2 *dp = dst + f.off + ((x >> f.lqr) << f.lq) + ((j - k) << 2) + k;
+        float2 *a = it.a;
+        // W, W^2, W^3 from one table read and two products
+        float2 w = cmulf(it.wc[0], it.wf[0]);
+        if (INV) w.y = -w.y;
+        const float2 w2 = cmulf(w, w);
+        a[1] = cmulf(w, a[1]);
+        a[2] = cmulf(w2, a[2]);
+        a[3] = cmulf(cmulf(w, w2), a[3]);
+        const float2 t0 = caddf(a[0], a[2]), t1 = csubf(a[0], a[2]);
+        const float2 t2 = caddf(a[1], a[3]);
+        float2 t3 = csubf(a[1], a[3]);
+        t3 = INV ? make_float2(-t3.y, t3.x) : make_float2(t3.y, -t3.x); // times -+j
+        const float2 y0 = caddf(t0, t2), y1 = caddf(t1, t3), y2 = csubf(t0, t2), y3 = csubf(t1, t3);
+        if (h == 1) { // dp = 4 j: four neighbouring entries
+            float4 *d4 = reinterpret_cast<float4 *>(dp);
+            d4[0] = make_float4(y0.x, y0.y, y1.x, y1.y);
+            d4[1] = make_float4(y2.x, y2.y, y3.x, y3.y);
+        } else {
+            dp[0] = y0;
+            dp[h] = y1;
+            dp[2 * h] = y2;
+            dp[3 * h] = y3;
+        }
+    } else if (f.kind == 2) {
+        const int x2 = 2 * x, j = x2 & ((1 << f.lqr) - 1), k = j & (h - 1);
+        float2 *dp = dst + f.off + ((x2 >> f.lqr) << f.lq) + ((j - k) << 1) + k;
+        float2 w0 = cmulf(it.wc[0], it.wf[0]), w1 = cmulf(it.wc[1], it.wf[1]);
+        if (INV) {
+            w0.y = -w0.y;
+            w1.y = -w1.y;
+        }
+        const float2 b0 = cmulf(w0, it.a[1]), b1 = cmulf(w1, it.a[3]);
+        const float2 s0 = caddf(it.a[0], b0), d0 = csubf(it.a[0], b0);
+        const float2 s1 = caddf(it.a[2], b1), d1 = csubf(it.a[2], b1);
+        float4 *d4 = reinterpret_cast<float4 *>(dp);
+        if (h == 1) { // j -> 2 j, 2 j + 1; j + 1 -> 2 j + 2, 2 j + 3
+            d4[0] = make_float4(s0.x, s0.y, d0.x, d0.y);
+            d4[1] = make_float4(s1.x, s1.y, d1.x, d1.y);
+        } else { // k + 1 < h: j + 1 lands next to j in both halves
+            d4[0] = make_float4(s0.x, s0.y, s1.x, s1.y);
+            *reinterpret_cast<float4 *>(dp + h) = make_float4(d0.x, d0.y, d1.x, d1.y);
+        }
+    } else {
+        float4 *dp = reinterpret_cast<float4 *>(dst + f.off + 4 * x);
+        dp[0] = make_float4(it.a[0].x, it.a[0].y, it.a[1].x, it.a[1].y);
+        dp[1] = make_float4(it.a[2].x, it.a[2].y, it.a[3].x, it.a[3].y);
+    }
+}
+
 template <bool INV>
 __device__ __forceinline__ void fast_multi_stage(const float2 *src, float2 *dst, int lg, int S, int st,
                                                  const float2 *coarse, const float2 *fine, int tb, int tid)
 {
-    int o = 0, off = 0;
+    constexpr int NW = kFastThreads / 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    int cb = 0, off = 0;
 #pragma unroll
     for (int l = kFastFftL; l <= kFastLgMax; ++l) { // unrolled: l is a constant in each copy
         if (l > lg) break;
-        const FastStage f = fast_stage_of(l - 2, S, st);
-        const int lr = f.r == 4 ? 2 : (f.r == 2 ? 1 : 0), lq = l - 2;
-        const int items = (2 * (lg - l + 1)) << (lq - lr);
-        const int lqr = lq - lr, h = 1 << f.lh, lstep = lg - f.lh - lr;
-        FAST_FOR_ITEMS(x, o, items)
-        {
-            if (f.r == 1) { // copy
-                dst[off + x] = src[off + x];
-                continue;
-            }
-            const int sq = x >> lqr, j = x & ((1 << lqr) - 1), k = j & (h - 1);
-            const float2 *sp = src + off + (sq << lq) + j;
-            float2 *dp = dst + off + (sq << lq) + ((j - k) << lr) + k;
-            if (f.r == 2) {
-                float2 w = table_twiddle(coarse, fine, k << lstep, tb);
-                if (INV) w.y = -w.y;
-                const float2 a0 = sp[0], a1 = cmulf(w, sp[1 << lqr]);
-                dp[0] = caddf(a0, a1);
-                dp[h] = csubf(a0, a1);
-            } else {
-                float2 a[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = sp[q << lqr];
-                // W, W^2, W^3 from one table read and two products
-                float2 w = table_twiddle(coarse, fine, k << lstep, tb);
-                if (INV) w.y = -w.y;
-                const float2 w2 = cmulf(w, w);
-                a[1] = cmulf(w, a[1]);
-                a[2] = cmulf(w2, a[2]);
-                a[3] = cmulf(cmulf(w, w2), a[3]);
-                const float2 t0 = caddf(a[0], a[2]), t1 = csubf(a[0], a[2]);
-                const float2 t2 = caddf(a[1], a[3]);
-                float2 t3 = csubf(a[1], a[3]);
-                t3 = INV ? make_float2(-t3.y, t3.x) : make_float2(t3.y, -t3.x); // times -+j
-                dp[0] = caddf(t0, t2);
-                dp[h] = caddf(t1, t3);
-                dp[2 * h] = csubf(t0, t2);
-                dp[3 * h] = csubf(t1, t3);
+        const int lq = l - 2, items = (lg - l + 1) << (l - 3), nc = (items + 63) >> 6;
+        const FastStage s = fast_stage_of(lq, S, st);
+        const int lr = s.r == 4 ? 2 : 1;
+        const FastChunk f{s.r, off, lq, lq - lr, s.lh, lg - s.lh - lr};
+        // this wave's chunks of the length: c = wave mod NW, cb <= c < cb + nc
+        for (int c = cb + ((wave - cb) & (NW - 1)); c < cb + nc; c += NW) {
+            const int x = ((c - cb) << 6) + lane;
+            if (x < items) {
+                FastItem it;
+                fast_item_load(f, src, coarse, fine, tb, x, it);
+                fast_item_store<INV>(f, dst, x, it);
             }
         }
-        o += items;
+        cb += nc;
         off += (lg - l + 1) << (l - 1);
     }
 }
@@ -302,7 +389,8 @@ __device__ __forceinline__ void fast_multi_stage(const float2 *src, float2 *dst,
 template <int MODE>
 __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
 {
-    extern __shared__ float2 fsm[];
+    extern __shared__ float4 fsm4[]; // 16-byte aligned: the stages move entry pairs
+    float2 *fsm = reinterpret_cast<float2 *>(fsm4);
     const int n = P.n, lg = P.lg, tid = threadIdx.x;
     // two regions of 2n entries: R1 holds the folds, then serves as an FFT buffer, then T;
     // R2 holds the gathered correlation inputs, then the other FFT buffer, then the FFT of

@@ -517,33 +517,46 @@ __global__ __launch_bounds__(kFastThreads) void fast_ndft_kernel(FastParams P)
         // group order, [l][c][e][a] into R2 ----
         for (int v = tid; v <= lg; v += kFastThreads) YS[v] = Y[yoff(v)];
         {
-            const int tot = soff(lsmall + 1);
-            for (int t = tid; t < tot; t += kFastThreads) {
-                int l = 1, o = 0;
-                while (t >= o + ((lg - l + 1) << (l - 1))) {
-                    o += (lg - l + 1) << (l - 1);
-                    ++l;
-                }
+            // the widest first: a length-32 sum is split over 4 neighbouring lanes and a
+            // length-16 sum over 2 (4 terms a lane, their reads issued together), the partial
+            // sums added across the lanes; 730 lanes at N = 4096
+            int ou = 0;
+#pragma unroll
+            for (int l = kFastFftL - 1; l >= 1; --l) {
+                if (l > lsmall) continue;
                 const int L = 1 << l, half = L >> 1;
-                const int c = (t - o) >> (l - 1), i1 = (t - o) & (half - 1), w = lg - l - c;
-                const int g1 = gl(i1, l);
-                const float2 *y = Y + yoff(c);
-                float2 acc = make_float2(0.0f, 0.0f);
-                // t over the group order: 5^a, then L - 5^a (a < L / 4; {1} for L = 2)
-                const int q = l == 1 ? 1 : half >> 1;
-                for (int e2 = 0; e2 < (l == 1 ? 1 : 2); ++e2) {
-                    int pw = 1;
-                    for (int a = 0; a < q; ++a) {
-                        const int g2 = e2 ? (L - pw) & (L - 1) : pw;
-                        pw = (pw * 5) & (L - 1);
+                const int lp = l >= 4 ? l - 3 : 0; // log2 of the lanes per sum
+                const int T = half >> lp;         // terms a lane
+                const int items = (lg - l + 1) << (l - 1), so = soff(l), o = ou;
+                ou += items << lp;
+                FAST_FOR_ITEMS(u, o, items << lp)
+                {
+                    const int it = u >> lp, part = u & ((1 << lp) - 1);
+                    const int c = it >> (l - 1), i1 = it & (half - 1), w = lg - l - c;
+                    const int g1 = gl(i1, l);
+                    const float2 *y = Y + yoff(c);
+                    float2 acc = make_float2(0.0f, 0.0f);
+                    // this lane's terms: group-order indices part T .. part T + T - 1 (5^a, then
+                    // L - 5^a, a < L / 4; {1} for L = 2)
+#pragma unroll
+                    for (int k = 0; k < (l >= 3 ? 4 : (l == 2 ? 2 : 1)); ++k) {
+                        const int g2 = gl(part * T + k, l);
                         const TwSign ph = twiddle_sign((g1 * g2) & (L - 1), L);
                         const float2 yv = y[g2 << w];
                         // (ph.c + j ph.t) yv
                         acc.x += (float)ph.c * yv.x - (float)ph.t * yv.y;
                         acc.y += (float)ph.c * yv.y + (float)ph.t * yv.x;
                     }
+                    if (lp >= 1) {
+                        acc.x += __shfl_xor(acc.x, 1);
+                        acc.y += __shfl_xor(acc.y, 1);
+                    }
+                    if (lp >= 2) {
+                        acc.x += __shfl_xor(acc.x, 2);
+                        acc.y += __shfl_xor(acc.y, 2);
+                    }
+                    if (part == 0) SD[so + it] = acc;
                 }
-                SD[t] = acc;
             }
         }
         for (int l = kFastFftL, o = 0; l <= lg; o += (lg - l + 1) << (l - 1), ++l) {

@@ -256,3 +256,12 @@ def test_unsupported_shape_rejected_before_any_launch():
                 assert st == (WORKSPACE if need > 0 else UNSUPPORTED), (n, prec, n_dop, need, st)
                 seen.add(st)
     assert UNSUPPORTED in seen  # some plan's table does not fit at these lengths
+
+
+def test_fast_tables_hook_without_a_device():
+    # with no device current the hook reports -1 instead of a mask (and touches nothing)
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    assert _lib.load().ndft_dbg_fast_tables(0) == -1
+    assert _lib.load().ndft_dbg_fast_tables(1) == -1
